@@ -1,0 +1,171 @@
+"""Throughput of plain parallel tempering on one MI355X.
+
+Workload (the large plain-PT configuration): N = 256 modes, 8 disorder
+samples (random frequencies, frequency-matched terms, Gaussian couplings of
+variance N/c), 40 temperatures geometric in [0.25, 1.5], 2 replicas (640
+copies), FP32 fields and energy changes, FP64 energy recomputation every 100
+sweeps, a swap round and a measurement after every sweep.  A step is one
+sweep of every copy (N/2 two-mode updates each) followed by its swap round,
+measurement and, every 100 steps, the recomputation.  Inputs are synthetic
+and already resident in HBM when timing starts.
+
+Prints one JSON line.  ``value`` = mode-updates/s (N mode-updates per copy
+per sweep) over the timed steps.  ``roofline`` describes the sweep kernel:
+algorithmic bytes per launch (8 B per list entry streamed: packed indices +
+FP32 coupling) over its mean duration measured with HIP events on the
+context's stream.  ``cpu_baseline`` times the CPU FP64 oracle on a bounded
+slice of the same workload (sample 0, all 80 copies, whole sweeps for ~10 s).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SEED_BASE = 2511135080 + 400  # disorder seed of sample mu: SEED_BASE + mu
+HBM_PEAK_GBS = 8000.0
+METRIC = "mode-updates/s + τ_int-corrected sweeps/s (learned vs plain PT), N=256, 1 GPU"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_n256_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2511_13508_amd", "csrc", "kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for_current_kernel(launch_bytes_alg: float):
+    """HBM bytes per sweep launch from committed rocprofv3 counters, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(N, temps, n_reps, budget_s, n_threads):
+    from oracle import oracle as O
+    og = O.Graph(N, SEED_BASE + 0)
+    pt = O.PT(og, temps, n_reps=n_reps, run_seed=1, sample=0, swap_interval=1, resync_interval=100,
+              measure_start=0, measure_interval=1, n_bins=100, n_threads=n_threads)
+    t0 = time.perf_counter()
+    sweeps = 0
+    while time.perf_counter() - t0 < budget_s:
+        pt.run(1)
+        sweeps += 1
+    el = time.perf_counter() - t0
+    return {"value": N * pt.R * sweeps / el, "unit": "mode-updates/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"sample 0 of the workload: {pt.R} copies x {sweeps} whole sweeps "
+                      f"(N={N}, {og.n_terms} terms), FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n-modes", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=8)
+    ap.add_argument("--temps", type=int, default=40)
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--shared-pairs", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copies-per-block", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (disorder samples would shard "
+              "across GPUs, see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_13508_amd import rlpt
+
+    torch.cuda.set_device(0)
+    N, S, T, reps = args.n_modes, args.samples, args.temps, args.reps
+    temps = 0.25 * (1.5 / 0.25) ** (np.arange(T) / (T - 1))
+    log(f"building {S} graphs N={N}")
+    graphs = [rlpt.Graph(N, SEED_BASE + mu) for mu in range(S)]
+    infos = [g.info() for g in graphs]
+    ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32,
+                       shared_pairs=args.shared_pairs, swap_interval=1, resync_interval=100, measure_start=0,
+                       measure_interval=1, n_bins=100, block_threads=args.block,
+                       copies_per_block=args.copies_per_block)
+    ctx.init(1)
+    log(f"warmup {args.warmup} sweeps")
+    ctx.sweep(args.warmup)
+    ctx.check()
+    torch.cuda.synchronize()
+    ctx.sweep_timing(True)
+    log(f"timing {args.steps} sweeps")
+    t0 = time.perf_counter()
+    ctx.sweep(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.check()
+    kms, launches = ctx.sweep_time()
+    ctx.sweep_timing(False)
+    n_copies = ctx.n_copies
+    value = N * n_copies * args.steps / el
+    # algorithmic bytes of one sweep launch (one sweep): every copy streams, per
+    # two-mode step, the lists of j and k; over a sweep of N/2 uniform pairs that
+    # is 4c entries on average, 8 bytes each
+    sweeps_per_launch = args.steps / launches
+    bytes_per_launch = sweeps_per_launch * sum(reps * T * inf["deg_sum"] * 8 for inf in infos)
+    t_launch = kms / launches * 1e-3
+    achieved = bytes_per_launch / t_launch / 1e9
+    traffic = traffic_for_current_kernel(bytes_per_launch)
+    log(f"{value:.4g} mode-updates/s; sweep kernel {kms / launches:.3f} ms/launch, {achieved:.0f} GB/s")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "mode-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"plain PT N={N}, {S} samples x {T} temperatures x {reps} replicas, FP32 fields, "
+                               f"FP64 resync/100, swap+measure every sweep",
+                   "n_modes": N, "samples": S, "temperatures": T, "replicas": reps, "copies": n_copies,
+                   "terms_per_sample": [inf["n_terms"] for inf in infos],
+                   "pair_schedule": "shared per sample" if args.shared_pairs else "per copy"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "k_sweep", "ms_per_launch": kms / launches,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "sweeps_per_s": args.steps / el,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            nthr = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        except (ValueError, AttributeError):
+            nthr = os.cpu_count() or 1
+        log(f"cpu baseline: oracle on {nthr} threads for ~{args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(N, temps, reps, args.cpu_seconds, nthr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

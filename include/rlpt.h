@@ -1,0 +1,259 @@
+/*
+ * rlpt.h -- C ABI of librlpt: parallel-tempering Monte Carlo of the 4-body
+ * smoothed-cubic random-laser Hamiltonian on a mode-locked graph, for AMD
+ * Instinct MI355X (gfx950).  Method: Benedetti & Leuzzi, "Smoothed-Cubic
+ * Spin-Glass Model of Random Lasers", arXiv 2511.13508.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns int: RLPT_OK (0) or a negative RLPT_E_* code; the
+ *    message of the last failure on the calling thread is rlpt_last_error().
+ *  - Host pointers are plain caller-owned arrays.  Device memory for a context
+ *    is ONE caller-owned workspace (e.g. a torch uint8 tensor), sized by
+ *    rlpt_workspace_size(); the library never allocates device memory for a
+ *    context and never frees the workspace.  The stream is caller-owned too.
+ *  - Work submitted by rlpt_init / rlpt_sweep / rlpt_swap is asynchronous on
+ *    the context's stream.  Calls that return host data synchronise the stream.
+ *  - Complex amplitudes cross the boundary as interleaved (re, im) doubles.
+ *  - A term (p, s, m, n) is the monomial conj(a_p) conj(a_s) a_m a_n; the
+ *    Hamiltonian is H = -sum_q J_q (X_q + c.c.) = -2 sum_q J_q Re X_q
+ *    (eq. H4 of the paper with H2 = 0 and real couplings, sec. II).
+ *  - Copies: a context holds S disorder samples, each with n_reps ladders of
+ *    n_temps baths (Table I layout).  Copy c = mu*R + r*n_temps + i with
+ *    R = n_temps*n_reps; copy c starts at temperature index i of its ladder
+ *    and moves between temperatures only through swaps.
+ */
+#ifndef RLPT_H
+#define RLPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RLPT_ABI_VERSION 1
+
+enum {
+    RLPT_OK = 0,
+    RLPT_E_ARG = -1,         /* invalid argument or size */
+    RLPT_E_NOMEM = -2,       /* host allocation failed or workspace too small */
+    RLPT_E_HIP = -3,         /* a HIP runtime call failed */
+    RLPT_E_STATE = -4,       /* NaN or energy / constraint drift found at a resync */
+    RLPT_E_UNSUPPORTED = -5  /* option not supported by this build */
+};
+
+enum { RLPT_OMEGA_RANDOM = 0, RLPT_OMEGA_COMB = 1 };
+enum { RLPT_SPLIT_A = 1, RLPT_SPLIT_B = 2, RLPT_SPLIT_C = 4, RLPT_SPLIT_ALL = 7 };
+enum { RLPT_FP32 = 0, RLPT_FP64 = 1 };
+
+/* ABI version (RLPT_ABI_VERSION of the built library). */
+int rlpt_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer is
+ * valid until the next rlpt call on the same thread. */
+const char* rlpt_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Graph and couplings (sec. II.C: quenched random frequencies, eq.          */
+/* gamma_scaling, "Graph generation", eq. Gauss).  Host only.                */
+/* ------------------------------------------------------------------------ */
+typedef struct rlpt_graph rlpt_graph;
+
+typedef struct rlpt_graph_desc {
+    int32_t n_modes;     /* N, 4 <= N <= 1024 */
+    int32_t omega_kind;  /* RLPT_OMEGA_RANDOM: sorted uniforms on [0,1); RLPT_OMEGA_COMB: k/(N-1) */
+    uint64_t seed;       /* disorder seed: frequencies and couplings */
+    int32_t split_mask;  /* which splits of each i<j<k<l are tested (RLPT_SPLIT_*) */
+    int32_t pad;
+    double gamma;        /* linewidth; <= 0 selects 1/(2(N-1)) (eq. gamma_scaling) */
+} rlpt_graph_desc;
+
+typedef struct rlpt_graph_info {
+    int32_t n_modes;
+    int32_t pad;
+    int64_t n_terms;     /* c, number of kept terms */
+    int64_t deg_min, deg_max, deg_sum; /* per-mode term counts; deg_sum = 4c */
+    double gamma;
+    double sigma2;       /* coupling variance N / c */
+    int64_t list_entries;/* per-mode list entries after padding */
+    int64_t list_bytes;  /* bytes streamed by the sweep for all per-mode lists (FP32 build) */
+} rlpt_graph_info;
+
+/* Build one disorder sample: frequencies; every split of every i<j<k<l into a
+ * conjugated pair (p, s) and a plain pair (m, n) with |w_p + w_s - w_m - w_n|
+ * < gamma becomes a term (splits tested in the order (i,l|j,k), (i,k|j,l),
+ * (i,j|k,l)); J_q ~ N(0, N/c) drawn in term order.  Generator: Philox4x64-10
+ * keyed by (seed, "GRAPH").  On success *out owns host memory; free it with
+ * rlpt_graph_free.  Errors: RLPT_E_ARG (N out of range, NULL), RLPT_E_NOMEM. */
+int rlpt_graph_build(const rlpt_graph_desc* desc, rlpt_graph** out);
+void rlpt_graph_free(rlpt_graph* g);
+int rlpt_graph_info_get(const rlpt_graph* g, rlpt_graph_info* out);
+
+/* Copy out frequencies omega[N], terms quads[c][4] (p, s, m, n) and couplings
+ * J[c] (double).  Any output pointer may be NULL.  Caller-allocated. */
+int rlpt_graph_export(const rlpt_graph* g, double* omega, int16_t* quads, double* J);
+
+/* ------------------------------------------------------------------------ */
+/* Parallel-tempering context (sec. III.A).                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct rlpt_ctx rlpt_ctx;
+
+typedef struct rlpt_config {
+    int32_t n_temps;          /* baths per ladder (N_PT of Table I) */
+    int32_t n_reps;           /* ladders (replicas) per sample, >= 1; overlaps need >= 2 */
+    int32_t precision;        /* RLPT_FP32 (fields, dE, running energy in FP32) or RLPT_FP64 */
+    int32_t shared_pairs;     /* 0: each copy draws its own pair sequence (paper);
+                                 1: all copies of a sample share one pair sequence */
+    int32_t swap_interval;    /* sweeps between swap rounds, >= 1 */
+    int32_t resync_interval;  /* sweeps between FP64 energy recomputations (0 = never) */
+    double renorm_tol;        /* rescale a copy when |sum|a|^4/N - 1| exceeds this */
+    double drift_tol;         /* RLPT_E_STATE when |E_run - H|/max(|H|,1) exceeds this at a
+                                 recomputation (<= 0: no check; NaN always fails) */
+    int32_t measure_start;    /* measure after completed sweep n when n > measure_start */
+    int32_t measure_interval; /* ... and n % measure_interval == 0 */
+    int32_t n_bins;           /* overlap histogram bins on [-1, 1] */
+    int32_t series_len;       /* stored measurements of E (ladder 0) and q_01 per bath */
+    int32_t block_threads;    /* threads per workgroup of the sweep kernel: 0 = tuned, else 64..1024 */
+    int32_t copies_per_block; /* copies per workgroup: 0 = tuned, else divides block_threads/64 */
+} rlpt_config;
+
+/* Fill *cfg with defaults: FP32, per-copy pairs, swap every sweep, FP64
+ * recomputation every 100 sweeps, renorm_tol 1e-6, drift_tol 1e-3, 100 bins. */
+int rlpt_config_default(rlpt_config* cfg);
+
+/* Device bytes needed for a context over graphs[0..n_graphs) (one per sample). */
+int rlpt_workspace_size(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs,
+                        size_t* bytes);
+
+/* Create a context.  temps[n_temps] (strictly ascending, > 0) is the ladder of
+ * every sample.  d_workspace: caller-owned device memory of at least
+ * rlpt_workspace_size() bytes, 256-byte aligned, alive until rlpt_destroy.
+ * hip_stream: a hipStream_t (NULL = default stream).  Uploads lists,
+ * couplings and ladders (host -> device copies on the stream).  The graphs
+ * may be freed after this call.  Errors: RLPT_E_ARG, RLPT_E_NOMEM, RLPT_E_HIP. */
+int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs,
+                const double* temps, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                rlpt_ctx** out);
+int rlpt_destroy(rlpt_ctx* ctx);
+
+/* Draw every copy from the infinite-temperature law of eq. ProbDistr (flat
+ * measure on sum|a|^4 = N, eq. SmoothedCubic rescaled): |a_k|^2 =
+ * sqrt(N)|g_k|/||g||, g standard normal, phases uniform; Philox keyed by
+ * (run_seed, "INIT") at counter (k, copy, 0, 0).  Resets temperatures,
+ * counters and accumulators; computes every energy in FP64.  Async. */
+int rlpt_init(rlpt_ctx* ctx, uint64_t run_seed);
+
+/* Advance n_sweeps sweeps.  One sweep = N/2 two-mode updates per copy (sec.
+ * III.A "Single Metropolis update"): distinct j, k from the pair stream;
+ * K^4 = |a_j|^4 + |a_k|^4; new phases 2 pi u; theta = (pi/2) u; |a_j'| =
+ * K sqrt(cos theta), |a_k'| = K sqrt(sin theta); accept when dE <= 0 or
+ * u < exp(-beta dE).  After every swap_interval sweeps a swap round, every
+ * resync_interval sweeps an FP64 recomputation, and measurements on the
+ * configured schedule.  Async; a drift/NaN failure is reported by the next
+ * synchronising call (rlpt_check, rlpt_observables, ...). */
+int rlpt_sweep(rlpt_ctx* ctx, int32_t n_sweeps);
+
+/* One extra swap round now (sec. III.A: neighbouring baths proposed in
+ * ascending order, accepted with min[1, exp((b_i - b_{i+1})(H_i - H_{i+1}))]).
+ * Async. */
+int rlpt_swap(rlpt_ctx* ctx);
+
+/* Recompute every energy in FP64 now (and renormalise drifted copies);
+ * synchronises; *max_drift (may be NULL) receives the largest relative
+ * difference between running and recomputed energies. */
+int rlpt_resync(rlpt_ctx* ctx, double* max_drift);
+
+/* Synchronise and report any drift / NaN failure recorded so far. */
+int rlpt_check(rlpt_ctx* ctx);
+
+/* Capture the work of one segment of n_sweeps sweeps (sweeps, swaps,
+ * recomputations, measurements) in a HIP graph and replay it n_segments
+ * times.  n_sweeps must be a multiple of swap_interval, resync_interval and
+ * measure_interval (those > 0) so that every replay performs the same work.
+ * Async. */
+int rlpt_run_graph(rlpt_ctx* ctx, int32_t n_sweeps, int32_t n_segments);
+
+/* Sweep-kernel timing: while enabled, every sweep launch outside graph capture
+ * is bracketed by HIP events on the context's stream.  rlpt_sweep_time_get
+ * synchronises, returns the summed kernel time in ms and the number of
+ * timed launches since the last reset, and resets the sums. */
+int rlpt_sweep_timing(rlpt_ctx* ctx, int32_t enable);
+int rlpt_sweep_time_get(rlpt_ctx* ctx, double* total_ms, int64_t* n_launches);
+
+/* Counters. */
+int rlpt_counters(rlpt_ctx* ctx, int64_t* sweeps_done, int64_t* swaps_done, int64_t* n_meas);
+
+/* ------------------------------------------------------------------------ */
+/* State access and test hooks (synchronous, host buffers).                  */
+/* ------------------------------------------------------------------------ */
+
+/* Amplitudes of n_copies copies starting at first_copy, each 2*N doubles
+ * (interleaved re, im); all copies in the range must belong to samples of one N.
+ * set_state converts to the context precision and does NOT update energies
+ * (call rlpt_resync afterwards). */
+int rlpt_get_state(rlpt_ctx* ctx, int32_t first_copy, int32_t n_copies, double* a);
+int rlpt_set_state(rlpt_ctx* ctx, int32_t first_copy, int32_t n_copies, const double* a);
+
+/* Running energies E[n_copies], temperature index of each copy temp_of[n_copies]. */
+int rlpt_get_energies(rlpt_ctx* ctx, double* E, int32_t* temp_of);
+
+/* FP64 energy of every copy (no state change). */
+int rlpt_energy_fp64(rlpt_ctx* ctx, double* E);
+
+/* Local fields F_l = sum over terms containing l of J conj(a_x) a_y a_z
+ * (x: l's partner on its side of the term, (y, z): the other side) of one copy,
+ * computed by the sweep kernel's own field code in the context precision.
+ * F: 2*N doubles.  (Energy update of sec. III.A "Energy update parallel
+ * computation".) */
+int rlpt_local_fields(rlpt_ctx* ctx, int32_t copy, double* F);
+
+/* Energy change of the two-mode update (a_j, a_k) -> (aj_new, ak_new) of one
+ * copy, by the sweep kernel's code path: both fields on one snapshot holding
+ * aj_new and the old a_k.  n pairs; j, k, aj_new (2n), ak_new (2n), dE (n). */
+int rlpt_pair_dE(rlpt_ctx* ctx, int32_t copy, int32_t n, const int32_t* j, const int32_t* k,
+                 const double* aj_new, const double* ak_new, double* dE);
+
+/* ------------------------------------------------------------------------ */
+/* Observables (sec. IV): accumulated since rlpt_init per sample mu and bath t */
+/* ------------------------------------------------------------------------ */
+typedef struct rlpt_obs {
+    /* each array is caller-allocated; NULL skips it.  Shapes use S samples,
+     * T baths, B bins, L series length. */
+    double* e_n;     /* [S][T] number of energy samples (measurements x replicas) */
+    double* e_sum;   /* [S][T] sum E */
+    double* e_sq;    /* [S][T] sum E^2            -> C_V = (<E^2> - <E>^2)/T^2 (eq. SpecificHeat) */
+    double* y2_sum;  /* [S][T] sum Y_2 ; Y_n = sum|a|^(2n) / (sum|a|^n)^2 */
+    double* y4_sum;  /* [S][T] sum Y_4 */
+    double* q_n;     /* [S][T] number of overlap samples (measurements x replica pairs) */
+    double* q_sum;   /* [S][T] sum q ; q_cd = (1/N) Re sum conj(a^c) a^d */
+    double* q_sq;    /* [S][T] */
+    double* q_4;     /* [S][T] */
+    double* hist;    /* [S][T][B] overlap histogram on [-1, 1] */
+    double* acc;     /* [S][T] accepted two-mode moves */
+    double* tries;   /* [S][T] proposed two-mode moves */
+    double* swap_acc;   /* [S][T-1] accepted exchanges (summed over ladders) */
+    double* swap_tries; /* [S][T-1] */
+    double* series_e;   /* [S][T][L] energy of ladder 0's copy at bath t, per measurement */
+    double* series_q;   /* [S][T][L] overlap of ladders 0 and 1 at bath t, per measurement */
+} rlpt_obs;
+
+/* Copy the accumulators to host (synchronises).  Returns RLPT_E_STATE if a
+ * drift / NaN failure was recorded. */
+int rlpt_observables(rlpt_ctx* ctx, rlpt_obs* out);
+
+/* ------------------------------------------------------------------------ */
+/* Analysis helpers (host).                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Integrated autocorrelation time of a series x[n] with Sokal's automatic
+ * window: tau(W) = 1/2 + sum_{t=1..W} rho(t), smallest W >= c_window*tau(W).
+ * *tau receives tau_int, *window the chosen W. */
+int rlpt_tau_int(const double* x, int64_t n, double c_window, double* tau, int64_t* window);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLPT_H */

@@ -1,0 +1,805 @@
+// C-ABI runtime of librlpt: contexts over a caller-owned workspace, the
+// sweep / swap / recomputation / measurement schedule of parallel tempering
+// (sec. III.A and sec. III.B of Benedetti & Leuzzi, arXiv 2511.13508), HIP
+// graph replay of whole segments, observables read-back and host analysis.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace rlpt {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+    return fail(RLPT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                           \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Launch tile of the sweep kernel for a sample of N modes: threads per
+// workgroup and copies per workgroup (each copy gets (block/64)/copies waves).
+// Entries streamed per two-mode step ~ 2 * 4c/N ~ 2N^2/3; small N packs
+// several copies (one wave each) into a workgroup.
+struct Tile {
+    int block;
+    int copies;
+};
+
+static Tile default_tile(int N) {
+    if (N >= 192) return {256, 1};
+    if (N >= 96) return {256, 2};
+    return {256, 4};
+}
+
+static Tile tile_for(const rlpt_config& cfg, int N) {
+    Tile t = default_tile(N);
+    if (cfg.block_threads > 0) t.block = cfg.block_threads;
+    if (cfg.copies_per_block > 0) t.copies = cfg.copies_per_block;
+    return t;
+}
+
+}  // namespace rlpt
+
+using namespace rlpt;
+
+struct rlpt_ctx {
+    rlpt_config cfg{};
+    hipStream_t stream = nullptr;
+    int S = 0, T = 0, reps = 0, Rc = 0, n_copies = 0, max_N = 0;
+    std::vector<int> N;
+    std::vector<double> temps;
+    std::vector<SampleDev> samples;
+    std::vector<ItemDev> items;
+    ShapeInfo sh{};
+    SweepLaunch launch{};
+    DevPtrs<float> pf{};
+    DevPtrs<double> pd{};
+    // regions of the workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    unsigned char* acc_region = nullptr;  // accumulators cleared at init
+    size_t acc_region_bytes = 0;
+    double* scratch = nullptr;            // hook / state-transfer buffer (doubles)
+    size_t scratch_doubles = 0;
+    int64_t amp_complex = 0;
+    int64_t sweeps_done = 0, swaps_done = 0;
+    bool inited = false;
+    // cached HIP graph of one segment
+    hipGraphExec_t exec = nullptr;
+    int graph_sweeps = 0;
+    int64_t graph_phase = -1;
+    bool graph_measuring = false;
+    // sweep-kernel timing
+    bool timing = false;
+    bool capturing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events, spare;
+
+    const void* ptrs() const {
+        return cfg.precision == RLPT_FP64 ? static_cast<const void*>(&pd) : static_cast<const void*>(&pf);
+    }
+    size_t real_bytes() const { return cfg.precision == RLPT_FP64 ? 8 : 4; }
+};
+
+namespace {
+
+// byte layout of a workspace; also used to size it
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+struct Regions {
+    size_t samples, items, mode_start, idx, J, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
+    size_t acc_begin, acc, swap_acc, obs, hist, series_e, series_q, meas_cnt, counters, acc_end;
+    size_t scratch, scratch_doubles, total;
+};
+
+int check_config(const rlpt_config* cfg) {
+    if (!cfg) return fail(RLPT_E_ARG, "config is NULL");
+    if (cfg->n_temps < 1 || cfg->n_reps < 1) return fail(RLPT_E_ARG, "n_temps and n_reps must be >= 1");
+    if (cfg->precision != RLPT_FP32 && cfg->precision != RLPT_FP64) return fail(RLPT_E_ARG, "bad precision");
+    if (cfg->swap_interval < 1) return fail(RLPT_E_ARG, "swap_interval must be >= 1");
+    if (cfg->resync_interval < 0 || cfg->measure_interval < 0) return fail(RLPT_E_ARG, "negative interval");
+    if (cfg->n_bins < 1) return fail(RLPT_E_ARG, "n_bins must be >= 1");
+    if (cfg->series_len < 0) return fail(RLPT_E_ARG, "series_len must be >= 0");
+    if (cfg->block_threads != 0 && (cfg->block_threads < 64 || cfg->block_threads > 1024 ||
+                                    (cfg->block_threads & (cfg->block_threads - 1))))
+        return fail(RLPT_E_ARG, "block_threads must be 0 or a power of two in [64, 1024]");
+    if (cfg->copies_per_block < 0) return fail(RLPT_E_ARG, "copies_per_block must be >= 0");
+    return RLPT_OK;
+}
+
+int check_graphs(const rlpt_graph* const* g, int n) {
+    if (!g || n < 1) return fail(RLPT_E_ARG, "need at least one graph");
+    for (int i = 0; i < n; ++i)
+        if (!g[i]) return fail(RLPT_E_ARG, "graph pointer is NULL");
+    return RLPT_OK;
+}
+
+Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S) {
+    const size_t rb = cfg.precision == RLPT_FP64 ? 8 : 4;
+    const size_t T = cfg.n_temps, reps = cfg.n_reps, Rc = T * reps, copies = Rc * S;
+    size_t modes = 0, entries = 0, quads = 0, amp = 0;
+    int max_N = 0;
+    for (int i = 0; i < S; ++i) {
+        modes += g[i]->N + 1;
+        entries += g[i]->mode_start.back();
+        quads += g[i]->n_terms();
+        amp += Rc * g[i]->N;
+        max_N = std::max(max_N, g[i]->N);
+    }
+    Layout L;
+    Regions r{};
+    r.samples = L.take(S * sizeof(SampleDev));
+    r.items = L.take(copies * sizeof(ItemDev));
+    r.mode_start = L.take(modes * 4);
+    r.idx = L.take(entries * 4);
+    r.J = L.take(entries * rb);
+    r.quads = L.take(quads * 8);
+    r.Jq = L.take(quads * 8);
+    r.amp = L.take(amp * 2 * rb);
+    r.E = L.take(copies * rb);
+    r.E64 = L.take(copies * 8);
+    r.drift = L.take(copies * 8);
+    r.temp_of = L.take(copies * 4);
+    r.copy_at = L.take(S * reps * T * 4);
+    r.beta = L.take(T * rb);
+    r.beta64 = L.take(T * 8);
+    r.acc_begin = L.off;
+    r.acc = L.take(S * T * 8);
+    r.swap_acc = L.take(S * reps * std::max<size_t>(T - 1, 1) * 8);
+    r.obs = L.take(kNumObs * S * T * 8);
+    r.hist = L.take(S * T * cfg.n_bins * 8);
+    r.series_e = L.take(S * T * std::max(cfg.series_len, 1) * 8);
+    r.series_q = L.take(S * T * std::max(cfg.series_len, 1) * 8);
+    r.meas_cnt = L.take(S * T * 4);
+    r.counters = L.take(sizeof(Counters));
+    r.acc_end = L.off;
+    r.scratch_doubles = std::max<size_t>(2 * amp, 8192);
+    r.scratch = L.take(r.scratch_doubles * 8);
+    r.total = L.off;
+    return r;
+}
+
+template <typename R>
+void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
+    P.samples = reinterpret_cast<const SampleDev*>(b + r.samples);
+    P.items = reinterpret_cast<const ItemDev*>(b + r.items);
+    P.mode_start = reinterpret_cast<const uint32_t*>(b + r.mode_start);
+    P.idx = reinterpret_cast<const uint32_t*>(b + r.idx);
+    P.J = reinterpret_cast<const R*>(b + r.J);
+    P.quads = reinterpret_cast<const ushort4*>(b + r.quads);
+    P.Jq = reinterpret_cast<const double*>(b + r.Jq);
+    P.amp = reinterpret_cast<R*>(b + r.amp);
+    P.E = reinterpret_cast<R*>(b + r.E);
+    P.E64 = reinterpret_cast<double*>(b + r.E64);
+    P.drift = reinterpret_cast<double*>(b + r.drift);
+    P.temp_of = reinterpret_cast<int32_t*>(b + r.temp_of);
+    P.copy_at = reinterpret_cast<int32_t*>(b + r.copy_at);
+    P.beta = reinterpret_cast<const R*>(b + r.beta);
+    P.beta64 = reinterpret_cast<const double*>(b + r.beta64);
+    P.acc = reinterpret_cast<unsigned long long*>(b + r.acc);
+    P.swap_acc = reinterpret_cast<unsigned long long*>(b + r.swap_acc);
+    P.obs = reinterpret_cast<double*>(b + r.obs);
+    P.hist = reinterpret_cast<double*>(b + r.hist);
+    P.series_e = reinterpret_cast<double*>(b + r.series_e);
+    P.series_q = reinterpret_cast<double*>(b + r.series_q);
+    P.meas_cnt = reinterpret_cast<int32_t*>(b + r.meas_cnt);
+    P.counters = reinterpret_cast<Counters*>(b + r.counters);
+}
+
+template <typename T>
+hipError_t upload(unsigned char* base, size_t off, const std::vector<T>& v, hipStream_t st) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+Counters* counters_of(rlpt_ctx* c) { return c->cfg.precision == RLPT_FP64 ? c->pd.counters : c->pf.counters; }
+
+bool measuring_at(const rlpt_ctx* c, int64_t n) {
+    return n > c->cfg.measure_start && c->cfg.measure_interval > 0 && n % c->cfg.measure_interval == 0;
+}
+
+// enqueue n sweeps starting after `done` completed sweeps (no host mirror update)
+int enqueue_sweeps(rlpt_ctx* c, int64_t done, int64_t n, int64_t* swaps_added) {
+    const rlpt_config& cfg = c->cfg;
+    int64_t k = 0;
+    *swaps_added = 0;
+    while (k < n) {
+        const int64_t cur = done + k;
+        // sweeps until the next event boundary
+        int64_t step = n - k;
+        const int iv[3] = {cfg.swap_interval, cfg.resync_interval, cfg.measure_interval};
+        for (int i = 0; i < 3; ++i)
+            if (iv[i] > 0) step = std::min<int64_t>(step, iv[i] - cur % iv[i]);
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (c->timing && !c->capturing) {
+            if (!c->spare.empty()) {
+                ev = c->spare.back();
+                c->spare.pop_back();
+            } else {
+                HIP_TRY(hipEventCreate(&ev.first), "event create");
+                HIP_TRY(hipEventCreate(&ev.second), "event create");
+            }
+            HIP_TRY(hipEventRecord(ev.first, c->stream), "event record");
+        }
+        HIP_TRY(launch_sweep(cfg.precision, c->ptrs(), c->sh, c->launch, (int)step, c->stream), "sweep launch");
+        if (ev.first) {
+            HIP_TRY(hipEventRecord(ev.second, c->stream), "event record");
+            c->events.push_back(ev);
+        }
+        const int64_t after = cur + step;
+        const bool swap = c->T > 1 && after % cfg.swap_interval == 0;
+        if (swap) HIP_TRY(launch_swap(cfg.precision, c->ptrs(), c->sh, c->stream), "swap launch");
+        HIP_TRY(launch_tick(c->ptrs(), cfg.precision, step, swap ? 1 : 0, c->stream), "tick launch");
+        if (swap) *swaps_added += 1;
+        if (cfg.resync_interval > 0 && after % cfg.resync_interval == 0)
+            HIP_TRY(launch_resync(cfg.precision, c->ptrs(), c->sh, c->n_copies, 0, c->stream), "resync launch");
+        if (measuring_at(c, after)) HIP_TRY(launch_measure(cfg.precision, c->ptrs(), c->sh, c->stream), "measure launch");
+        k += step;
+    }
+    return RLPT_OK;
+}
+
+int sync_and_flags(rlpt_ctx* c) {
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    Counters h{};
+    HIP_TRY(hipMemcpy(&h, counters_of(c), sizeof(Counters), hipMemcpyDeviceToHost), "read counters");
+    if (h.error_flags & 2) return fail(RLPT_E_STATE, "non-finite energy or amplitude found at a recomputation");
+    if (h.error_flags & 1) return fail(RLPT_E_STATE, "running energy drifted beyond drift_tol");
+    return RLPT_OK;
+}
+
+void drop_events(rlpt_ctx* c) {
+    for (auto* v : {&c->events, &c->spare})
+        for (auto& e : *v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    c->events.clear();
+    c->spare.clear();
+}
+
+void drop_graph(rlpt_ctx* c) {
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    c->exec = nullptr;
+    c->graph_sweeps = 0;
+    c->graph_phase = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlpt_abi_version(void) { return RLPT_ABI_VERSION; }
+
+const char* rlpt_last_error(void) { return g_last_error.c_str(); }
+
+int rlpt_config_default(rlpt_config* cfg) {
+    if (!cfg) return fail(RLPT_E_ARG, "config is NULL");
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->n_temps = 1;
+    cfg->n_reps = 2;
+    cfg->precision = RLPT_FP32;
+    cfg->shared_pairs = 0;
+    cfg->swap_interval = 1;
+    cfg->resync_interval = 100;
+    cfg->renorm_tol = 1e-6;
+    cfg->drift_tol = 1e-3;
+    cfg->measure_start = 0;
+    cfg->measure_interval = 1;
+    cfg->n_bins = 100;
+    cfg->series_len = 0;
+    return RLPT_OK;
+}
+
+int rlpt_workspace_size(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs, size_t* bytes) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if ((rc = check_graphs(graphs, n_graphs))) return rc;
+    if (!bytes) return fail(RLPT_E_ARG, "bytes is NULL");
+    *bytes = plan(*cfg, graphs, n_graphs).total;
+    return RLPT_OK;
+}
+
+int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs, const double* temps,
+                void* d_workspace, size_t workspace_bytes, void* hip_stream, rlpt_ctx** out) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if ((rc = check_graphs(graphs, n_graphs))) return rc;
+    if (!temps || !out) return fail(RLPT_E_ARG, "temps / out is NULL");
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(RLPT_E_ARG, "workspace must be 256-byte aligned");
+    *out = nullptr;
+    for (int t = 0; t < cfg->n_temps; ++t) {
+        if (!(temps[t] > 0.0) || !isfinite(temps[t])) return fail(RLPT_E_ARG, "temperatures must be finite and > 0");
+        if (t > 0 && !(temps[t] > temps[t - 1])) return fail(RLPT_E_ARG, "temperatures must be strictly ascending");
+    }
+    const Regions r = plan(*cfg, graphs, n_graphs);
+    if (workspace_bytes < r.total) return fail(RLPT_E_NOMEM, "workspace smaller than rlpt_workspace_size()");
+    rlpt_ctx* c = new (std::nothrow) rlpt_ctx;
+    if (!c) return fail(RLPT_E_NOMEM, "out of host memory");
+    c->cfg = *cfg;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->S = n_graphs;
+    c->T = cfg->n_temps;
+    c->reps = cfg->n_reps;
+    c->Rc = c->T * c->reps;
+    c->n_copies = c->Rc * c->S;
+    c->temps.assign(temps, temps + c->T);
+    c->ws = d_workspace;
+    c->ws_bytes = workspace_bytes;
+    unsigned char* b = static_cast<unsigned char*>(d_workspace);
+    fill_ptrs(c->pf, b, r);
+    fill_ptrs(c->pd, b, r);
+    c->acc_region = b + r.acc_begin;
+    c->acc_region_bytes = r.acc_end - r.acc_begin;
+    c->scratch = reinterpret_cast<double*>(b + r.scratch);
+    c->scratch_doubles = r.scratch_doubles;
+
+    // host images of the device tables
+    std::vector<uint32_t> ms, idx;
+    std::vector<float> J32;
+    std::vector<double> J64, Jq;
+    std::vector<ushort4> quads;
+    int64_t amp_base = 0, quad_base = 0;
+    for (int s = 0; s < c->S; ++s) {
+        const rlpt_graph* g = graphs[s];
+        SampleDev sd{};
+        sd.N = g->N;
+        sd.n_steps = g->N / 2;
+        sd.mode_base = (uint32_t)ms.size();
+        sd.amp_base = amp_base;
+        sd.quad_base = quad_base;
+        sd.n_quads = g->n_terms();
+        const uint32_t ebase = (uint32_t)idx.size();
+        for (uint32_t v : g->mode_start) ms.push_back(v + ebase);
+        idx.insert(idx.end(), g->idx.begin(), g->idx.end());
+        if (cfg->precision == RLPT_FP64) J64.insert(J64.end(), g->Jl.begin(), g->Jl.end());
+        else
+            for (double v : g->Jl) J32.push_back((float)v);
+        for (int64_t q = 0; q < g->n_terms(); ++q) {
+            ushort4 u;
+            u.x = (unsigned short)g->quads[4 * q];
+            u.y = (unsigned short)g->quads[4 * q + 1];
+            u.z = (unsigned short)g->quads[4 * q + 2];
+            u.w = (unsigned short)g->quads[4 * q + 3];
+            quads.push_back(u);
+        }
+        Jq.insert(Jq.end(), g->J.begin(), g->J.end());
+        amp_base += (int64_t)c->Rc * g->N;
+        quad_base += g->n_terms();
+        c->samples.push_back(sd);
+        c->N.push_back(g->N);
+        c->max_N = std::max(c->max_N, g->N);
+    }
+    c->amp_complex = amp_base;
+    // work items: samples ordered by decreasing N (longest work first), copies
+    // in chunks of the tile's copies-per-workgroup
+    int block = 0, max_cpi = 1;
+    {
+        int Nbig = c->max_N;
+        block = tile_for(*cfg, Nbig).block;
+        std::vector<int> order(c->S);
+        for (int s = 0; s < c->S; ++s) order[s] = s;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return c->N[a] > c->N[b2]; });
+        for (int s : order) {
+            int cpw = tile_for(*cfg, c->N[s]).copies;
+            cpw = std::max(1, std::min(cpw, block / 64));
+            for (int first = 0; first < c->Rc; first += cpw) {
+                ItemDev it{};
+                it.first_copy = s * c->Rc + first;
+                it.n_copies = std::min(cpw, c->Rc - first);
+                it.sample = s;
+                c->items.push_back(it);
+                max_cpi = std::max(max_cpi, it.n_copies);
+            }
+        }
+    }
+    c->launch.block_threads = block;
+    c->launch.n_items = (int)c->items.size();
+    c->launch.max_copies_per_item = max_cpi;
+    c->launch.max_N = c->max_N;
+    c->launch.lds_bytes = sweep_lds_bytes(cfg->precision, block, max_cpi, c->max_N);
+    if (c->launch.lds_bytes > 64 * 1024) {
+        delete c;
+        return fail(RLPT_E_ARG, "sweep tile needs more LDS than a CU has; use fewer copies per block");
+    }
+    c->sh.n_samples = c->S;
+    c->sh.n_temps = c->T;
+    c->sh.n_reps = c->reps;
+    c->sh.copies_per_sample = c->Rc;
+    c->sh.n_bins = cfg->n_bins;
+    c->sh.series_len = cfg->series_len;
+    c->sh.shared_pairs = cfg->shared_pairs;
+    c->sh.renorm_tol = cfg->renorm_tol;
+    c->sh.drift_tol = cfg->drift_tol;
+
+    std::vector<float> b32(c->T);
+    std::vector<double> b64(c->T);
+    for (int t = 0; t < c->T; ++t) {
+        b64[t] = 1.0 / temps[t];
+        b32[t] = (float)b64[t];
+    }
+    hipError_t e = hipSuccess;
+    auto up = [&](size_t off, auto& v) {
+        if (e == hipSuccess) e = upload(b, off, v, c->stream);
+    };
+    up(r.samples, c->samples);
+    up(r.items, c->items);
+    up(r.mode_start, ms);
+    up(r.idx, idx);
+    if (cfg->precision == RLPT_FP64) up(r.J, J64);
+    else up(r.J, J32);
+    up(r.quads, quads);
+    up(r.Jq, Jq);
+    if (cfg->precision == RLPT_FP64) up(r.beta, b64);
+    else up(r.beta, b32);
+    up(r.beta64, b64);
+    if (e == hipSuccess) e = launch_zero(c->acc_region, c->acc_region_bytes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "rlpt_create upload");
+    }
+    *out = c;
+    return RLPT_OK;
+}
+
+int rlpt_destroy(rlpt_ctx* c) {
+    if (!c) return RLPT_OK;
+    (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    drop_events(c);
+    delete c;
+    return RLPT_OK;
+}
+
+int rlpt_init(rlpt_ctx* c, uint64_t run_seed) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    drop_graph(c);
+    c->sh.run_seed = run_seed;
+    HIP_TRY(launch_zero(c->acc_region, c->acc_region_bytes, c->stream), "zero accumulators");
+    HIP_TRY(launch_init(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 256, c->stream), "init launch");
+    HIP_TRY(launch_resync(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 2, c->stream), "initial energies");
+    c->sweeps_done = 0;
+    c->swaps_done = 0;
+    c->inited = true;
+    return RLPT_OK;
+}
+
+int rlpt_sweep(rlpt_ctx* c, int32_t n_sweeps) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    if (n_sweeps < 0) return fail(RLPT_E_ARG, "n_sweeps must be >= 0");
+    int64_t swaps = 0;
+    int rc = enqueue_sweeps(c, c->sweeps_done, n_sweeps, &swaps);
+    if (rc) return rc;
+    c->sweeps_done += n_sweeps;
+    c->swaps_done += swaps;
+    return RLPT_OK;
+}
+
+int rlpt_swap(rlpt_ctx* c) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    if (c->T < 2) return RLPT_OK;
+    HIP_TRY(launch_swap(c->cfg.precision, c->ptrs(), c->sh, c->stream), "swap launch");
+    HIP_TRY(launch_tick(c->ptrs(), c->cfg.precision, 0, 1, c->stream), "tick launch");
+    c->swaps_done += 1;
+    return RLPT_OK;
+}
+
+int rlpt_resync(rlpt_ctx* c, double* max_drift) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    HIP_TRY(launch_resync(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 0, c->stream), "resync launch");
+    int rc = sync_and_flags(c);
+    if (max_drift) {
+        std::vector<double> d(c->n_copies);
+        const double* dp = c->cfg.precision == RLPT_FP64 ? c->pd.drift : c->pf.drift;
+        HIP_TRY(hipMemcpy(d.data(), dp, d.size() * 8, hipMemcpyDeviceToHost), "read drift");
+        double m = 0.0;
+        for (double v : d) m = (v > m || v != v) ? v : m;
+        *max_drift = m;
+    }
+    return rc;
+}
+
+int rlpt_check(rlpt_ctx* c) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    return sync_and_flags(c);
+}
+
+int rlpt_run_graph(rlpt_ctx* c, int32_t n_sweeps, int32_t n_segments) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    if (n_sweeps < 1 || n_segments < 0) return fail(RLPT_E_ARG, "n_sweeps must be >= 1 and n_segments >= 0");
+    const rlpt_config& cfg = c->cfg;
+    const int iv[3] = {cfg.swap_interval, cfg.resync_interval, cfg.measure_interval};
+    for (int i = 0; i < 3; ++i)
+        if (iv[i] > 0 && n_sweeps % iv[i] != 0)
+            return fail(RLPT_E_ARG, "n_sweeps must be a multiple of swap, resync and measure intervals");
+    const int64_t end = c->sweeps_done + (int64_t)n_sweeps * n_segments;
+    if (c->sweeps_done < cfg.measure_start && end > cfg.measure_start)
+        return fail(RLPT_E_ARG, "graph segments may not straddle measure_start; advance with rlpt_sweep first");
+    if (n_segments == 0) return RLPT_OK;
+    const bool measuring = c->sweeps_done >= cfg.measure_start;
+    const int64_t phase = c->sweeps_done % n_sweeps;
+    int64_t swaps_per_segment = 0;
+    if (!c->exec || c->graph_sweeps != n_sweeps || c->graph_phase != phase || c->graph_measuring != measuring) {
+        drop_graph(c);
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        int64_t sw = 0;
+        c->capturing = true;
+        int rc = enqueue_sweeps(c, c->sweeps_done, n_sweeps, &sw);
+        c->capturing = false;
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        e = hipGraphInstantiate(&c->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            c->exec = nullptr;
+            return hip_fail(e, "graph instantiate");
+        }
+        c->graph_sweeps = n_sweeps;
+        c->graph_phase = phase;
+        c->graph_measuring = measuring;
+    }
+    {  // swaps per segment from the schedule (same for every replay)
+        for (int64_t k = 1; k <= n_sweeps; ++k)
+            if (c->T > 1 && (c->sweeps_done + k) % cfg.swap_interval == 0) ++swaps_per_segment;
+    }
+    for (int s = 0; s < n_segments; ++s) HIP_TRY(hipGraphLaunch(c->exec, c->stream), "graph launch");
+    c->sweeps_done += (int64_t)n_sweeps * n_segments;
+    c->swaps_done += swaps_per_segment * n_segments;
+    return RLPT_OK;
+}
+
+int rlpt_sweep_timing(rlpt_ctx* c, int32_t enable) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    c->timing = enable != 0;
+    return RLPT_OK;
+}
+
+int rlpt_sweep_time_get(rlpt_ctx* c, double* total_ms, int64_t* n_launches) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    double sum = 0.0;
+    for (auto& e : c->events) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second), "event elapsed");
+        sum += ms;
+        c->spare.push_back(e);
+    }
+    if (n_launches) *n_launches = (int64_t)c->events.size();
+    if (total_ms) *total_ms = sum;
+    c->events.clear();
+    return RLPT_OK;
+}
+
+int rlpt_counters(rlpt_ctx* c, int64_t* sweeps_done, int64_t* swaps_done, int64_t* n_meas) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    if (sweeps_done) *sweeps_done = c->sweeps_done;
+    if (swaps_done) *swaps_done = c->swaps_done;
+    if (n_meas) {
+        int32_t m = 0;
+        const int32_t* mp = c->cfg.precision == RLPT_FP64 ? c->pd.meas_cnt : c->pf.meas_cnt;
+        HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+        HIP_TRY(hipMemcpy(&m, mp, 4, hipMemcpyDeviceToHost), "read measurement count");
+        *n_meas = m;
+    }
+    return RLPT_OK;
+}
+
+static int copy_range(rlpt_ctx* c, int first, int n, int64_t* off, int64_t* count) {
+    if (first < 0 || n < 0 || first + n > c->n_copies) return fail(RLPT_E_ARG, "copy range out of bounds");
+    int64_t o = 0, k = 0;
+    for (int cp = 0; cp < first + n; ++cp) {
+        const int64_t Nc = c->N[cp / c->Rc];
+        if (cp < first) o += Nc;
+        else k += Nc;
+    }
+    *off = o;
+    *count = k;
+    if ((size_t)(2 * k) > c->scratch_doubles) return fail(RLPT_E_ARG, "copy range too large");
+    return RLPT_OK;
+}
+
+int rlpt_get_state(rlpt_ctx* c, int32_t first, int32_t n, double* a) {
+    if (!c || !a) return fail(RLPT_E_ARG, "NULL argument");
+    int64_t off, k;
+    int rc = copy_range(c, first, n, &off, &k);
+    if (rc) return rc;
+    unsigned char* amp = reinterpret_cast<unsigned char*>(c->cfg.precision == RLPT_FP64 ? (void*)c->pd.amp : (void*)c->pf.amp);
+    HIP_TRY(launch_convert_state(c->cfg.precision, amp + off * 2 * c->real_bytes(), c->scratch, k, 0, c->stream), "convert");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY(hipMemcpy(a, c->scratch, k * 16, hipMemcpyDeviceToHost), "state read");
+    return RLPT_OK;
+}
+
+int rlpt_set_state(rlpt_ctx* c, int32_t first, int32_t n, const double* a) {
+    if (!c || !a) return fail(RLPT_E_ARG, "NULL argument");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    int64_t off, k;
+    int rc = copy_range(c, first, n, &off, &k);
+    if (rc) return rc;
+    for (int64_t i = 0; i < 2 * k; ++i)
+        if (!isfinite(a[i])) return fail(RLPT_E_ARG, "state holds a non-finite value");
+    unsigned char* amp = reinterpret_cast<unsigned char*>(c->cfg.precision == RLPT_FP64 ? (void*)c->pd.amp : (void*)c->pf.amp);
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY(hipMemcpy(c->scratch, a, k * 16, hipMemcpyHostToDevice), "state write");
+    HIP_TRY(launch_convert_state(c->cfg.precision, amp + off * 2 * c->real_bytes(), c->scratch, k, 1, c->stream), "convert");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    return RLPT_OK;
+}
+
+int rlpt_get_energies(rlpt_ctx* c, double* E, int32_t* temp_of) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    if (E) {
+        if (c->cfg.precision == RLPT_FP64) {
+            HIP_TRY(hipMemcpy(E, c->pd.E, c->n_copies * 8, hipMemcpyDeviceToHost), "read energies");
+        } else {
+            std::vector<float> e(c->n_copies);
+            HIP_TRY(hipMemcpy(e.data(), c->pf.E, c->n_copies * 4, hipMemcpyDeviceToHost), "read energies");
+            for (int i = 0; i < c->n_copies; ++i) E[i] = e[i];
+        }
+    }
+    if (temp_of) {
+        const int32_t* tp = c->cfg.precision == RLPT_FP64 ? c->pd.temp_of : c->pf.temp_of;
+        HIP_TRY(hipMemcpy(temp_of, tp, c->n_copies * 4, hipMemcpyDeviceToHost), "read temperatures");
+    }
+    return RLPT_OK;
+}
+
+int rlpt_energy_fp64(rlpt_ctx* c, double* E) {
+    if (!c || !E) return fail(RLPT_E_ARG, "NULL argument");
+    HIP_TRY(launch_resync(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 1, c->stream), "energy launch");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    const double* ep = c->cfg.precision == RLPT_FP64 ? c->pd.E64 : c->pf.E64;
+    HIP_TRY(hipMemcpy(E, ep, c->n_copies * 8, hipMemcpyDeviceToHost), "read energies");
+    return RLPT_OK;
+}
+
+int rlpt_local_fields(rlpt_ctx* c, int32_t copy, double* F) {
+    if (!c || !F) return fail(RLPT_E_ARG, "NULL argument");
+    if (copy < 0 || copy >= c->n_copies) return fail(RLPT_E_ARG, "copy out of range");
+    const int mu = copy / c->Rc, N = c->N[mu];
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY(launch_fields_sh(c->cfg.precision, c->ptrs(), c->sh, copy, mu, c->scratch, c->stream), "fields launch");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY(hipMemcpy(F, c->scratch, (size_t)N * 16, hipMemcpyDeviceToHost), "read fields");
+    return RLPT_OK;
+}
+
+int rlpt_pair_dE(rlpt_ctx* c, int32_t copy, int32_t n, const int32_t* j, const int32_t* k, const double* aj_new,
+                 const double* ak_new, double* dE) {
+    if (!c || !j || !k || !aj_new || !ak_new || !dE) return fail(RLPT_E_ARG, "NULL argument");
+    if (copy < 0 || copy >= c->n_copies) return fail(RLPT_E_ARG, "copy out of range");
+    const int mu = copy / c->Rc, N = c->N[mu];
+    if (n < 0 || (size_t)n * 8 > c->scratch_doubles) return fail(RLPT_E_ARG, "too many pairs");
+    std::vector<int32_t> jk(2 * (size_t)n);
+    std::vector<double> nw(4 * (size_t)n);
+    for (int p = 0; p < n; ++p) {
+        if (j[p] < 0 || j[p] >= N || k[p] < 0 || k[p] >= N || j[p] == k[p])
+            return fail(RLPT_E_ARG, "pair indices must be distinct modes in [0, N)");
+        jk[2 * p] = j[p];
+        jk[2 * p + 1] = k[p];
+        nw[4 * p] = aj_new[2 * p];
+        nw[4 * p + 1] = aj_new[2 * p + 1];
+        nw[4 * p + 2] = ak_new[2 * p];
+        nw[4 * p + 3] = ak_new[2 * p + 1];
+    }
+    if (n == 0) return RLPT_OK;
+    double* d_nw = c->scratch;
+    double* d_dE = c->scratch + 4 * (size_t)n;
+    int32_t* d_jk = reinterpret_cast<int32_t*>(c->scratch + 5 * (size_t)n);
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY(hipMemcpy(d_nw, nw.data(), nw.size() * 8, hipMemcpyHostToDevice), "write proposals");
+    HIP_TRY(hipMemcpy(d_jk, jk.data(), jk.size() * 4, hipMemcpyHostToDevice), "write pairs");
+    HIP_TRY(launch_pair_dE_sh(c->cfg.precision, c->ptrs(), c->sh, copy, mu, n, d_jk, d_nw, d_dE, c->stream), "pair launch");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY(hipMemcpy(dE, d_dE, (size_t)n * 8, hipMemcpyDeviceToHost), "read dE");
+    return RLPT_OK;
+}
+
+int rlpt_observables(rlpt_ctx* c, rlpt_obs* o) {
+    if (!c || !o) return fail(RLPT_E_ARG, "NULL argument");
+    int rc = sync_and_flags(c);
+    const bool f64 = c->cfg.precision == RLPT_FP64;
+    const int ST = c->S * c->T, T1 = std::max(c->T - 1, 1);
+    std::vector<double> obs((size_t)kNumObs * ST);
+    HIP_TRY(hipMemcpy(obs.data(), f64 ? c->pd.obs : c->pf.obs, obs.size() * 8, hipMemcpyDeviceToHost), "read obs");
+    double* dst[kNumObs] = {o->e_n, o->e_sum, o->e_sq, o->y2_sum, o->y4_sum, o->q_n, o->q_sum, o->q_sq, o->q_4};
+    for (int f = 0; f < kNumObs; ++f)
+        if (dst[f]) std::copy(obs.begin() + (size_t)f * ST, obs.begin() + (size_t)(f + 1) * ST, dst[f]);
+    if (o->hist)
+        HIP_TRY(hipMemcpy(o->hist, f64 ? c->pd.hist : c->pf.hist, (size_t)ST * c->cfg.n_bins * 8, hipMemcpyDeviceToHost),
+                "read hist");
+    if (c->cfg.series_len > 0) {
+        if (o->series_e)
+            HIP_TRY(hipMemcpy(o->series_e, f64 ? c->pd.series_e : c->pf.series_e, (size_t)ST * c->cfg.series_len * 8,
+                              hipMemcpyDeviceToHost), "read series");
+        if (o->series_q)
+            HIP_TRY(hipMemcpy(o->series_q, f64 ? c->pd.series_q : c->pf.series_q, (size_t)ST * c->cfg.series_len * 8,
+                              hipMemcpyDeviceToHost), "read series");
+    }
+    if (o->acc || o->tries) {
+        std::vector<unsigned long long> a(ST);
+        HIP_TRY(hipMemcpy(a.data(), f64 ? c->pd.acc : c->pf.acc, ST * 8, hipMemcpyDeviceToHost), "read acc");
+        for (int i = 0; i < ST; ++i) {
+            if (o->acc) o->acc[i] = (double)a[i];
+            if (o->tries) o->tries[i] = (double)c->reps * (double)(c->N[i / c->T] / 2) * (double)c->sweeps_done;
+        }
+    }
+    if (o->swap_acc || o->swap_tries) {
+        std::vector<unsigned long long> a((size_t)c->S * c->reps * T1);
+        HIP_TRY(hipMemcpy(a.data(), f64 ? c->pd.swap_acc : c->pf.swap_acc, a.size() * 8, hipMemcpyDeviceToHost),
+                "read swap acc");
+        for (int s = 0; s < c->S; ++s)
+            for (int i = 0; i < T1; ++i) {
+                double sum = 0;
+                for (int r = 0; r < c->reps; ++r) sum += (double)a[((size_t)s * c->reps + r) * T1 + i];
+                if (o->swap_acc) o->swap_acc[(size_t)s * T1 + i] = sum;
+                if (o->swap_tries) o->swap_tries[(size_t)s * T1 + i] = c->T > 1 ? (double)c->reps * c->swaps_done : 0.0;
+            }
+    }
+    return rc;
+}
+
+int rlpt_tau_int(const double* x, int64_t n, double c_window, double* tau, int64_t* window) {
+    if (!x || !tau || n < 2) return fail(RLPT_E_ARG, "need a series of at least 2 points");
+    if (!(c_window > 0)) return fail(RLPT_E_ARG, "c_window must be > 0");
+    double mean = 0;
+    for (int64_t i = 0; i < n; ++i) mean += x[i];
+    mean /= (double)n;
+    double c0 = 0;
+    for (int64_t i = 0; i < n; ++i) c0 += (x[i] - mean) * (x[i] - mean);
+    c0 /= (double)n;
+    if (!(c0 > 0)) {
+        *tau = 0.5;
+        if (window) *window = 0;
+        return RLPT_OK;
+    }
+    double t = 0.5;
+    int64_t W = 0;
+    for (int64_t lag = 1; lag < n; ++lag) {
+        double ct = 0;
+        for (int64_t i = 0; i + lag < n; ++i) ct += (x[i] - mean) * (x[i + lag] - mean);
+        ct /= (double)n;
+        t += ct / c0;
+        W = lag;
+        if ((double)lag >= c_window * t) break;
+    }
+    *tau = t;
+    if (window) *window = W;
+    return RLPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal types shared by the host runtime (api.cpp, graph.cpp) and the
+// device kernels (kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rlpt.h"
+
+// ----------------------------------------------------------------- host graph
+struct rlpt_graph {
+    int32_t N = 0;
+    uint64_t seed = 0;
+    double gamma = 0.0;
+    double sigma2 = 0.0;
+    std::vector<double> omega;         // [N] sorted frequencies
+    std::vector<int16_t> quads;        // [c][4] (p, s, m, n)
+    std::vector<double> J;             // [c]
+    // per-mode lists: entries of mode l are [mode_start[l], mode_start[l+1]),
+    // padded to a multiple of 4; entry = (x, y, z) packed 10 bits each, coupling
+    std::vector<uint32_t> mode_start;  // [N+1]
+    std::vector<uint32_t> idx;         // packed x | y << 10 | z << 20
+    std::vector<double> Jl;            // coupling of each entry (0 for padding)
+    int64_t n_terms() const { return (int64_t)J.size(); }
+};
+
+namespace rlpt {
+
+constexpr int kMaxModes = 1024;  // three 10-bit mode indices per packed entry
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+// ----------------------------------------------------------------- device-side descriptors
+struct SampleDev {
+    int32_t N;
+    int32_t n_steps;       // two-mode updates per sweep, N / 2
+    uint32_t mode_base;    // offset of this sample's mode_start block (N + 1 values)
+    uint32_t pad0;
+    int64_t amp_base;      // complex offset of the sample's first copy
+    int64_t quad_base;     // offset into the by-term arrays
+    int64_t n_quads;
+};
+
+// a unit of work of the sweep kernel: n_copies consecutive copies of one sample
+struct ItemDev {
+    int32_t first_copy;
+    int32_t n_copies;
+    int32_t sample;
+    int32_t pad;
+};
+
+struct Counters {
+    int64_t sweeps_done;
+    int64_t swaps_done;
+    int32_t error_flags;  // bit0: drift above tolerance, bit1: NaN/Inf
+    int32_t pad;
+};
+
+// pointers into the caller's workspace
+template <typename R>
+struct DevPtrs {
+    const SampleDev* samples;
+    const ItemDev* items;
+    const uint32_t* mode_start;
+    const uint32_t* idx;
+    const R* J;               // per-mode entries, context precision
+    const ushort4* quads;     // by term (p, s, m, n)
+    const double* Jq;         // by term, FP64
+    R* amp;                   // interleaved complex [copy][N]
+    R* E;                     // running energies
+    double* E64;              // last FP64 energies
+    double* drift;            // per-copy relative drift at the last recomputation
+    int32_t* temp_of;         // [copies]
+    int32_t* copy_at;         // [S][reps][T]
+    const R* beta;            // [T]
+    const double* beta64;     // [T]
+    unsigned long long* acc;  // [S][T]
+    unsigned long long* swap_acc;  // [S][reps][T-1]
+    double* obs;              // accumulators, see ObsLayout
+    double* series_e;
+    double* series_q;
+    double* hist;
+    int32_t* meas_cnt;        // [S][T]
+    Counters* counters;
+};
+
+// offsets (in doubles) of the [S][T] accumulator blocks inside DevPtrs::obs
+enum ObsField { kEN = 0, kESum, kESq, kY2, kY4, kQN, kQSum, kQSq, kQ4, kNumObs };
+
+struct ShapeInfo {
+    int32_t n_samples;
+    int32_t n_temps;
+    int32_t n_reps;
+    int32_t copies_per_sample;  // R = n_temps * n_reps
+    int32_t n_bins;
+    int32_t series_len;
+    int32_t shared_pairs;
+    int32_t pad;
+    uint64_t run_seed;
+    double renorm_tol;
+    double drift_tol;
+};
+
+// ----------------------------------------------------------------- launchers (kernels.hip)
+struct SweepLaunch {
+    int block_threads;
+    int n_items;
+    int max_copies_per_item;
+    int max_N;
+    size_t lds_bytes;
+};
+
+size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N);
+
+hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int block,
+                       hipStream_t st);
+hipError_t launch_sweep(int precision, const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L,
+                        int n_sweeps, hipStream_t st);
+hipError_t launch_swap(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st);
+hipError_t launch_tick(const void* ptrs_any, int precision, int64_t d_sweeps, int64_t d_swaps,
+                       hipStream_t st);
+// mode 0: periodic recomputation (drift check, renormalisation, store E);
+// mode 1: FP64 energies into E64 only; mode 2: store E = H without checks
+hipError_t launch_resync(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int mode,
+                         hipStream_t st);
+hipError_t launch_measure(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_fields_sh(int precision, const void* ptrs, const ShapeInfo& sh, int copy, int sample,
+                            double* F_dev, hipStream_t st);
+hipError_t launch_pair_dE_sh(int precision, const void* ptrs, const ShapeInfo& sh, int copy, int sample, int n,
+                             const int32_t* jk_dev, const double* new_dev, double* dE_dev, hipStream_t st);
+hipError_t launch_convert_state(int precision, void* amp_ctx, double* buf, int64_t n_complex, int to_ctx,
+                                hipStream_t st);
+
+}  // namespace rlpt

@@ -1,0 +1,729 @@
+// Device kernels of librlpt for CDNA4 (gfx950): initial draw, the sweep
+// (local fields + two-mode Metropolis update), replica exchange, FP64 energy
+// recomputation, observables, and the test hooks that reuse the sweep's field
+// code.  Method: Benedetti & Leuzzi, arXiv 2511.13508, sec. III.A.
+//
+// Sweep kernel layout
+//   * one workgroup runs an "item": n_copies copies of one disorder sample;
+//     each copy is served by waves_per_copy = (block/64)/n_copies waves;
+//   * a copy's amplitudes live in LDS for the whole launch;
+//   * the per-mode lists (packed x|y<<10|z<<20 and J) stream from HBM with
+//     16-byte loads, 4 entries per lane per load, coalesced across the wave;
+//   * the state-independent parts of each step (pair, phases, sqrt(cos),
+//     sqrt(sin), acceptance uniform) are drawn in parallel at the start of a
+//     sweep into LDS tables;
+//   * per step: barrier, both fields over the two lists on one snapshot
+//     (a_j already replaced by its proposal), wave reduction by shuffles,
+//     cross-wave sum in LDS, barrier, then one lane decides, updates LDS and
+//     prepares the next step's snapshot.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace rlpt {
+namespace {
+
+template <typename R>
+struct V2;
+template <>
+struct V2<float> {
+    using T = float2;
+};
+template <>
+struct V2<double> {
+    using T = double2;
+};
+template <typename R>
+using R2 = typename V2<R>::T;
+
+template <typename R>
+__device__ inline R2<R> mk2(R x, R y) {
+    R2<R> v;
+    v.x = x;
+    v.y = y;
+    return v;
+}
+
+template <typename R>
+__device__ inline R pi_v() {
+    return (R)3.14159265358979323846;
+}
+
+__device__ inline void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ inline void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename R>
+__device__ inline R wave_sum(R v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// contribution J conj(a_x) a_y a_z of one packed entry
+template <typename R>
+__device__ inline void field_term(uint32_t e, R j, const R2<R>* __restrict__ a, R& fr, R& fi) {
+    const R2<R> ax = a[e & 1023u];
+    const R2<R> ay = a[(e >> 10) & 1023u];
+    const R2<R> az = a[e >> 20];
+    const R pr = ax.x * ay.x + ax.y * ay.y;
+    const R pi = ax.x * ay.y - ax.y * ay.x;
+    const R qr = pr * az.x - pi * az.y;
+    const R qi = pr * az.y + pi * az.x;
+    fr += j * qr;
+    fi += j * qi;
+}
+
+template <typename R>
+struct J4;
+template <>
+struct J4<float> {
+    using T = float4;
+};
+template <>
+struct J4<double> {
+    using T = double4;
+};
+
+// partial field of one mode's list, entries [beg, end) (multiples of 4),
+// thread t of nt threads takes every nt-th group of 4 entries
+template <typename R>
+__device__ inline void field_partial(const uint32_t* __restrict__ idx, const R* __restrict__ J, uint32_t beg,
+                                     uint32_t end, const R2<R>* __restrict__ a, int t, int nt, R& fr, R& fi) {
+    using JT = typename J4<R>::T;
+    const uint4* __restrict__ I4 = reinterpret_cast<const uint4*>(idx + beg);
+    const JT* __restrict__ Jv = reinterpret_cast<const JT*>(J + beg);
+    const int n4 = (int)((end - beg) >> 2);
+    int e = t;
+    for (; e + nt < n4; e += 2 * nt) {
+        const uint4 i0 = I4[e];
+        const JT j0 = Jv[e];
+        const uint4 i1 = I4[e + nt];
+        const JT j1 = Jv[e + nt];
+        field_term<R>(i0.x, j0.x, a, fr, fi);
+        field_term<R>(i0.y, j0.y, a, fr, fi);
+        field_term<R>(i0.z, j0.z, a, fr, fi);
+        field_term<R>(i0.w, j0.w, a, fr, fi);
+        field_term<R>(i1.x, j1.x, a, fr, fi);
+        field_term<R>(i1.y, j1.y, a, fr, fi);
+        field_term<R>(i1.z, j1.z, a, fr, fi);
+        field_term<R>(i1.w, j1.w, a, fr, fi);
+    }
+    if (e < n4) {
+        const uint4 i0 = I4[e];
+        const JT j0 = Jv[e];
+        field_term<R>(i0.x, j0.x, a, fr, fi);
+        field_term<R>(i0.y, j0.y, a, fr, fi);
+        field_term<R>(i0.z, j0.z, a, fr, fi);
+        field_term<R>(i0.w, j0.w, a, fr, fi);
+    }
+}
+
+// energy change of the two-mode update from the two fields of one snapshot:
+// dE = -2 Re(conj(aj_new - aj_old) F_j) - 2 Re(conj(ak_new - ak_old) F_k)
+template <typename R>
+__device__ inline R pair_delta(R2<R> ajo, R2<R> ajn, R2<R> ako, R2<R> akn, R2<R> Fj, R2<R> Fk) {
+    const R djr = ajn.x - ajo.x, dji = ajn.y - ajo.y;
+    const R dkr = akn.x - ako.x, dki = akn.y - ako.y;
+    return (R)-2 * (djr * Fj.x + dji * Fj.y) - (R)2 * (dkr * Fk.x + dki * Fk.y);
+}
+
+// state-independent part of step s of sweep w for one copy (sec. III.A):
+// distinct j, k; unit phasors of the new phases; sqrt(cos theta), sqrt(sin theta);
+// acceptance uniform
+template <typename R>
+struct StepDraw {
+    int32_t jk;  // j | k << 16
+    R ejr, eji, ekr, eki, cj, sk, u;
+};
+
+template <typename R>
+__device__ inline StepDraw<R> draw_step(uint64_t seed, int64_t pair_stream, int64_t copy_id, int64_t sweep,
+                                        int step, int N) {
+    const Philox4 wp = philox4x64((uint64_t)step, (uint64_t)sweep, (uint64_t)pair_stream, 0, seed, kTagPair);
+    const Philox4 wm = philox4x64((uint64_t)step, (uint64_t)sweep, (uint64_t)copy_id, 0, seed, kTagMove);
+    const int j = index_below(wp.v[0], N);
+    int k = index_below(wp.v[1], N - 1);
+    k += (k >= j) ? 1 : 0;
+    StepDraw<R> d;
+    d.jk = j | (k << 16);
+    const R two_pi = (R)2 * pi_v<R>();
+    R s, c;
+    sincos_r(two_pi * uniform01<R>(wm.v[0]), &s, &c);
+    d.ejr = c;
+    d.eji = s;
+    sincos_r(two_pi * uniform01<R>(wm.v[1]), &s, &c);
+    d.ekr = c;
+    d.eki = s;
+    sincos_r((R)0.5 * pi_v<R>() * uniform01<R>(wm.v[2]), &s, &c);
+    d.cj = sqrt(c > (R)0 ? c : (R)0);
+    d.sk = sqrt(s > (R)0 ? s : (R)0);
+    d.u = uniform01<R>(wm.v[3]);
+    return d;
+}
+
+// LDS bytes of one copy group: amplitudes of max_N modes + step tables + reduction slots
+template <typename R>
+__host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
+    const size_t amp = (size_t)max_N * 2 * sizeof(R);
+    const size_t tab = (size_t)(max_N / 2 + 1) * sizeof(StepDraw<R>);
+    const size_t red = (size_t)waves_per_block * 4 * sizeof(R);
+    return (amp + tab + red + 15) & ~(size_t)15;
+}
+
+template <typename R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kWaves = BLOCK / 64;
+    const ItemDev it = P.items[blockIdx.x];
+    const SampleDev sd = P.samples[it.sample];
+    const int N = sd.N, steps = sd.n_steps;
+    const int wpc = kWaves / it.n_copies;  // waves per copy
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = wave / wpc;              // copy group of this wave
+    const bool active = g < it.n_copies;
+    const int gw = wave - g * wpc;         // wave index inside the group
+    const int gt = threadIdx.x - g * wpc * 64;
+    const int nt = wpc * 64;
+    const int gsel = active ? g : 0;
+
+    unsigned char* base = smem + (size_t)gsel * group_bytes<R>(max_N, kWaves);
+    R2<R>* a = reinterpret_cast<R2<R>*>(base);
+    StepDraw<R>* tab = reinterpret_cast<StepDraw<R>*>(base + (size_t)max_N * 2 * sizeof(R));
+    R* red = reinterpret_cast<R*>(base + (size_t)max_N * 2 * sizeof(R) + (size_t)(max_N / 2 + 1) * sizeof(StepDraw<R>));
+
+    const int c = it.first_copy + gsel;
+    const int64_t local = c - (int64_t)it.sample * sh.copies_per_sample;
+    R2<R>* amp_g = reinterpret_cast<R2<R>*>(P.amp) + sd.amp_base + local * N;
+    if (active)
+        for (int i = gt; i < N; i += nt) a[i] = amp_g[i];
+    const int t_idx = P.temp_of[c];
+    const R beta = P.beta[t_idx];
+    R E = P.E[c];
+    unsigned int n_acc = 0;
+    const int64_t pair_stream = sh.shared_pairs ? (int64_t)it.sample : (int64_t)c;
+    const int64_t sweep0 = P.counters->sweeps_done;
+    const uint32_t* ms = P.mode_start + sd.mode_base;
+
+    R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        __syncthreads();
+        if (active)
+            for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N);
+        __syncthreads();
+        if (active && gt == 0) {  // snapshot of step 0
+            const int j = tab[0].jk & 0xffff, k = tab[0].jk >> 16;
+            ajo = a[j];
+            const R2<R> ako = a[k];
+            const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako.x * ako.x + ako.y * ako.y;
+            const R K = sqrt(sqrt(uj * uj + uk * uk));
+            ajn = mk2<R>(K * tab[0].cj * tab[0].ejr, K * tab[0].cj * tab[0].eji);
+            akn = mk2<R>(K * tab[0].sk * tab[0].ekr, K * tab[0].sk * tab[0].eki);
+            a[j] = ajn;
+        }
+        for (int s = 0; s < steps; ++s) {
+            __syncthreads();
+            R fjr = 0, fji = 0, fkr = 0, fki = 0;
+            if (active) {
+                const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
+                field_partial<R>(P.idx, P.J, ms[j], ms[j + 1], a, gt, nt, fjr, fji);
+                field_partial<R>(P.idx, P.J, ms[k], ms[k + 1], a, gt, nt, fkr, fki);
+            }
+            fjr = wave_sum(fjr);
+            fji = wave_sum(fji);
+            fkr = wave_sum(fkr);
+            fki = wave_sum(fki);
+            if (active && lane == 0) {
+                red[4 * gw + 0] = fjr;
+                red[4 * gw + 1] = fji;
+                red[4 * gw + 2] = fkr;
+                red[4 * gw + 3] = fki;
+            }
+            __syncthreads();
+            if (active && gt == 0) {
+                R2<R> Fj = mk2<R>(0, 0), Fk = mk2<R>(0, 0);
+                for (int w = 0; w < wpc; ++w) {
+                    Fj.x += red[4 * w + 0];
+                    Fj.y += red[4 * w + 1];
+                    Fk.x += red[4 * w + 2];
+                    Fk.y += red[4 * w + 3];
+                }
+                const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
+                const R2<R> ako = a[k];
+                const R dE = pair_delta<R>(ajo, ajn, ako, akn, Fj, Fk);
+                const bool accept = (dE <= (R)0) || (tab[s].u < exp(-beta * dE));
+                if (accept) {
+                    a[k] = akn;
+                    E += dE;
+                    ++n_acc;
+                } else {
+                    a[j] = ajo;
+                }
+                if (s + 1 < steps) {  // snapshot of the next step
+                    const StepDraw<R> d = tab[s + 1];
+                    const int j2 = d.jk & 0xffff, k2 = d.jk >> 16;
+                    ajo = a[j2];
+                    const R2<R> ako2 = a[k2];
+                    const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
+                    const R K = sqrt(sqrt(uj * uj + uk * uk));
+                    ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
+                    akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
+                    a[j2] = ajn;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        for (int i = gt; i < N; i += nt) amp_g[i] = a[i];
+        if (gt == 0) {
+            P.E[c] = E;
+            atomicAdd(&P.acc[(size_t)it.sample * sh.n_temps + t_idx], (unsigned long long)n_acc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- initial draw
+// one block per copy; exact draw from the infinite-temperature law on
+// sum |a|^4 = N: |a_k|^2 = sqrt(N) |g_k| / ||g||, phases uniform
+template <typename R>
+__global__ __launch_bounds__(256) void k_init(DevPtrs<R> P, ShapeInfo sh) {
+    __shared__ double red[4];
+    const int c = blockIdx.x;
+    const int mu = c / sh.copies_per_sample;
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
+    R* amp = P.amp + 2 * (sd.amp_base + local * N);
+    double part = 0.0;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const Philox4 w = philox4x64((uint64_t)k, (uint64_t)c, 0, 0, sh.run_seed, kTagInit);
+        const double u1 = 1.0 - uniform01<double>(w.v[0]), u2 = uniform01<double>(w.v[1]);
+        const double gk = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+        part += gk * gk;
+    }
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    const double norm2 = red[0] + red[1] + red[2] + red[3];
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const Philox4 w = philox4x64((uint64_t)k, (uint64_t)c, 0, 0, sh.run_seed, kTagInit);
+        const double u1 = 1.0 - uniform01<double>(w.v[0]), u2 = uniform01<double>(w.v[1]);
+        const double gk = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+        const double ph = 2.0 * 3.14159265358979323846 * uniform01<double>(w.v[2]);
+        const double u = sqrt((double)N) * fabs(gk) / sqrt(norm2);
+        const double A = sqrt(u);
+        amp[2 * k] = (R)(A * cos(ph));
+        amp[2 * k + 1] = (R)(A * sin(ph));
+    }
+    if (threadIdx.x == 0) {
+        P.temp_of[c] = (int32_t)(local % sh.n_temps);
+        const int r = (int)(local / sh.n_temps);
+        P.copy_at[((size_t)mu * sh.n_reps + r) * sh.n_temps + local % sh.n_temps] = c;
+    }
+}
+
+// ---------------------------------------------------------------- FP64 recomputation
+// one block per copy: H = -2 sum_q J_q Re(conj a_p conj a_s a_m a_n) and
+// S = sum |a|^4 in FP64.  mode 0: drift check, renormalise when
+// |S/N - 1| > renorm_tol (H scales by N/S), store E; mode 1: E64 only.
+template <typename R>
+__global__ __launch_bounds__(256) void k_resync(DevPtrs<R> P, ShapeInfo sh, int mode) {
+    __shared__ double2 a[kMaxModes];
+    __shared__ double red[2][4];
+    __shared__ double bc[2];
+    const int c = blockIdx.x;
+    const int mu = c / sh.copies_per_sample;
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
+    R* amp = P.amp + 2 * (sd.amp_base + local * N);
+    double s4 = 0.0;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const double x = (double)amp[2 * k], y = (double)amp[2 * k + 1];
+        a[k] = make_double2(x, y);
+        const double u = x * x + y * y;
+        s4 += u * u;
+    }
+    __syncthreads();
+    double H = 0.0;
+    const ushort4* Q = P.quads + sd.quad_base;
+    const double* Jq = P.Jq + sd.quad_base;
+    for (int64_t q = threadIdx.x; q < sd.n_quads; q += blockDim.x) {
+        const ushort4 t = Q[q];
+        const double2 p = a[t.x], s = a[t.y], m = a[t.z], n = a[t.w];
+        // conj(p) conj(s) = (p.x s.x - p.y s.y, -(p.x s.y + p.y s.x))
+        const double cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
+        const double dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
+        H += -2.0 * Jq[q] * (cr * dr - ci * di);
+    }
+    H = wave_sum(H);
+    s4 = wave_sum(s4);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = H;
+        red[1][threadIdx.x >> 6] = s4;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double Ht = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        const double St = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        double f = 1.0;
+        if (mode == 2) P.E[c] = (R)Ht;
+        if (mode == 0) {
+            const double Er = (double)P.E[c];
+            const double scale = fabs(Ht) > 1.0 ? fabs(Ht) : 1.0;
+            const double d = fabs(Er - Ht) / scale;
+            P.drift[c] = d;
+            if (!isfinite(Ht) || !isfinite(St) || !isfinite(Er)) atomicOr(&P.counters->error_flags, 2);
+            else if (sh.drift_tol > 0.0 && d > sh.drift_tol) atomicOr(&P.counters->error_flags, 1);
+            if (fabs(St / (double)N - 1.0) > sh.renorm_tol && St > 0.0) {
+                f = pow((double)N / St, 0.25);
+                Ht *= (double)N / St;
+            }
+            P.E[c] = (R)Ht;
+        }
+        P.E64[c] = Ht;
+        bc[0] = f;
+    }
+    __syncthreads();
+    if (mode == 0 && bc[0] != 1.0) {
+        const double f = bc[0];
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            amp[2 * k] = (R)(a[k].x * f);
+            amp[2 * k + 1] = (R)(a[k].y * f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- replica exchange
+// one thread per ladder (sample, replica): neighbouring baths in ascending
+// order, accepted with min[1, exp((b_i - b_{i+1})(E_i - E_{i+1}))]
+template <typename R>
+__global__ void k_swap(DevPtrs<R> P, ShapeInfo sh) {
+    const int L = blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= sh.n_samples * sh.n_reps) return;
+    const int T = sh.n_temps;
+    int32_t* at = P.copy_at + (size_t)L * T;
+    const int64_t round = P.counters->swaps_done;
+    for (int i = 0; i + 1 < T; ++i) {
+        const Philox4 w = philox4x64((uint64_t)i, (uint64_t)round, (uint64_t)L, 0, sh.run_seed, kTagSwap);
+        const int ci = at[i], cj = at[i + 1];
+        const double x = (P.beta64[i] - P.beta64[i + 1]) * ((double)P.E[ci] - (double)P.E[cj]);
+        const bool accept = (x >= 0.0) || (uniform01<double>(w.v[0]) < exp(x));
+        if (accept) {
+            at[i] = cj;
+            at[i + 1] = ci;
+            P.temp_of[ci] = i + 1;
+            P.temp_of[cj] = i;
+            P.swap_acc[(size_t)L * (T - 1) + i] += 1ull;
+        }
+    }
+}
+
+__global__ void k_tick(Counters* cnt, int64_t d_sweeps, int64_t d_swaps) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt->sweeps_done += d_sweeps;
+        cnt->swaps_done += d_swaps;
+    }
+}
+
+__global__ void k_zero(uint32_t* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- observables
+// one block of 64 threads per (sample, bath): energy moments, IPR Y_2 and Y_4
+// of every replica, overlap of every replica pair and its histogram
+template <typename R>
+__global__ __launch_bounds__(64) void k_measure(DevPtrs<R> P, ShapeInfo sh) {
+    const int st = blockIdx.x;  // sample * T + t
+    const int mu = st / sh.n_temps, t = st % sh.n_temps;
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int lane = threadIdx.x;
+    const int S_T = sh.n_samples * sh.n_temps;
+    const int m = P.meas_cnt[st];
+    double eS = 0, eQ = 0, y2S = 0, y4S = 0, e0 = 0;
+    for (int r = 0; r < sh.n_reps; ++r) {
+        const int c = P.copy_at[((size_t)mu * sh.n_reps + r) * sh.n_temps + t];
+        const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
+        const R* a = P.amp + 2 * (sd.amp_base + local * N);
+        double s1 = 0, s2 = 0, s4 = 0;
+        for (int k = lane; k < N; k += 64) {
+            const double x = a[2 * k], y = a[2 * k + 1];
+            const double I = x * x + y * y;
+            s1 += I;
+            s2 += I * I;
+            s4 += (I * I) * (I * I);
+        }
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        s4 = wave_sum(s4);
+        const double E = (double)P.E[c];
+        if (r == 0) e0 = E;
+        eS += E;
+        eQ += E * E;
+        y2S += s2 / (s1 * s1);
+        y4S += s4 / (s2 * s2);
+    }
+    double qS = 0, qQ = 0, q4 = 0, qn = 0, q01 = 0;
+    for (int r = 0; r < sh.n_reps; ++r)
+        for (int r2 = r + 1; r2 < sh.n_reps; ++r2) {
+            const int c1 = P.copy_at[((size_t)mu * sh.n_reps + r) * sh.n_temps + t];
+            const int c2 = P.copy_at[((size_t)mu * sh.n_reps + r2) * sh.n_temps + t];
+            const R* x = P.amp + 2 * (sd.amp_base + (c1 - (int64_t)mu * sh.copies_per_sample) * N);
+            const R* y = P.amp + 2 * (sd.amp_base + (c2 - (int64_t)mu * sh.copies_per_sample) * N);
+            double q = 0;
+            for (int k = lane; k < N; k += 64) q += (double)x[2 * k] * y[2 * k] + (double)x[2 * k + 1] * y[2 * k + 1];
+            q = wave_sum(q) / (double)N;
+            qS += q;
+            qQ += q * q;
+            q4 += (q * q) * (q * q);
+            qn += 1.0;
+            if (r == 0 && r2 == 1) q01 = q;
+            if (lane == 0) {
+                int b = (int)floor((q + 1.0) * 0.5 * sh.n_bins);
+                b = b < 0 ? 0 : (b >= sh.n_bins ? sh.n_bins - 1 : b);
+                P.hist[(size_t)st * sh.n_bins + b] += 1.0;
+            }
+        }
+    if (lane == 0) {
+        double* o = P.obs;
+        o[kEN * S_T + st] += (double)sh.n_reps;
+        o[kESum * S_T + st] += eS;
+        o[kESq * S_T + st] += eQ;
+        o[kY2 * S_T + st] += y2S;
+        o[kY4 * S_T + st] += y4S;
+        o[kQN * S_T + st] += qn;
+        o[kQSum * S_T + st] += qS;
+        o[kQSq * S_T + st] += qQ;
+        o[kQ4 * S_T + st] += q4;
+        if (m < sh.series_len) {
+            P.series_e[(size_t)st * sh.series_len + m] = e0;
+            if (sh.n_reps > 1) P.series_q[(size_t)st * sh.series_len + m] = q01;
+        }
+        P.meas_cnt[st] = m + 1;
+    }
+}
+
+// ---------------------------------------------------------------- test hooks
+// all N local fields of one copy with the sweep's field code (one block)
+template <typename R>
+__global__ __launch_bounds__(256) void k_fields(DevPtrs<R> P, ShapeInfo sh, int copy, int mu, double* F) {
+    __shared__ R2<R> a[kMaxModes];
+    __shared__ R red[4][2];
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int64_t local = copy - (int64_t)mu * sh.copies_per_sample;
+    const R2<R>* amp = reinterpret_cast<const R2<R>*>(P.amp) + sd.amp_base + local * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = amp[i];
+    __syncthreads();
+    const uint32_t* ms = P.mode_start + sd.mode_base;
+    for (int l = 0; l < N; ++l) {
+        R fr = 0, fi = 0;
+        field_partial<R>(P.idx, P.J, ms[l], ms[l + 1], a, threadIdx.x, blockDim.x, fr, fi);
+        fr = wave_sum(fr);
+        fi = wave_sum(fi);
+        if ((threadIdx.x & 63) == 0) {
+            red[threadIdx.x >> 6][0] = fr;
+            red[threadIdx.x >> 6][1] = fi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            R sr = 0, si = 0;
+            for (int w = 0; w < 4; ++w) {
+                sr += red[w][0];
+                si += red[w][1];
+            }
+            F[2 * l] = (double)sr;
+            F[2 * l + 1] = (double)si;
+        }
+        __syncthreads();
+    }
+}
+
+// pair energy changes on given proposals, with the sweep's snapshot rule
+template <typename R>
+__global__ __launch_bounds__(256) void k_pair_dE(DevPtrs<R> P, ShapeInfo sh, int copy, int mu, int n,
+                                                 const int32_t* jk, const double* nw, double* dE) {
+    __shared__ R2<R> a[kMaxModes];
+    __shared__ R red[4][4];
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int64_t local = copy - (int64_t)mu * sh.copies_per_sample;
+    const R2<R>* amp = reinterpret_cast<const R2<R>*>(P.amp) + sd.amp_base + local * N;
+    const uint32_t* ms = P.mode_start + sd.mode_base;
+    for (int p = 0; p < n; ++p) {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = amp[i];
+        __syncthreads();
+        const int j = jk[2 * p], k = jk[2 * p + 1];
+        const R2<R> ajo = amp[j], ako = amp[k];
+        const R2<R> ajn = mk2<R>((R)nw[4 * p], (R)nw[4 * p + 1]);
+        const R2<R> akn = mk2<R>((R)nw[4 * p + 2], (R)nw[4 * p + 3]);
+        if (threadIdx.x == 0) a[j] = ajn;
+        __syncthreads();
+        R fjr = 0, fji = 0, fkr = 0, fki = 0;
+        field_partial<R>(P.idx, P.J, ms[j], ms[j + 1], a, threadIdx.x, blockDim.x, fjr, fji);
+        field_partial<R>(P.idx, P.J, ms[k], ms[k + 1], a, threadIdx.x, blockDim.x, fkr, fki);
+        fjr = wave_sum(fjr);
+        fji = wave_sum(fji);
+        fkr = wave_sum(fkr);
+        fki = wave_sum(fki);
+        if ((threadIdx.x & 63) == 0) {
+            red[threadIdx.x >> 6][0] = fjr;
+            red[threadIdx.x >> 6][1] = fji;
+            red[threadIdx.x >> 6][2] = fkr;
+            red[threadIdx.x >> 6][3] = fki;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            R2<R> Fj = mk2<R>(0, 0), Fk = mk2<R>(0, 0);
+            for (int w = 0; w < 4; ++w) {
+                Fj.x += red[w][0];
+                Fj.y += red[w][1];
+                Fk.x += red[w][2];
+                Fk.y += red[w][3];
+            }
+            dE[p] = (double)pair_delta<R>(ajo, ajn, ako, akn, Fj, Fk);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void k_convert(R* amp, double* buf, int64_t n, int to_ctx) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (to_ctx) amp[i] = (R)buf[i];
+        else buf[i] = (double)amp[i];
+    }
+}
+
+template <typename R, int BLOCK>
+hipError_t launch_sweep_t(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,
+                          hipStream_t st) {
+    const DevPtrs<R>& P = *static_cast<const DevPtrs<R>*>(ptrs);
+    hipLaunchKernelGGL((k_sweep<R, BLOCK>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh, L.max_N, n_sweeps);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_sweep_r(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,
+                          hipStream_t st) {
+    switch (L.block_threads) {
+        case 64: return launch_sweep_t<R, 64>(ptrs, sh, L, n_sweeps, st);
+        case 128: return launch_sweep_t<R, 128>(ptrs, sh, L, n_sweeps, st);
+        case 256: return launch_sweep_t<R, 256>(ptrs, sh, L, n_sweeps, st);
+        case 512: return launch_sweep_t<R, 512>(ptrs, sh, L, n_sweeps, st);
+        case 1024: return launch_sweep_t<R, 1024>(ptrs, sh, L, n_sweeps, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N) {
+    const int waves = block_threads / 64;
+    return (size_t)max_copies_per_item *
+           (precision == RLPT_FP64 ? group_bytes<double>(max_N, waves) : group_bytes<float>(max_N, waves));
+}
+
+hipError_t launch_sweep(int precision, const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,
+                        hipStream_t st) {
+    return precision == RLPT_FP64 ? launch_sweep_r<double>(ptrs, sh, L, n_sweeps, st)
+                                  : launch_sweep_r<float>(ptrs, sh, L, n_sweeps, st);
+}
+
+template <typename R>
+static hipError_t init_t(const void* ptrs, const ShapeInfo& sh, int n_copies, hipStream_t st) {
+    hipLaunchKernelGGL(k_init<R>, dim3(n_copies), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh);
+    return hipGetLastError();
+}
+hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int, hipStream_t st) {
+    return precision == RLPT_FP64 ? init_t<double>(ptrs, sh, n_copies, st) : init_t<float>(ptrs, sh, n_copies, st);
+}
+
+template <typename R>
+static hipError_t swap_t(const void* ptrs, const ShapeInfo& sh, hipStream_t st) {
+    const int n = sh.n_samples * sh.n_reps;
+    hipLaunchKernelGGL(k_swap<R>, dim3((n + 63) / 64), dim3(64), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh);
+    return hipGetLastError();
+}
+hipError_t launch_swap(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st) {
+    return precision == RLPT_FP64 ? swap_t<double>(ptrs, sh, st) : swap_t<float>(ptrs, sh, st);
+}
+
+hipError_t launch_tick(const void* ptrs, int precision, int64_t d_sweeps, int64_t d_swaps, hipStream_t st) {
+    Counters* cnt = precision == RLPT_FP64 ? static_cast<const DevPtrs<double>*>(ptrs)->counters
+                                           : static_cast<const DevPtrs<float>*>(ptrs)->counters;
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, cnt, d_sweeps, d_swaps);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t resync_t(const void* ptrs, const ShapeInfo& sh, int n_copies, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_resync<R>, dim3(n_copies), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh, mode);
+    return hipGetLastError();
+}
+hipError_t launch_resync(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int mode, hipStream_t st) {
+    return precision == RLPT_FP64 ? resync_t<double>(ptrs, sh, n_copies, mode, st)
+                                  : resync_t<float>(ptrs, sh, n_copies, mode, st);
+}
+
+template <typename R>
+static hipError_t measure_t(const void* ptrs, const ShapeInfo& sh, hipStream_t st) {
+    hipLaunchKernelGGL(k_measure<R>, dim3(sh.n_samples * sh.n_temps), dim3(64), 0, st,
+                       *static_cast<const DevPtrs<R>*>(ptrs), sh);
+    return hipGetLastError();
+}
+hipError_t launch_measure(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st) {
+    return precision == RLPT_FP64 ? measure_t<double>(ptrs, sh, st) : measure_t<float>(ptrs, sh, st);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, static_cast<uint32_t*>(p), n);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t fields_t(const void* ptrs, int copy, int mu, double* F, hipStream_t st, const ShapeInfo& sh) {
+    hipLaunchKernelGGL(k_fields<R>, dim3(1), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, F);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t pair_t(const void* ptrs, int copy, int mu, int n, const int32_t* jk, const double* nw, double* dE,
+                         hipStream_t st, const ShapeInfo& sh) {
+    hipLaunchKernelGGL(k_pair_dE<R>, dim3(1), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, n,
+                       jk, nw, dE);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t convert_t(void* amp, double* buf, int64_t n, int to_ctx, hipStream_t st) {
+    int blocks = (int)((2 * n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_convert<R>, dim3(blocks), dim3(256), 0, st, static_cast<R*>(amp), buf, n, to_ctx);
+    return hipGetLastError();
+}
+hipError_t launch_convert_state(int precision, void* amp, double* buf, int64_t n, int to_ctx, hipStream_t st) {
+    return precision == RLPT_FP64 ? convert_t<double>(amp, buf, n, to_ctx, st) : convert_t<float>(amp, buf, n, to_ctx, st);
+}
+
+// the test hooks need the shape; they are launched through these two entry points
+hipError_t launch_fields_sh(int precision, const void* ptrs, const ShapeInfo& sh, int copy, int mu, double* F,
+                            hipStream_t st) {
+    return precision == RLPT_FP64 ? fields_t<double>(ptrs, copy, mu, F, st, sh) : fields_t<float>(ptrs, copy, mu, F, st, sh);
+}
+hipError_t launch_pair_dE_sh(int precision, const void* ptrs, const ShapeInfo& sh, int copy, int mu, int n,
+                             const int32_t* jk, const double* nw, double* dE, hipStream_t st) {
+    return precision == RLPT_FP64 ? pair_t<double>(ptrs, copy, mu, n, jk, nw, dE, st, sh)
+                                  : pair_t<float>(ptrs, copy, mu, n, jk, nw, dE, st, sh);
+}
+
+}  // namespace rlpt

@@ -1,0 +1,309 @@
+"""Python binding of librlpt (argument marshalling only).
+
+Every computation runs in librlpt.so: the host graph builder in C++ and the
+Monte Carlo path in HIP kernels for gfx950.  PyTorch provides the device
+workspace and the stream.  Names follow the C ABI in include/rlpt.h.
+Importing this module does not need a GPU; creating a context does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librlpt.so")
+
+RLPT_OK, RLPT_E_ARG, RLPT_E_NOMEM, RLPT_E_HIP, RLPT_E_STATE, RLPT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+OMEGA_RANDOM, OMEGA_COMB = 0, 1
+SPLIT_A, SPLIT_B, SPLIT_C, SPLIT_ALL = 1, 2, 4, 7
+FP32, FP64 = 0, 1
+
+# every symbol declared in include/rlpt.h
+EXPORTS = [
+    "rlpt_abi_version", "rlpt_last_error", "rlpt_graph_build", "rlpt_graph_free", "rlpt_graph_info_get",
+    "rlpt_graph_export", "rlpt_config_default", "rlpt_workspace_size", "rlpt_create", "rlpt_destroy",
+    "rlpt_init", "rlpt_sweep", "rlpt_swap", "rlpt_resync", "rlpt_check", "rlpt_run_graph", "rlpt_sweep_timing",
+    "rlpt_sweep_time_get", "rlpt_counters",
+    "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64", "rlpt_local_fields",
+    "rlpt_pair_dE", "rlpt_observables", "rlpt_tau_int",
+]
+
+
+class RlptError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librlpt error {code}: {msg}")
+        self.code = code
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("omega_kind", C.c_int32), ("seed", C.c_uint64),
+                ("split_mask", C.c_int32), ("pad", C.c_int32), ("gamma", C.c_double)]
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("pad", C.c_int32), ("n_terms", C.c_int64), ("deg_min", C.c_int64),
+                ("deg_max", C.c_int64), ("deg_sum", C.c_int64), ("gamma", C.c_double), ("sigma2", C.c_double),
+                ("list_entries", C.c_int64), ("list_bytes", C.c_int64)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_temps", C.c_int32), ("n_reps", C.c_int32), ("precision", C.c_int32),
+                ("shared_pairs", C.c_int32), ("swap_interval", C.c_int32), ("resync_interval", C.c_int32),
+                ("renorm_tol", C.c_double), ("drift_tol", C.c_double), ("measure_start", C.c_int32),
+                ("measure_interval", C.c_int32), ("n_bins", C.c_int32), ("series_len", C.c_int32),
+                ("block_threads", C.c_int32), ("copies_per_block", C.c_int32)]
+
+
+OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",
+              "swap_acc", "swap_tries", "series_e", "series_q"]
+
+
+class Obs(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in OBS_FIELDS]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load librlpt.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"librlpt.so not built at {LIB_PATH}; run `python -m paper_2511_13508_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    sig = {
+        "rlpt_abi_version": ([], C.c_int),
+        "rlpt_last_error": ([], C.c_char_p),
+        "rlpt_graph_build": ([P, P], C.c_int),
+        "rlpt_graph_free": ([P], None),
+        "rlpt_graph_info_get": ([P, P], C.c_int),
+        "rlpt_graph_export": ([P, P, P, P], C.c_int),
+        "rlpt_config_default": ([P], C.c_int),
+        "rlpt_workspace_size": ([P, P, i32, P], C.c_int),
+        "rlpt_create": ([P, P, i32, P, P, C.c_size_t, P, P], C.c_int),
+        "rlpt_destroy": ([P], C.c_int),
+        "rlpt_init": ([P, u64], C.c_int),
+        "rlpt_sweep": ([P, i32], C.c_int),
+        "rlpt_swap": ([P], C.c_int),
+        "rlpt_resync": ([P, P], C.c_int),
+        "rlpt_check": ([P], C.c_int),
+        "rlpt_run_graph": ([P, i32, i32], C.c_int),
+        "rlpt_sweep_timing": ([P, i32], C.c_int),
+        "rlpt_sweep_time_get": ([P, P, P], C.c_int),
+        "rlpt_counters": ([P, P, P, P], C.c_int),
+        "rlpt_get_state": ([P, i32, i32, P], C.c_int),
+        "rlpt_set_state": ([P, i32, i32, P], C.c_int),
+        "rlpt_get_energies": ([P, P, P], C.c_int),
+        "rlpt_energy_fp64": ([P, P], C.c_int),
+        "rlpt_local_fields": ([P, i32, P], C.c_int),
+        "rlpt_pair_dE": ([P, i32, i32, P, P, P, P, P], C.c_int),
+        "rlpt_observables": ([P, P], C.c_int),
+        "rlpt_tau_int": ([P, i64, d, P, P], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != RLPT_OK:
+        raise RlptError(rc, lib().rlpt_last_error().decode())
+
+
+def _ptr(x: np.ndarray):
+    return x.ctypes.data_as(C.c_void_p)
+
+
+def abi_version() -> int:
+    return lib().rlpt_abi_version()
+
+
+class Graph:
+    """A disorder sample built by rlpt_graph_build (host memory)."""
+
+    def __init__(self, n_modes: int, seed: int, omega_kind: int = OMEGA_RANDOM, split_mask: int = SPLIT_ALL,
+                 gamma: float = 0.0):
+        self._h = C.c_void_p()
+        desc = GraphDesc(n_modes=n_modes, omega_kind=omega_kind, seed=seed, split_mask=split_mask, gamma=gamma)
+        _check(lib().rlpt_graph_build(C.byref(desc), C.byref(self._h)))
+        self.N = n_modes
+        self.seed = seed
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.rlpt_graph_free(self._h)
+            self._h = None
+
+    def info(self) -> dict:
+        inf = GraphInfo()
+        _check(lib().rlpt_graph_info_get(self._h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in GraphInfo._fields_ if f != "pad"}
+
+    def export(self):
+        inf = self.info()
+        c = inf["n_terms"]
+        omega = np.zeros(self.N)
+        quads = np.zeros((c, 4), dtype=np.int16)
+        J = np.zeros(c)
+        _check(lib().rlpt_graph_export(self._h, _ptr(omega), _ptr(quads), _ptr(J)))
+        return omega, quads, J
+
+
+def default_config(**kw) -> Config:
+    cfg = Config()
+    _check(lib().rlpt_config_default(C.byref(cfg)))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Context:
+    """A parallel-tempering context over a torch-owned device workspace."""
+
+    def __init__(self, graphs, temps, config: Config | None = None, device: str = "cuda:0", stream=None, **kw):
+        import torch
+
+        self.graphs = list(graphs)
+        self.cfg = config if config is not None else default_config(**kw)
+        if config is not None and kw:
+            for k, v in kw.items():
+                setattr(self.cfg, k, v)
+        self.temps = np.ascontiguousarray(temps, dtype=np.float64)
+        if len(self.temps) != self.cfg.n_temps:
+            raise ValueError("len(temps) must equal config n_temps")
+        arr = (C.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
+        self._garr = arr
+        nbytes = C.c_size_t()
+        _check(lib().rlpt_workspace_size(C.byref(self.cfg), arr, len(self.graphs), C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = C.c_void_p()
+        _check(lib().rlpt_create(C.byref(self.cfg), arr, len(self.graphs), _ptr(self.temps),
+                                 C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(self._h)))
+        self.S = len(self.graphs)
+        self.T = self.cfg.n_temps
+        self.reps = self.cfg.n_reps
+        self.R = self.T * self.reps
+        self.n_copies = self.R * self.S
+        self.Ns = [g.N for g in self.graphs]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().rlpt_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def init(self, run_seed: int):
+        _check(lib().rlpt_init(self._h, run_seed))
+
+    def sweep(self, n: int):
+        _check(lib().rlpt_sweep(self._h, n))
+
+    def swap(self):
+        _check(lib().rlpt_swap(self._h))
+
+    def resync(self) -> float:
+        d = C.c_double()
+        _check(lib().rlpt_resync(self._h, C.byref(d)))
+        return d.value
+
+    def check(self):
+        _check(lib().rlpt_check(self._h))
+
+    def run_graph(self, n_sweeps: int, n_segments: int):
+        _check(lib().rlpt_run_graph(self._h, n_sweeps, n_segments))
+
+    def sweep_timing(self, enable: bool = True):
+        _check(lib().rlpt_sweep_timing(self._h, int(enable)))
+
+    def sweep_time(self):
+        """(summed sweep-kernel ms, timed launches) since the last call."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().rlpt_sweep_time_get(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def counters(self):
+        a, b, m = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().rlpt_counters(self._h, C.byref(a), C.byref(b), C.byref(m)))
+        return a.value, b.value, m.value
+
+    def _n_complex(self, first, n):
+        return sum(self.Ns[c // self.R] for c in range(first, first + n))
+
+    def get_state(self, first: int = 0, n: int | None = None) -> np.ndarray:
+        n = self.n_copies - first if n is None else n
+        buf = np.zeros(self._n_complex(first, n), dtype=np.complex128)
+        _check(lib().rlpt_get_state(self._h, first, n, _ptr(buf)))
+        return buf
+
+    def set_state(self, a: np.ndarray, first: int = 0, n: int | None = None):
+        a = np.ascontiguousarray(a, dtype=np.complex128).ravel()
+        n = self.n_copies - first if n is None else n
+        if a.size != self._n_complex(first, n):
+            raise ValueError("state size does not match the copy range")
+        _check(lib().rlpt_set_state(self._h, first, n, _ptr(a)))
+
+    def energies(self):
+        E = np.zeros(self.n_copies)
+        t = np.zeros(self.n_copies, dtype=np.int32)
+        _check(lib().rlpt_get_energies(self._h, _ptr(E), _ptr(t)))
+        return E, t
+
+    def energy_fp64(self) -> np.ndarray:
+        E = np.zeros(self.n_copies)
+        _check(lib().rlpt_energy_fp64(self._h, _ptr(E)))
+        return E
+
+    def local_fields(self, copy: int) -> np.ndarray:
+        F = np.zeros(self.Ns[copy // self.R], dtype=np.complex128)
+        _check(lib().rlpt_local_fields(self._h, copy, _ptr(F)))
+        return F
+
+    def pair_dE(self, copy: int, j, k, aj_new, ak_new) -> np.ndarray:
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        x = np.ascontiguousarray(aj_new, dtype=np.complex128)
+        y = np.ascontiguousarray(ak_new, dtype=np.complex128)
+        dE = np.zeros(len(j))
+        _check(lib().rlpt_pair_dE(self._h, copy, len(j), _ptr(j), _ptr(k), _ptr(x), _ptr(y), _ptr(dE)))
+        return dE
+
+    def observables(self) -> dict:
+        S, T, B, Lh = self.S, self.T, self.cfg.n_bins, max(self.cfg.series_len, 1)
+        shapes = {"hist": (S, T, B), "swap_acc": (S, max(T - 1, 1)), "swap_tries": (S, max(T - 1, 1)),
+                  "series_e": (S, T, Lh), "series_q": (S, T, Lh)}
+        out = {f: np.zeros(shapes.get(f, (S, T))) for f in OBS_FIELDS}
+        o = Obs(**{f: _ptr(out[f]).value for f in OBS_FIELDS})
+        _check(lib().rlpt_observables(self._h, C.byref(o)))
+        return out
+
+
+def tau_int(x, c_window: float = 6.0):
+    """Integrated autocorrelation time (Sokal's automatic window); returns (tau, window)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    tau, W = C.c_double(), C.c_int64()
+    _check(lib().rlpt_tau_int(_ptr(x), len(x), c_window, C.byref(tau), C.byref(W)))
+    return tau.value, W.value
