@@ -59,6 +59,67 @@ def traffic_for_current_kernel(launch_bytes_alg: float):
     return t.get("hbm_bytes_per_launch")
 
 
+PROFILE_CMDS = {
+    "kt": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kt -o kt -- python bench.py --steps 20 --warmup 5 "
+          "--no-cpu-baseline",
+    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex k_sweep -f csv -d gpurun_out/pmc_{C} -o pmc -- python bench.py "
+           "--steps 4 --warmup 2 --no-cpu-baseline",
+    "cal": "rocprofv3 --pmc {C} -f csv -d gpurun_out/cal_{C} -o cal -- python bench.py --copy-calibration",
+}
+
+
+def summarize_profiles(d):
+    """Turn the rocprofv3 CSVs of the commands above (under directory d) into
+    profiles/sweep_n256_kernel_stats.txt and profiles/sweep_n256_traffic.json."""
+    import csv
+
+    def rows(path):
+        with open(path) as f:
+            return list(csv.DictReader(f))
+
+    def mean_counter(path, kernel_pred):
+        vals = [float(r["Counter_Value"]) for r in rows(path) if kernel_pred(r["Kernel_Name"])]
+        return sum(vals) / len(vals), len(vals)
+
+    stats = rows(os.path.join(d, "kt", "kt_kernel_stats.csv"))
+    lines = ["# rocprofv3 kernel statistics, plain PT N=256 bench workload (8 samples x 40 T x 2 replicas)",
+             "# command (from the repository root on the GPU box):",
+             "#   " + PROFILE_CMDS["kt"], "",
+             f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+    for r in stats:
+        name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
+        lines.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                     f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
+    sweep = [r for r in stats if "k_sweep" in r["Name"]][0]
+    is_sweep = lambda n: "k_sweep" in n  # noqa: E731
+    is_copy = lambda n: "copyBuffer" in n  # noqa: E731
+    fetch_kib, nf = mean_counter(os.path.join(d, "pmc_FETCH_SIZE", "pmc_counter_collection.csv"), is_sweep)
+    write_kib, nw = mean_counter(os.path.join(d, "pmc_WRITE_SIZE", "pmc_counter_collection.csv"), is_sweep)
+    cal_f, _ = mean_counter(os.path.join(d, "cal_FETCH_SIZE", "cal_counter_collection.csv"), is_copy)
+    cal_w, _ = mean_counter(os.path.join(d, "cal_WRITE_SIZE", "cal_counter_collection.csv"), is_copy)
+    copy_bytes = 512 * 1024 * 1024
+    f_scale, w_scale = copy_bytes / (cal_f * 1024), copy_bytes / (cal_w * 1024)
+    hbm = fetch_kib * 1024 * f_scale + write_kib * 1024 * w_scale
+    traffic = {"kernel": "k_sweep<float, 256>", "kernel_source_sha": kernel_sha(),
+               "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib, "dispatches": [nf, nw],
+               "copy_kernel_fetch_kib": cal_f, "copy_kernel_write_kib": cal_w, "copy_bytes": copy_bytes,
+               "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
+               "avg_duration_ns_kernel_trace": float(sweep["AverageNs"]),
+               "commands": [PROFILE_CMDS["pmc"].format(C="FETCH_SIZE"), PROFILE_CMDS["pmc"].format(C="WRITE_SIZE"),
+                            PROFILE_CMDS["cal"].format(C="FETCH_SIZE"), PROFILE_CMDS["cal"].format(C="WRITE_SIZE")]}
+    lines += ["", "# HBM traffic of k_sweep per dispatch (rocprofv3 --pmc, one counter per run):",
+              f"#   FETCH_SIZE {fetch_kib:.0f} KiB x {f_scale:.4f} (copy-kernel scale) + WRITE_SIZE {write_kib:.0f} KiB "
+              f"x {w_scale:.4f} = {hbm / 1e9:.3f} GB per launch",
+              f"#   over the kernel-trace average {float(sweep['AverageNs']) / 1e6:.3f} ms: "
+              f"{hbm / float(sweep['AverageNs']):.0f} GB/s"]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "sweep_n256_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(traffic, f, indent=1)
+    print("\n".join(lines))
+
+
 def cpu_baseline(N, temps, n_reps, budget_s, n_threads):
     from oracle import oracle as O
     og = O.Graph(N, SEED_BASE + 0)
@@ -89,7 +150,14 @@ def main():
     ap.add_argument("--copies-per-block", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (disorder samples would shard "
               "across GPUs, see the design notes); run with --gpus 1", file=sys.stderr)
@@ -99,6 +167,15 @@ def main():
     from paper_2511_13508_amd import rlpt
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 128 * 1024 * 1024  # 512 MiB of float32 read and 512 MiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_dispatch": 4 * n}), flush=True)
+        return
     N, S, T, reps = args.n_modes, args.samples, args.temps, args.reps
     temps = 0.25 * (1.5 / 0.25) ** (np.arange(T) / (T - 1))
     log(f"building {S} graphs N={N}")

@@ -535,6 +535,7 @@ int rlpt_run_graph(rlpt_ctx* c, int32_t n_sweeps, int32_t n_segments) {
     if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
     if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
     if (n_sweeps < 1 || n_segments < 0) return fail(RLPT_E_ARG, "n_sweeps must be >= 1 and n_segments >= 0");
+    if (c->stream == nullptr) return fail(RLPT_E_ARG, "graph capture needs a context created on a non-default stream");
     const rlpt_config& cfg = c->cfg;
     const int iv[3] = {cfg.swap_interval, cfg.resync_interval, cfg.measure_interval};
     for (int i = 0; i < 3; ++i)

@@ -74,6 +74,9 @@ def lib() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"librlpt.so not built at {LIB_PATH}; run `python -m paper_2511_13508_amd.build`")
+    # torch bundles its own HIP runtime with the same soname; load it first so
+    # that librlpt binds to that one runtime instead of pulling in a second
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, i32, i64, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     sig = {
@@ -187,7 +190,8 @@ class Context:
         _check(lib().rlpt_workspace_size(C.byref(self.cfg), arr, len(self.graphs), C.byref(nbytes)))
         self.device = torch.device(device)
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): HIP graphs cannot capture the null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self._h = C.c_void_p()
         _check(lib().rlpt_create(C.byref(self.cfg), arr, len(self.graphs), _ptr(self.temps),
                                  C.c_void_p(self.workspace.data_ptr()), nbytes.value,

@@ -118,7 +118,7 @@ def run_pair(oracle, Ns, temps, n_sweeps, seed, seeds=None, omega=rlpt.OMEGA_RAN
     ctx.check()
     ors = []
     for mu, (N, s) in enumerate(zip(Ns, seeds)):
-        pt = oracle_pt(oracle, oracle.Graph(N, s, omega), temps, mu, ctx.cfg)
+        pt = oracle_pt(oracle, oracle.Graph(N, s, omega), temps, mu, ctx.cfg, seed)
         pt.run(n_sweeps)
         ors.append(pt)
     return ctx, ors
