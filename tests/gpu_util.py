@@ -16,7 +16,8 @@ def make_ctx(graphs, temps, **cfg):
 def oracle_pt(oracle, og, temps, sample, ctx_cfg, run_seed, **kw):
     """An oracle PT run mirroring a library context's schedule for one sample."""
     c = ctx_cfg
-    return oracle.PT(og, temps, n_reps=c.n_reps, run_seed=run_seed, sample=sample, shared_pairs=bool(c.shared_pairs),
+    kw.setdefault("shared_pairs", bool(c.shared_pairs))
+    return oracle.PT(og, temps, n_reps=c.n_reps, run_seed=run_seed, sample=sample,
                      swap_interval=c.swap_interval, resync_interval=c.resync_interval, renorm_tol=c.renorm_tol,
                      measure_start=c.measure_start, measure_interval=c.measure_interval, n_bins=c.n_bins,
                      series_len=c.series_len, **kw)
