@@ -148,6 +148,7 @@ def main():
     ap.add_argument("--shared-pairs", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--copies-per-block", type=int, default=0)
+    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 packed (8 B/entry), 2 chunked (6.25 B/entry)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
@@ -184,7 +185,7 @@ def main():
     ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32,
                        shared_pairs=args.shared_pairs, swap_interval=1, resync_interval=100, measure_start=0,
                        measure_interval=1, n_bins=100, block_threads=args.block,
-                       copies_per_block=args.copies_per_block)
+                       copies_per_block=args.copies_per_block, list_layout=args.layout)
     ctx.init(1)
     log(f"warmup {args.warmup} sweeps")
     ctx.sweep(args.warmup)
@@ -203,9 +204,12 @@ def main():
     value = N * n_copies * args.steps / el
     # algorithmic bytes of one sweep launch (one sweep): every copy streams, per
     # two-mode step, the lists of j and k; over a sweep of N/2 uniform pairs that
-    # is 4c entries on average, 8 bytes each
+    # is the 4c entries of all lists on average: 8 B per entry in the packed
+    # layout, 25 B per 4 entries in the chunked one (padding not counted)
+    chunked = args.layout == 2 or (args.layout == 0 and N <= 256 and N >= 32)
+    per_entry = 6.25 if chunked else 8.0
     sweeps_per_launch = args.steps / launches
-    bytes_per_launch = sweeps_per_launch * sum(reps * T * inf["deg_sum"] * 8 for inf in infos)
+    bytes_per_launch = sweeps_per_launch * sum(reps * T * inf["deg_sum"] * per_entry for inf in infos)
     t_launch = kms / launches * 1e-3
     achieved = bytes_per_launch / t_launch / 1e9
     traffic = traffic_for_current_kernel(bytes_per_launch)
@@ -227,7 +231,8 @@ def main():
                                f"FP64 resync/100, swap+measure every sweep",
                    "n_modes": N, "samples": S, "temperatures": T, "replicas": reps, "copies": n_copies,
                    "terms_per_sample": [inf["n_terms"] for inf in infos],
-                   "pair_schedule": "shared per sample" if args.shared_pairs else "per copy"},
+                   "pair_schedule": "shared per sample" if args.shared_pairs else "per copy",
+                   "list_layout": "chunked" if chunked else "packed"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_sweep", "ms_per_launch": kms / launches,

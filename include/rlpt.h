@@ -47,6 +47,7 @@ enum {
 enum { RLPT_OMEGA_RANDOM = 0, RLPT_OMEGA_COMB = 1 };
 enum { RLPT_SPLIT_A = 1, RLPT_SPLIT_B = 2, RLPT_SPLIT_C = 4, RLPT_SPLIT_ALL = 7 };
 enum { RLPT_FP32 = 0, RLPT_FP64 = 1 };
+enum { RLPT_LAYOUT_AUTO = 0, RLPT_LAYOUT_PACKED = 1, RLPT_LAYOUT_CHUNKED = 2 };
 
 /* ABI version (RLPT_ABI_VERSION of the built library). */
 int rlpt_abi_version(void);
@@ -77,8 +78,10 @@ typedef struct rlpt_graph_info {
     int64_t deg_min, deg_max, deg_sum; /* per-mode term counts; deg_sum = 4c */
     double gamma;
     double sigma2;       /* coupling variance N / c */
-    int64_t list_entries;/* per-mode list entries after padding */
-    int64_t list_bytes;  /* bytes streamed by the sweep for all per-mode lists (FP32 build) */
+    int64_t list_entries;/* packed layout: per-mode list entries after padding to multiples of 4 */
+    int64_t list_bytes;  /* packed layout: bytes of all per-mode lists in an FP32 context (8 B/entry) */
+    int64_t chunk_entries;/* chunked layout (N <= 256): entries after padding each partner group to 4 */
+    int64_t chunk_bytes; /* chunked layout: bytes of all lists in an FP32 context (25 B per 4 entries) */
 } rlpt_graph_info;
 
 /* Build one disorder sample: frequencies; every split of every i<j<k<l into a
@@ -117,6 +120,11 @@ typedef struct rlpt_config {
     int32_t series_len;       /* stored measurements of E (ladder 0) and q_01 per bath */
     int32_t block_threads;    /* threads per workgroup of the sweep kernel: 0 = tuned, else 64..1024 */
     int32_t copies_per_block; /* copies per workgroup: 0 = tuned, else divides block_threads/64 */
+    int32_t list_layout;      /* per-mode list layout streamed by the sweep: RLPT_LAYOUT_AUTO,
+                                 RLPT_LAYOUT_PACKED (8 B/entry, any N) or RLPT_LAYOUT_CHUNKED
+                                 (entries grouped by partner mode in chunks of 4 sharing one
+                                 partner byte, 6.25 B/entry, N <= 256) */
+    int32_t pad;
 } rlpt_config;
 
 /* Fill *cfg with defaults: FP32, per-copy pairs, swap every sweep, FP64

@@ -110,7 +110,7 @@ struct Layout {
 };
 
 struct Regions {
-    size_t samples, items, mode_start, idx, J, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
+    size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
     size_t acc_begin, acc, swap_acc, obs, hist, series_e, series_q, meas_cnt, counters, acc_end;
     size_t scratch, scratch_doubles, total;
 };
@@ -127,6 +127,26 @@ int check_config(const rlpt_config* cfg) {
                                     (cfg->block_threads & (cfg->block_threads - 1))))
         return fail(RLPT_E_ARG, "block_threads must be 0 or a power of two in [64, 1024]");
     if (cfg->copies_per_block < 0) return fail(RLPT_E_ARG, "copies_per_block must be >= 0");
+    if (cfg->list_layout < RLPT_LAYOUT_AUTO || cfg->list_layout > RLPT_LAYOUT_CHUNKED)
+        return fail(RLPT_E_ARG, "bad list_layout");
+    return RLPT_OK;
+}
+
+// list layout of a context: chunked needs N <= 256 everywhere; the automatic
+// choice also avoids it for small N, where padding partner groups to 4
+// entries inflates the lists
+int choose_layout(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int* layout) {
+    int max_N = 0, min_N = 1 << 30;
+    for (int i = 0; i < S; ++i) {
+        max_N = std::max(max_N, g[i]->N);
+        min_N = std::min(min_N, g[i]->N);
+    }
+    if (cfg.list_layout == RLPT_LAYOUT_PACKED) *layout = kLayoutPacked;
+    else if (cfg.list_layout == RLPT_LAYOUT_CHUNKED) {
+        if (max_N > kMaxChunkModes) return fail(RLPT_E_ARG, "the chunked list layout needs N <= 256");
+        *layout = kLayoutChunked;
+    } else
+        *layout = (max_N <= kMaxChunkModes && min_N >= 32) ? kLayoutChunked : kLayoutPacked;
     return RLPT_OK;
 }
 
@@ -137,14 +157,15 @@ int check_graphs(const rlpt_graph* const* g, int n) {
     return RLPT_OK;
 }
 
-Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S) {
+Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layout) {
     const size_t rb = cfg.precision == RLPT_FP64 ? 8 : 4;
     const size_t T = cfg.n_temps, reps = cfg.n_reps, Rc = T * reps, copies = Rc * S;
-    size_t modes = 0, entries = 0, quads = 0, amp = 0;
+    size_t modes = 0, entries = 0, chunks = 0, quads = 0, amp = 0;
     int max_N = 0;
     for (int i = 0; i < S; ++i) {
         modes += g[i]->N + 1;
-        entries += g[i]->mode_start.back();
+        if (layout == kLayoutPacked) entries += g[i]->mode_start.back();
+        else chunks += g[i]->cx.size();
         quads += g[i]->n_terms();
         amp += Rc * g[i]->N;
         max_N = std::max(max_N, g[i]->N);
@@ -156,6 +177,10 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S) {
     r.mode_start = L.take(modes * 4);
     r.idx = L.take(entries * 4);
     r.J = L.take(entries * rb);
+    r.chunk_start = L.take(layout == kLayoutChunked ? modes * 4 : 0);
+    r.cx = L.take(chunks);
+    r.cyz = L.take(chunks * 8);
+    r.cJ = L.take(chunks * 4 * rb);
     r.quads = L.take(quads * 8);
     r.Jq = L.take(quads * 8);
     r.amp = L.take(amp * 2 * rb);
@@ -189,6 +214,10 @@ void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
     P.mode_start = reinterpret_cast<const uint32_t*>(b + r.mode_start);
     P.idx = reinterpret_cast<const uint32_t*>(b + r.idx);
     P.J = reinterpret_cast<const R*>(b + r.J);
+    P.chunk_start = reinterpret_cast<const uint32_t*>(b + r.chunk_start);
+    P.cx = reinterpret_cast<const uint8_t*>(b + r.cx);
+    P.cyz = reinterpret_cast<const uint2*>(b + r.cyz);
+    P.cJ = reinterpret_cast<const R*>(b + r.cJ);
     P.quads = reinterpret_cast<const ushort4*>(b + r.quads);
     P.Jq = reinterpret_cast<const double*>(b + r.Jq);
     P.amp = reinterpret_cast<R*>(b + r.amp);
@@ -311,6 +340,7 @@ int rlpt_config_default(rlpt_config* cfg) {
     cfg->measure_interval = 1;
     cfg->n_bins = 100;
     cfg->series_len = 0;
+    cfg->list_layout = RLPT_LAYOUT_AUTO;
     return RLPT_OK;
 }
 
@@ -319,7 +349,9 @@ int rlpt_workspace_size(const rlpt_config* cfg, const rlpt_graph* const* graphs,
     if (rc) return rc;
     if ((rc = check_graphs(graphs, n_graphs))) return rc;
     if (!bytes) return fail(RLPT_E_ARG, "bytes is NULL");
-    *bytes = plan(*cfg, graphs, n_graphs).total;
+    int layout = 0;
+    if ((rc = choose_layout(*cfg, graphs, n_graphs, &layout))) return rc;
+    *bytes = plan(*cfg, graphs, n_graphs, layout).total;
     return RLPT_OK;
 }
 
@@ -335,7 +367,9 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         if (!(temps[t] > 0.0) || !isfinite(temps[t])) return fail(RLPT_E_ARG, "temperatures must be finite and > 0");
         if (t > 0 && !(temps[t] > temps[t - 1])) return fail(RLPT_E_ARG, "temperatures must be strictly ascending");
     }
-    const Regions r = plan(*cfg, graphs, n_graphs);
+    int layout = 0;
+    if ((rc = choose_layout(*cfg, graphs, n_graphs, &layout))) return rc;
+    const Regions r = plan(*cfg, graphs, n_graphs, layout);
     if (workspace_bytes < r.total) return fail(RLPT_E_NOMEM, "workspace smaller than rlpt_workspace_size()");
     rlpt_ctx* c = new (std::nothrow) rlpt_ctx;
     if (!c) return fail(RLPT_E_NOMEM, "out of host memory");
@@ -358,9 +392,11 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->scratch_doubles = r.scratch_doubles;
 
     // host images of the device tables
-    std::vector<uint32_t> ms, idx;
-    std::vector<float> J32;
-    std::vector<double> J64, Jq;
+    std::vector<uint32_t> ms, idx, cs;
+    std::vector<float> J32, cJ32;
+    std::vector<double> J64, Jq, cJ64;
+    std::vector<uint8_t> cx;
+    std::vector<uint16_t> cyz;
     std::vector<ushort4> quads;
     int64_t amp_base = 0, quad_base = 0;
     for (int s = 0; s < c->S; ++s) {
@@ -368,16 +404,26 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         SampleDev sd{};
         sd.N = g->N;
         sd.n_steps = g->N / 2;
-        sd.mode_base = (uint32_t)ms.size();
+        sd.mode_base = (uint32_t)(layout == kLayoutPacked ? ms.size() : cs.size());
         sd.amp_base = amp_base;
         sd.quad_base = quad_base;
         sd.n_quads = g->n_terms();
-        const uint32_t ebase = (uint32_t)idx.size();
-        for (uint32_t v : g->mode_start) ms.push_back(v + ebase);
-        idx.insert(idx.end(), g->idx.begin(), g->idx.end());
-        if (cfg->precision == RLPT_FP64) J64.insert(J64.end(), g->Jl.begin(), g->Jl.end());
-        else
-            for (double v : g->Jl) J32.push_back((float)v);
+        if (layout == kLayoutPacked) {
+            const uint32_t ebase = (uint32_t)idx.size();
+            for (uint32_t v : g->mode_start) ms.push_back(v + ebase);
+            idx.insert(idx.end(), g->idx.begin(), g->idx.end());
+            if (cfg->precision == RLPT_FP64) J64.insert(J64.end(), g->Jl.begin(), g->Jl.end());
+            else
+                for (double v : g->Jl) J32.push_back((float)v);
+        } else {
+            const uint32_t cbase = (uint32_t)cx.size();
+            for (uint32_t v : g->chunk_start) cs.push_back(v + cbase);
+            cx.insert(cx.end(), g->cx.begin(), g->cx.end());
+            cyz.insert(cyz.end(), g->cyz.begin(), g->cyz.end());
+            if (cfg->precision == RLPT_FP64) cJ64.insert(cJ64.end(), g->cJ.begin(), g->cJ.end());
+            else
+                for (double v : g->cJ) cJ32.push_back((float)v);
+        }
         for (int64_t q = 0; q < g->n_terms(); ++q) {
             ushort4 u;
             u.x = (unsigned short)g->quads[4 * q];
@@ -432,6 +478,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->sh.n_bins = cfg->n_bins;
     c->sh.series_len = cfg->series_len;
     c->sh.shared_pairs = cfg->shared_pairs;
+    c->sh.layout = layout;
     c->sh.renorm_tol = cfg->renorm_tol;
     c->sh.drift_tol = cfg->drift_tol;
 
@@ -451,6 +498,11 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     up(r.idx, idx);
     if (cfg->precision == RLPT_FP64) up(r.J, J64);
     else up(r.J, J32);
+    up(r.chunk_start, cs);
+    up(r.cx, cx);
+    up(r.cyz, cyz);
+    if (cfg->precision == RLPT_FP64) up(r.cJ, cJ64);
+    else up(r.cJ, cJ32);
     up(r.quads, quads);
     up(r.Jq, Jq);
     if (cfg->precision == RLPT_FP64) up(r.beta, b64);

@@ -127,6 +127,41 @@ extern "C" int rlpt_graph_build(const rlpt_graph_desc* d, rlpt_graph** out) {
                 g->Jl[e] = g->J[q];
             }
         }
+        // chunked lists: each mode's entries grouped by partner x (term order
+        // kept inside a group), every group padded to a multiple of 4 entries
+        if (N <= kMaxChunkModes) {
+            g->chunk_start.assign(N + 1, 0);
+            std::vector<uint32_t> order;
+            for (int l = 0; l < N; ++l) {
+                const uint32_t b = g->mode_start[l], e = b + (uint32_t)deg[l];
+                order.resize(e - b);
+                for (uint32_t i = 0; i < e - b; ++i) order[i] = b + i;
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](uint32_t u, uint32_t v) { return (g->idx[u] & 1023u) < (g->idx[v] & 1023u); });
+                size_t i = 0;
+                while (i < order.size()) {
+                    const uint32_t x = g->idx[order[i]] & 1023u;
+                    size_t end = i;
+                    while (end < order.size() && (g->idx[order[end]] & 1023u) == x) ++end;
+                    for (size_t c0 = i; c0 < end; c0 += 4) {
+                        g->cx.push_back((uint8_t)x);
+                        for (size_t k = c0; k < c0 + 4; ++k) {
+                            if (k < end) {
+                                const uint32_t v = g->idx[order[k]];
+                                const uint32_t y = (v >> 10) & 1023u, z = v >> 20;
+                                g->cyz.push_back((uint16_t)(y | (z << 8)));
+                                g->cJ.push_back(g->Jl[order[k]]);
+                            } else {
+                                g->cyz.push_back(0);
+                                g->cJ.push_back(0.0);
+                            }
+                        }
+                    }
+                    i = end;
+                }
+                g->chunk_start[l + 1] = (uint32_t)g->cx.size();
+            }
+        }
     } catch (const std::bad_alloc&) {
         delete g;
         return fail(RLPT_E_NOMEM, "rlpt_graph_build: out of host memory");
@@ -152,6 +187,8 @@ extern "C" int rlpt_graph_info_get(const rlpt_graph* g, rlpt_graph_info* out) {
     out->sigma2 = g->sigma2;
     out->list_entries = g->mode_start.back();
     out->list_bytes = (int64_t)g->mode_start.back() * (int64_t)(sizeof(uint32_t) + sizeof(float));
+    out->chunk_entries = 4 * (int64_t)g->cx.size();
+    out->chunk_bytes = (int64_t)g->cx.size() * 25;
     return RLPT_OK;
 }
 

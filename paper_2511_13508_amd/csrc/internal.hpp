@@ -23,12 +23,20 @@ struct rlpt_graph {
     std::vector<uint32_t> mode_start;  // [N+1]
     std::vector<uint32_t> idx;         // packed x | y << 10 | z << 20
     std::vector<double> Jl;            // coupling of each entry (0 for padding)
+    // chunked lists (N <= 256): mode l owns chunks [chunk_start[l], chunk_start[l+1]);
+    // a chunk is 4 entries with one partner x; (y, z) packed y | z << 8 in 16 bits
+    std::vector<uint32_t> chunk_start; // [N+1]
+    std::vector<uint8_t> cx;           // [chunks]
+    std::vector<uint16_t> cyz;         // [4 * chunks]
+    std::vector<double> cJ;            // [4 * chunks] (0 for padding)
     int64_t n_terms() const { return (int64_t)J.size(); }
 };
 
 namespace rlpt {
 
 constexpr int kMaxModes = 1024;  // three 10-bit mode indices per packed entry
+constexpr int kMaxChunkModes = 256;  // 8-bit indices in the chunked layout
+enum ListLayout { kLayoutPacked = 1, kLayoutChunked = 2 };
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -37,7 +45,7 @@ int fail(int code, const std::string& msg);
 struct SampleDev {
     int32_t N;
     int32_t n_steps;       // two-mode updates per sweep, N / 2
-    uint32_t mode_base;    // offset of this sample's mode_start block (N + 1 values)
+    uint32_t mode_base;    // offset of this sample's mode_start / chunk_start block (N + 1 values)
     uint32_t pad0;
     int64_t amp_base;      // complex offset of the sample's first copy
     int64_t quad_base;     // offset into the by-term arrays
@@ -67,6 +75,10 @@ struct DevPtrs {
     const uint32_t* mode_start;
     const uint32_t* idx;
     const R* J;               // per-mode entries, context precision
+    const uint32_t* chunk_start;  // chunked layout: absolute chunk index per mode
+    const uint8_t* cx;        // chunk partner
+    const uint2* cyz;         // chunk (y | z << 8) x 4 as 16-bit halves
+    const R* cJ;              // chunk couplings (4 per chunk)
     const ushort4* quads;     // by term (p, s, m, n)
     const double* Jq;         // by term, FP64
     R* amp;                   // interleaved complex [copy][N]
@@ -98,7 +110,7 @@ struct ShapeInfo {
     int32_t n_bins;
     int32_t series_len;
     int32_t shared_pairs;
-    int32_t pad;
+    int32_t layout;             // ListLayout
     uint64_t run_seed;
     double renorm_tol;
     double drift_tol;

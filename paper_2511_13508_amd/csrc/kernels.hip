@@ -120,6 +120,59 @@ __device__ inline void field_partial(const uint32_t* __restrict__ idx, const R* 
     }
 }
 
+// chunked layout: a chunk holds 4 entries sharing the partner x; the field
+// contribution is conj(a_x) * sum_i J_i a_{y_i} a_{z_i}
+template <typename R>
+__device__ inline void chunk_pair(uint32_t v, R j, const R2<R>* __restrict__ a, R& gr, R& gi) {
+    const R2<R> ay = a[v & 0xffu];
+    const R2<R> az = a[(v >> 8) & 0xffu];
+    gr += j * (ay.x * az.x - ay.y * az.y);
+    gi += j * (ay.x * az.y + ay.y * az.x);
+}
+
+template <typename R>
+__device__ inline void chunk_term(uint32_t x, uint2 yz, typename J4<R>::T j, const R2<R>* __restrict__ a, R& fr,
+                                  R& fi) {
+    R gr = 0, gi = 0;
+    chunk_pair<R>(yz.x & 0xffffu, j.x, a, gr, gi);
+    chunk_pair<R>(yz.x >> 16, j.y, a, gr, gi);
+    chunk_pair<R>(yz.y & 0xffffu, j.z, a, gr, gi);
+    chunk_pair<R>(yz.y >> 16, j.w, a, gr, gi);
+    const R2<R> ax = a[x];
+    fr += ax.x * gr + ax.y * gi;
+    fi += ax.x * gi - ax.y * gr;
+}
+
+template <typename R>
+__device__ inline void field_partial_chunk(const uint8_t* __restrict__ cx, const uint2* __restrict__ cyz,
+                                           const R* __restrict__ cJ, uint32_t beg, uint32_t end,
+                                           const R2<R>* __restrict__ a, int t, int nt, R& fr, R& fi) {
+    using JT = typename J4<R>::T;
+    const JT* __restrict__ Jv = reinterpret_cast<const JT*>(cJ);
+    uint32_t c = beg + t;
+    for (; c + nt < end; c += 2 * nt) {
+        const uint32_t x0 = cx[c], x1 = cx[c + nt];
+        const uint2 y0 = cyz[c], y1 = cyz[c + nt];
+        const JT j0 = Jv[c], j1 = Jv[c + nt];
+        chunk_term<R>(x0, y0, j0, a, fr, fi);
+        chunk_term<R>(x1, y1, j1, a, fr, fi);
+    }
+    if (c < end) chunk_term<R>(cx[c], cyz[c], Jv[c], a, fr, fi);
+}
+
+// partial field of mode l of sample sd in the context's list layout
+template <typename R, int LAYOUT>
+__device__ inline void mode_field(const DevPtrs<R>& P, const SampleDev& sd, int l, const R2<R>* __restrict__ a, int t,
+                                  int nt, R& fr, R& fi) {
+    if constexpr (LAYOUT == kLayoutChunked) {
+        const uint32_t* cs = P.chunk_start + sd.mode_base;
+        field_partial_chunk<R>(P.cx, P.cyz, P.cJ, cs[l], cs[l + 1], a, t, nt, fr, fi);
+    } else {
+        const uint32_t* ms = P.mode_start + sd.mode_base;
+        field_partial<R>(P.idx, P.J, ms[l], ms[l + 1], a, t, nt, fr, fi);
+    }
+}
+
 // energy change of the two-mode update from the two fields of one snapshot:
 // dE = -2 Re(conj(aj_new - aj_old) F_j) - 2 Re(conj(ak_new - ak_old) F_k)
 template <typename R>
@@ -172,7 +225,7 @@ __host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
     return (amp + tab + red + 15) & ~(size_t)15;
 }
 
-template <typename R, int BLOCK>
+template <typename R, int BLOCK, int LAYOUT>
 __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kWaves = BLOCK / 64;
@@ -204,7 +257,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     unsigned int n_acc = 0;
     const int64_t pair_stream = sh.shared_pairs ? (int64_t)it.sample : (int64_t)c;
     const int64_t sweep0 = P.counters->sweeps_done;
-    const uint32_t* ms = P.mode_start + sd.mode_base;
 
     R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
     for (int sw = 0; sw < n_sweeps; ++sw) {
@@ -227,8 +279,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
             R fjr = 0, fji = 0, fkr = 0, fki = 0;
             if (active) {
                 const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
-                field_partial<R>(P.idx, P.J, ms[j], ms[j + 1], a, gt, nt, fjr, fji);
-                field_partial<R>(P.idx, P.J, ms[k], ms[k + 1], a, gt, nt, fkr, fki);
+                mode_field<R, LAYOUT>(P, sd, j, a, gt, nt, fjr, fji);
+                mode_field<R, LAYOUT>(P, sd, k, a, gt, nt, fkr, fki);
             }
             fjr = wave_sum(fjr);
             fji = wave_sum(fji);
@@ -509,7 +561,7 @@ __global__ __launch_bounds__(64) void k_measure(DevPtrs<R> P, ShapeInfo sh) {
 
 // ---------------------------------------------------------------- test hooks
 // all N local fields of one copy with the sweep's field code (one block)
-template <typename R>
+template <typename R, int LAYOUT>
 __global__ __launch_bounds__(256) void k_fields(DevPtrs<R> P, ShapeInfo sh, int copy, int mu, double* F) {
     __shared__ R2<R> a[kMaxModes];
     __shared__ R red[4][2];
@@ -519,10 +571,9 @@ __global__ __launch_bounds__(256) void k_fields(DevPtrs<R> P, ShapeInfo sh, int 
     const R2<R>* amp = reinterpret_cast<const R2<R>*>(P.amp) + sd.amp_base + local * N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = amp[i];
     __syncthreads();
-    const uint32_t* ms = P.mode_start + sd.mode_base;
     for (int l = 0; l < N; ++l) {
         R fr = 0, fi = 0;
-        field_partial<R>(P.idx, P.J, ms[l], ms[l + 1], a, threadIdx.x, blockDim.x, fr, fi);
+        mode_field<R, LAYOUT>(P, sd, l, a, threadIdx.x, blockDim.x, fr, fi);
         fr = wave_sum(fr);
         fi = wave_sum(fi);
         if ((threadIdx.x & 63) == 0) {
@@ -544,7 +595,7 @@ __global__ __launch_bounds__(256) void k_fields(DevPtrs<R> P, ShapeInfo sh, int 
 }
 
 // pair energy changes on given proposals, with the sweep's snapshot rule
-template <typename R>
+template <typename R, int LAYOUT>
 __global__ __launch_bounds__(256) void k_pair_dE(DevPtrs<R> P, ShapeInfo sh, int copy, int mu, int n,
                                                  const int32_t* jk, const double* nw, double* dE) {
     __shared__ R2<R> a[kMaxModes];
@@ -553,7 +604,6 @@ __global__ __launch_bounds__(256) void k_pair_dE(DevPtrs<R> P, ShapeInfo sh, int
     const int N = sd.N;
     const int64_t local = copy - (int64_t)mu * sh.copies_per_sample;
     const R2<R>* amp = reinterpret_cast<const R2<R>*>(P.amp) + sd.amp_base + local * N;
-    const uint32_t* ms = P.mode_start + sd.mode_base;
     for (int p = 0; p < n; ++p) {
         for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = amp[i];
         __syncthreads();
@@ -564,8 +614,8 @@ __global__ __launch_bounds__(256) void k_pair_dE(DevPtrs<R> P, ShapeInfo sh, int
         if (threadIdx.x == 0) a[j] = ajn;
         __syncthreads();
         R fjr = 0, fji = 0, fkr = 0, fki = 0;
-        field_partial<R>(P.idx, P.J, ms[j], ms[j + 1], a, threadIdx.x, blockDim.x, fjr, fji);
-        field_partial<R>(P.idx, P.J, ms[k], ms[k + 1], a, threadIdx.x, blockDim.x, fkr, fki);
+        mode_field<R, LAYOUT>(P, sd, j, a, threadIdx.x, blockDim.x, fjr, fji);
+        mode_field<R, LAYOUT>(P, sd, k, a, threadIdx.x, blockDim.x, fkr, fki);
         fjr = wave_sum(fjr);
         fji = wave_sum(fji);
         fkr = wave_sum(fkr);
@@ -603,7 +653,12 @@ template <typename R, int BLOCK>
 hipError_t launch_sweep_t(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,
                           hipStream_t st) {
     const DevPtrs<R>& P = *static_cast<const DevPtrs<R>*>(ptrs);
-    hipLaunchKernelGGL((k_sweep<R, BLOCK>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh, L.max_N, n_sweeps);
+    if (sh.layout == kLayoutChunked)
+        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
+                           L.max_N, n_sweeps);
+    else
+        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutPacked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
+                           L.max_N, n_sweeps);
     return hipGetLastError();
 }
 
@@ -691,15 +746,24 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
 
 template <typename R>
 static hipError_t fields_t(const void* ptrs, int copy, int mu, double* F, hipStream_t st, const ShapeInfo& sh) {
-    hipLaunchKernelGGL(k_fields<R>, dim3(1), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, F);
+    if (sh.layout == kLayoutChunked)
+        hipLaunchKernelGGL((k_fields<R, kLayoutChunked>), dim3(1), dim3(256), 0, st,
+                           *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, F);
+    else
+        hipLaunchKernelGGL((k_fields<R, kLayoutPacked>), dim3(1), dim3(256), 0, st,
+                           *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, F);
     return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t pair_t(const void* ptrs, int copy, int mu, int n, const int32_t* jk, const double* nw, double* dE,
                          hipStream_t st, const ShapeInfo& sh) {
-    hipLaunchKernelGGL(k_pair_dE<R>, dim3(1), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, n,
-                       jk, nw, dE);
+    if (sh.layout == kLayoutChunked)
+        hipLaunchKernelGGL((k_pair_dE<R, kLayoutChunked>), dim3(1), dim3(256), 0, st,
+                           *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, n, jk, nw, dE);
+    else
+        hipLaunchKernelGGL((k_pair_dE<R, kLayoutPacked>), dim3(1), dim3(256), 0, st,
+                           *static_cast<const DevPtrs<R>*>(ptrs), sh, copy, mu, n, jk, nw, dE);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ RLPT_OK, RLPT_E_ARG, RLPT_E_NOMEM, RLPT_E_HIP, RLPT_E_STATE, RLPT_E_UNSUPPORTED 
 OMEGA_RANDOM, OMEGA_COMB = 0, 1
 SPLIT_A, SPLIT_B, SPLIT_C, SPLIT_ALL = 1, 2, 4, 7
 FP32, FP64 = 0, 1
+LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_CHUNKED = 0, 1, 2
 
 # every symbol declared in include/rlpt.h
 EXPORTS = [
@@ -45,7 +46,8 @@ class GraphDesc(C.Structure):
 class GraphInfo(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("pad", C.c_int32), ("n_terms", C.c_int64), ("deg_min", C.c_int64),
                 ("deg_max", C.c_int64), ("deg_sum", C.c_int64), ("gamma", C.c_double), ("sigma2", C.c_double),
-                ("list_entries", C.c_int64), ("list_bytes", C.c_int64)]
+                ("list_entries", C.c_int64), ("list_bytes", C.c_int64), ("chunk_entries", C.c_int64),
+                ("chunk_bytes", C.c_int64)]
 
 
 class Config(C.Structure):
@@ -53,7 +55,8 @@ class Config(C.Structure):
                 ("shared_pairs", C.c_int32), ("swap_interval", C.c_int32), ("resync_interval", C.c_int32),
                 ("renorm_tol", C.c_double), ("drift_tol", C.c_double), ("measure_start", C.c_int32),
                 ("measure_interval", C.c_int32), ("n_bins", C.c_int32), ("series_len", C.c_int32),
-                ("block_threads", C.c_int32), ("copies_per_block", C.c_int32)]
+                ("block_threads", C.c_int32), ("copies_per_block", C.c_int32), ("list_layout", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",

@@ -51,14 +51,16 @@ def test_init_matches_oracle(oracle, precision):
 
 
 # ------------------------------------------------------------------ fields / pair dE / energy
-CASES = [(16, rlpt.FP64), (16, rlpt.FP32), (64, rlpt.FP32), (97, rlpt.FP32), (64, rlpt.FP64)]
+PK, CH = rlpt.LAYOUT_PACKED, rlpt.LAYOUT_CHUNKED
+CASES = [(16, rlpt.FP64, PK), (16, rlpt.FP32, PK), (16, rlpt.FP32, CH), (64, rlpt.FP32, PK), (64, rlpt.FP32, CH),
+         (97, rlpt.FP32, CH), (97, rlpt.FP32, PK), (64, rlpt.FP64, CH), (256, rlpt.FP32, CH)]
 
 
-@pytest.mark.parametrize("N,precision", CASES)
-def test_local_fields_match_oracle(oracle, N, precision):
+@pytest.mark.parametrize("N,precision,layout", CASES)
+def test_local_fields_match_oracle(oracle, N, precision, layout):
     g = rlpt.Graph(N, SEED0 + N)
     og = oracle.Graph(N, SEED0 + N)
-    ctx = make_ctx([g], temps_geo(0.3, 1.5, 2), n_temps=2, n_reps=2, precision=precision)
+    ctx = make_ctx([g], temps_geo(0.3, 1.5, 2), n_temps=2, n_reps=2, precision=precision, list_layout=layout)
     ctx.init(1)
     states = synth.random_state(N, 5, n_copies=ctx.n_copies)
     ctx.set_state(states)
@@ -69,17 +71,17 @@ def test_local_fields_match_oracle(oracle, N, precision):
         assert_fields_close(F, ref, rel)
 
 
-@pytest.mark.parametrize("N,precision", CASES)
-def test_pair_dE_matches_oracle(oracle, N, precision):
+@pytest.mark.parametrize("N,precision,layout", CASES)
+def test_pair_dE_matches_oracle(oracle, N, precision, layout):
     g = rlpt.Graph(N, SEED0 + N)
     og = oracle.Graph(N, SEED0 + N)
-    ctx = make_ctx([g], [1.0], n_temps=1, n_reps=1, precision=precision)
+    ctx = make_ctx([g], [1.0], n_temps=1, n_reps=1, precision=precision, list_layout=layout)
     ctx.init(2)
     a = synth.random_state(N, 6)
     ctx.set_state(a)
     ar = rounded(a, precision)
-    pairs = synth.random_pairs(N, 7, 24)
-    new = rounded(synth.random_complex(8, 48), precision)
+    pairs = synth.random_pairs(N, 7, 24 if N < 200 else 6)
+    new = rounded(synth.random_complex(8, 2 * len(pairs)), precision)
     dE = ctx.pair_dE(0, pairs[:, 0], pairs[:, 1], new[0::2], new[1::2])
     F = oracle.fields(og, ar)
     for p, (j, k) in enumerate(pairs):
@@ -94,11 +96,11 @@ def test_pair_dE_matches_oracle(oracle, N, precision):
         assert abs(dE[p] - ref) <= tol, (p, dE[p], ref, tol)
 
 
-@pytest.mark.parametrize("N,precision", CASES)
-def test_energy_fp64_matches_oracle(oracle, N, precision):
+@pytest.mark.parametrize("N,precision,layout", CASES)
+def test_energy_fp64_matches_oracle(oracle, N, precision, layout):
     g = rlpt.Graph(N, SEED0 + N)
     og = oracle.Graph(N, SEED0 + N)
-    ctx = make_ctx([g], temps_geo(0.5, 1.0, 3), n_temps=3, n_reps=2, precision=precision)
+    ctx = make_ctx([g], temps_geo(0.5, 1.0, 3), n_temps=3, n_reps=2, precision=precision, list_layout=layout)
     ctx.init(3)
     states = synth.random_state(N, 9, n_copies=ctx.n_copies)
     ctx.set_state(states)
@@ -150,25 +152,26 @@ def compare_fp64(ctx, ors, state_tol=1e-9):
         assert np.array_equal(obs["hist"][mu], A["hist"])
 
 
-def test_trajectory_fp64_config0(oracle):
+@pytest.mark.parametrize("layout", [PK, CH])
+def test_trajectory_fp64_config0(oracle, layout):
     """Plain PT in FP64 at N = 16, 8 temperatures geometric in [0.3, 1.5], two
     replicas, 2000 sweeps, a swap round every sweep: the whole run, bit-for-bit
     in every discrete decision."""
     ctx, ors = run_pair(oracle, [16], temps_geo(0.3, 1.5, 8), 2000, 11, seeds=[SEED0], n_reps=2,
                         precision=rlpt.FP64, swap_interval=1, resync_interval=100, measure_start=1000,
-                        measure_interval=1, n_bins=100, series_len=64)
+                        measure_interval=1, n_bins=100, series_len=64, list_layout=layout)
     compare_fp64(ctx, ors)
     obs = ctx.observables()
     np.testing.assert_allclose(obs["series_e"][0], ors[0].acc["series_e"], rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(obs["series_q"][0], ors[0].acc["series_q"], rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("shared", [0, 1])
-def test_trajectory_fp64_uneven_batch(oracle, shared):
+@pytest.mark.parametrize("shared,layout", [(0, PK), (1, PK), (0, CH), (1, CH)])
+def test_trajectory_fp64_uneven_batch(oracle, shared, layout):
     """Several samples of different N in one launch, both pair schedules."""
     ctx, ors = run_pair(oracle, [24, 16, 33, 12], temps_geo(0.4, 1.5, 5), 150, 5, n_reps=2,
                         precision=rlpt.FP64, shared_pairs=shared, swap_interval=2, resync_interval=30,
-                        measure_start=50, measure_interval=3, n_bins=20)
+                        measure_start=50, measure_interval=3, n_bins=20, list_layout=layout)
     compare_fp64(ctx, ors)
 
 
@@ -188,12 +191,13 @@ def test_edge_cases_fp64(oracle):
         compare_fp64(ctx, ors)
 
 
-def test_trajectory_fp32_until_first_flip(oracle):
+@pytest.mark.parametrize("layout", [PK, CH])
+def test_trajectory_fp32_until_first_flip(oracle, layout):
     """FP32 fields: the same discrete decisions as the FP64 oracle over a short
     run; states agree to FP32 accuracy.  A boundary flip (a uniform within
     FP32 rounding of the acceptance threshold) may separate at most one copy."""
     ctx, ors = run_pair(oracle, [64], temps_geo(0.3, 1.5, 8), 3, 21, n_reps=2, precision=rlpt.FP32,
-                        resync_interval=0, n_bins=10)
+                        resync_interval=0, n_bins=10, list_layout=layout)
     a = ctx.get_state().reshape(ctx.R, 64)
     E, temp_of = ctx.energies()
     bad = 0
