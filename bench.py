@@ -136,6 +136,68 @@ def cpu_baseline(N, temps, n_reps, budget_s, n_threads):
                       f"(N={N}, {og.n_terms} terms), FP64, {el:.1f} s"}
 
 
+def batched(args):
+    """The batched uneven-N configuration: N in {32, 48, 64, 96, 128} x 32
+    samples x 32 temperatures x 2 replicas in one launch per sweep, a segment of
+    10 sweeps captured in a HIP graph and replayed; built-in tiles versus tiles
+    chosen by the autotuner.  Prints its own JSON line (not the headline)."""
+    import torch
+    from paper_2511_13508_amd import rlpt
+
+    Ns, per_N, T, reps = [32, 48, 64, 96, 128], 32, 32, 2
+    temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
+    log("building 160 graphs")
+    graphs = [rlpt.Graph(N, 2511135080 + 200 + 1000 * i + m) for i, N in enumerate(Ns) for m in range(per_N)]
+    copies = len(graphs) * T * reps
+    mode_updates_per_sweep = sum(g.N for g in graphs) * T * reps
+    kw = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=0, measure_start=0,
+              measure_interval=10, n_bins=100)
+
+    def run(tag):
+        ctx = rlpt.Context(graphs, temps, **kw)
+        ctx.init(1)
+        ctx.run_graph(10, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run_graph(10, args.steps // 10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.check()
+        block, cp = ctx.tile()
+        tile = {int(N): int(cp[i * per_N]) for i, N in enumerate(Ns)}
+        v = mode_updates_per_sweep * (args.steps // 10 * 10) / el
+        log(f"{tag}: {v:.4g} mode-updates/s, block {block}, copies per block {tile}")
+        ctx.close()
+        return v, block, tile
+
+    rlpt.tune_clear()
+    v0, b0, t0_ = run("built-in tiles")
+    log("autotuning")
+    t_tune = time.perf_counter()
+    n_trials = rlpt.autotune(graphs, temps, sweeps_per_trial=3, **kw)
+    t_tune = time.perf_counter() - t_tune
+    v1, b1, t1_ = run("tuned tiles")
+    per_N = {}
+    for e in rlpt.tune_entries():
+        N = e["n_modes"]
+        if e["block_threads"] == b1 and e["copies_per_block"] == t1_[N]:
+            per_N[N] = {"ms_per_sweep_alone": e["ms_per_sweep"],
+                        "mode_updates_per_s_alone": N * per_N_copies(per_N_count=32, T=T, reps=reps)
+                        / (e["ms_per_sweep"] * 1e-3)}
+    out = {"metric": "aggregate mode-updates/s, batched uneven N (one launch per sweep, HIP graph)",
+           "value": v1, "unit": "mode-updates/s", "untuned_value": v0, "tuned_vs_untuned": v1 / v0,
+           "copies": copies, "steps": args.steps // 10 * 10, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched uneven N: N in {32,48,64,96,128} x 32 samples x 32 temperatures x "
+                                  "2 replicas, FP32, 10-sweep HIP-graph segments"},
+           "tile_builtin": {"block": b0, "copies_per_block": t0_}, "tile_tuned": {"block": b1, "copies_per_block": t1_},
+           "autotune": {"trials": n_trials, "seconds": t_tune}, "per_N_alone": per_N}
+    print(json.dumps(out), flush=True)
+
+
+def per_N_copies(per_N_count, T, reps):
+    return per_N_count * T * reps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +215,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
+    ap.add_argument("--workload", choices=["n256", "batched"], default="n256",
+                    help="n256: the headline configuration; batched: the uneven-N configuration with autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -168,6 +232,9 @@ def main():
     from paper_2511_13508_amd import rlpt
 
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        batched(args)
+        return
     if args.copy_calibration:
         n = 128 * 1024 * 1024  # 512 MiB of float32 read and 512 MiB written per copy
         src = torch.ones(n, dtype=torch.float32, device="cuda")

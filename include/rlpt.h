@@ -190,6 +190,46 @@ int rlpt_run_graph(rlpt_ctx* ctx, int32_t n_sweeps, int32_t n_segments);
 int rlpt_sweep_timing(rlpt_ctx* ctx, int32_t enable);
 int rlpt_sweep_time_get(rlpt_ctx* ctx, double* total_ms, int64_t* n_launches);
 
+/* ------------------------------------------------------------------------ */
+/* Autotuning of the sweep kernel's launch tile (workgroup size, copies per  */
+/* workgroup).  A process-wide registry holds measured times per sweep; when */
+/* block_threads == 0 and copies_per_block == 0, rlpt_create takes, for the  */
+/* context's mix of N, the workgroup size minimising the summed best times    */
+/* and for each N the best copies per workgroup at that size (built-in       */
+/* defaults for N without entries).                                          */
+/* ------------------------------------------------------------------------ */
+typedef struct rlpt_tile {
+    int32_t n_modes;
+    int32_t precision;        /* RLPT_FP32 / RLPT_FP64 */
+    int32_t shared_pairs;     /* pair schedule */
+    int32_t block_threads;    /* power of two in [64, 1024] */
+    int32_t copies_per_block; /* 1 .. block_threads/64 */
+    int32_t pad;
+    double ms_per_sweep;      /* measured sweep-kernel time per sweep of the tuned context */
+} rlpt_tile;
+
+int rlpt_tune_clear(void);
+int rlpt_tune_set(const rlpt_tile* tile);
+/* Copy up to capacity entries to out (may be NULL); *count = entries held. */
+int rlpt_tune_get(rlpt_tile* out, int32_t capacity, int32_t* count);
+/* One JSON object per line, keyed by the device architecture (e.g. gfx950);
+ * load skips entries recorded on another architecture. */
+int rlpt_tune_save(const char* path);
+int rlpt_tune_load(const char* path);
+
+/* Measure every tile for each distinct N among graphs: one temporary context
+ * per N (the samples of that N, cfg's ladder and precision) in the caller's
+ * workspace (>= rlpt_workspace_size for all graphs), sweeps_per_trial timed
+ * sweeps per tile after one warm-up sweep, recorded in the registry.
+ * *n_trials (may be NULL) receives the number of tiles timed.  Synchronous. */
+int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs,
+                  const double* temps, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                  int32_t sweeps_per_trial, int32_t* n_trials);
+
+/* The launch tile a context uses: workgroup size and, for sample mu, the
+ * copies per workgroup (n_samples entries, may be NULL). */
+int rlpt_tile_of(rlpt_ctx* ctx, int32_t* block_threads, int32_t* copies_per_block);
+
 /* Counters. */
 int rlpt_counters(rlpt_ctx* ctx, int64_t* sweeps_done, int64_t* swaps_done, int64_t* n_meas);
 

@@ -33,10 +33,10 @@ static int hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
-// Launch tile of the sweep kernel for a sample of N modes: threads per
-// workgroup and copies per workgroup (each copy gets (block/64)/copies waves).
-// Entries streamed per two-mode step ~ 2 * 4c/N ~ 2N^2/3; small N packs
-// several copies (one wave each) into a workgroup.
+// Built-in launch tile of the sweep kernel for a sample of N modes: threads
+// per workgroup and copies per workgroup (each copy gets (block/64)/copies
+// waves).  Entries streamed per two-mode step ~ 2 * 4c/N ~ 2N^2/3; small N
+// packs several copies (one wave each) into a workgroup.
 struct Tile {
     int block;
     int copies;
@@ -46,13 +46,6 @@ static Tile default_tile(int N) {
     if (N >= 192) return {256, 1};
     if (N >= 96) return {256, 2};
     return {256, 4};
-}
-
-static Tile tile_for(const rlpt_config& cfg, int N) {
-    Tile t = default_tile(N);
-    if (cfg.block_threads > 0) t.block = cfg.block_threads;
-    if (cfg.copies_per_block > 0) t.copies = cfg.copies_per_block;
-    return t;
 }
 
 }  // namespace rlpt
@@ -81,6 +74,7 @@ struct rlpt_ctx {
     int64_t amp_complex = 0;
     int64_t sweeps_done = 0, swaps_done = 0;
     bool inited = false;
+    std::map<int, int> tile_copies;       // copies per workgroup for each N
     // cached HIP graph of one segment
     hipGraphExec_t exec = nullptr;
     int graph_sweeps = 0;
@@ -300,6 +294,48 @@ int sync_and_flags(rlpt_ctx* c) {
     return RLPT_OK;
 }
 
+// work items: samples ordered by decreasing N (longest work first), copies in
+// chunks of the tile's copies per workgroup; sets the launch description
+int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
+    if (block < 64 || block > 1024 || (block & (block - 1))) return fail(RLPT_E_ARG, "bad workgroup size");
+    std::vector<ItemDev> items;
+    int max_cpi = 1;
+    std::vector<int> order(c->S);
+    for (int s = 0; s < c->S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return c->N[a] > c->N[b2]; });
+    for (int s : order) {
+        auto it_c = copies.find(c->N[s]);
+        int cpw = it_c == copies.end() ? 1 : it_c->second;
+        cpw = std::max(1, std::min(cpw, block / 64));
+        for (int first = 0; first < c->Rc; first += cpw) {
+            ItemDev it{};
+            it.first_copy = s * c->Rc + first;
+            it.n_copies = std::min(cpw, c->Rc - first);
+            it.sample = s;
+            items.push_back(it);
+            max_cpi = std::max(max_cpi, it.n_copies);
+        }
+    }
+    const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N);
+    if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
+    c->items = items;
+    c->tile_copies = copies;
+    c->launch.block_threads = block;
+    c->launch.n_items = (int)items.size();
+    c->launch.max_copies_per_item = max_cpi;
+    c->launch.max_N = c->max_N;
+    c->launch.lds_bytes = lds;
+    return RLPT_OK;
+}
+
+int upload_items(rlpt_ctx* c) {
+    ItemDev* d = const_cast<ItemDev*>(c->cfg.precision == RLPT_FP64 ? c->pd.items : c->pf.items);
+    HIP_TRY(hipMemcpyAsync(d, c->items.data(), c->items.size() * sizeof(ItemDev), hipMemcpyHostToDevice, c->stream),
+            "upload items");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    return RLPT_OK;
+}
+
 void drop_events(rlpt_ctx* c) {
     for (auto* v : {&c->events, &c->spare})
         for (auto& e : *v) {
@@ -440,36 +476,23 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         c->max_N = std::max(c->max_N, g->N);
     }
     c->amp_complex = amp_base;
-    // work items: samples ordered by decreasing N (longest work first), copies
-    // in chunks of the tile's copies-per-workgroup
-    int block = 0, max_cpi = 1;
+    // launch tile: explicit in the config, else from the tune registry, else built in
     {
-        int Nbig = c->max_N;
-        block = tile_for(*cfg, Nbig).block;
-        std::vector<int> order(c->S);
-        for (int s = 0; s < c->S; ++s) order[s] = s;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return c->N[a] > c->N[b2]; });
-        for (int s : order) {
-            int cpw = tile_for(*cfg, c->N[s]).copies;
-            cpw = std::max(1, std::min(cpw, block / 64));
-            for (int first = 0; first < c->Rc; first += cpw) {
-                ItemDev it{};
-                it.first_copy = s * c->Rc + first;
-                it.n_copies = std::min(cpw, c->Rc - first);
-                it.sample = s;
-                c->items.push_back(it);
-                max_cpi = std::max(max_cpi, it.n_copies);
-            }
+        int block = 0;
+        std::map<int, int> copies;
+        std::map<int, int> counts;
+        for (int s = 0; s < c->S; ++s) counts[c->N[s]] += 1;
+        if (cfg->block_threads > 0 || cfg->copies_per_block > 0 ||
+            !tune_choose(counts, cfg->precision, cfg->shared_pairs, &block, &copies)) {
+            block = cfg->block_threads > 0 ? cfg->block_threads : default_tile(c->max_N).block;
+            for (const auto& nc : counts)
+                copies[nc.first] = cfg->copies_per_block > 0 ? cfg->copies_per_block : default_tile(nc.first).copies;
         }
-    }
-    c->launch.block_threads = block;
-    c->launch.n_items = (int)c->items.size();
-    c->launch.max_copies_per_item = max_cpi;
-    c->launch.max_N = c->max_N;
-    c->launch.lds_bytes = sweep_lds_bytes(cfg->precision, block, max_cpi, c->max_N);
-    if (c->launch.lds_bytes > 64 * 1024) {
-        delete c;
-        return fail(RLPT_E_ARG, "sweep tile needs more LDS than a CU has; use fewer copies per block");
+        rc = build_items(c, block, copies);
+        if (rc) {
+            delete c;
+            return rc;
+        }
     }
     c->sh.n_samples = c->S;
     c->sh.n_temps = c->T;
@@ -493,7 +516,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         if (e == hipSuccess) e = upload(b, off, v, c->stream);
     };
     up(r.samples, c->samples);
-    up(r.items, c->items);
+    up(r.items, c->items);  // sized for one item per copy (the finest tile)
     up(r.mode_start, ms);
     up(r.idx, idx);
     if (cfg->precision == RLPT_FP64) up(r.J, J64);
@@ -824,6 +847,67 @@ int rlpt_observables(rlpt_ctx* c, rlpt_obs* o) {
             }
     }
     return rc;
+}
+
+int rlpt_tile_of(rlpt_ctx* c, int32_t* block_threads, int32_t* copies_per_block) {
+    if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    if (block_threads) *block_threads = c->launch.block_threads;
+    if (copies_per_block)
+        for (int s = 0; s < c->S; ++s) copies_per_block[s] = c->tile_copies.count(c->N[s]) ? c->tile_copies[c->N[s]] : 1;
+    return RLPT_OK;
+}
+
+int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs, const double* temps,
+                  void* d_workspace, size_t workspace_bytes, void* hip_stream, int32_t sweeps_per_trial,
+                  int32_t* n_trials) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if ((rc = check_graphs(graphs, n_graphs))) return rc;
+    if (sweeps_per_trial < 1) return fail(RLPT_E_ARG, "sweeps_per_trial must be >= 1");
+    std::map<int, std::vector<const rlpt_graph*>> byN;
+    for (int i = 0; i < n_graphs; ++i) byN[graphs[i]->N].push_back(graphs[i]);
+    rlpt_config c2 = *cfg;
+    c2.swap_interval = 1 << 30;  // timing covers sweeps only: one launch per trial
+    c2.resync_interval = 0;
+    c2.measure_interval = 0;
+    c2.block_threads = 256;
+    c2.copies_per_block = 1;
+    int trials = 0;
+    for (auto& kv : byN) {
+        rlpt_ctx* c = nullptr;
+        rc = rlpt_create(&c2, kv.second.data(), (int32_t)kv.second.size(), temps, d_workspace, workspace_bytes,
+                         hip_stream, &c);
+        if (rc) return rc;
+        rc = rlpt_init(c, 1);
+        for (int b = 64; b <= 1024 && rc == RLPT_OK; b *= 2)
+            for (int cp = 1; cp <= b / 64 && rc == RLPT_OK; cp *= 2) {
+                std::map<int, int> copies{{kv.first, cp}};
+                if (build_items(c, b, copies) != RLPT_OK) continue;  // LDS limit
+                if ((rc = upload_items(c))) break;
+                if ((rc = rlpt_sweep(c, 1))) break;
+                c->timing = true;
+                if ((rc = rlpt_sweep(c, sweeps_per_trial))) break;
+                double ms = 0;
+                int64_t n = 0;
+                rc = rlpt_sweep_time_get(c, &ms, &n);
+                c->timing = false;
+                if (rc) break;
+                rlpt_tile t{};
+                t.n_modes = kv.first;
+                t.precision = cfg->precision;
+                t.shared_pairs = cfg->shared_pairs;
+                t.block_threads = b;
+                t.copies_per_block = cp;
+                t.ms_per_sweep = ms / sweeps_per_trial;
+                tune_record(t);
+                ++trials;
+            }
+        int rc2 = rlpt_destroy(c);
+        if (rc) return rc;
+        if (rc2) return rc2;
+    }
+    if (n_trials) *n_trials = trials;
+    return RLPT_OK;
 }
 
 int rlpt_tau_int(const double* x, int64_t n, double c_window, double* tau, int64_t* window) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,10 @@ enum ListLayout { kLayoutPacked = 1, kLayoutChunked = 2 };
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
+
+void tune_record(const rlpt_tile& t);
+bool tune_choose(const std::map<int, int>& counts, int precision, int shared, int* block,
+                 std::map<int, int>* copies);
 
 // ----------------------------------------------------------------- device-side descriptors
 struct SampleDev {

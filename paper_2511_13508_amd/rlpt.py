@@ -28,7 +28,8 @@ EXPORTS = [
     "rlpt_init", "rlpt_sweep", "rlpt_swap", "rlpt_resync", "rlpt_check", "rlpt_run_graph", "rlpt_sweep_timing",
     "rlpt_sweep_time_get", "rlpt_counters",
     "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64", "rlpt_local_fields",
-    "rlpt_pair_dE", "rlpt_observables", "rlpt_tau_int",
+    "rlpt_pair_dE", "rlpt_observables", "rlpt_tau_int", "rlpt_tune_clear", "rlpt_tune_set", "rlpt_tune_get",
+    "rlpt_tune_save", "rlpt_tune_load", "rlpt_autotune", "rlpt_tile_of",
 ]
 
 
@@ -36,6 +37,12 @@ class RlptError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"librlpt error {code}: {msg}")
         self.code = code
+
+
+class Tile(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("precision", C.c_int32), ("shared_pairs", C.c_int32),
+                ("block_threads", C.c_int32), ("copies_per_block", C.c_int32), ("pad", C.c_int32),
+                ("ms_per_sweep", C.c_double)]
 
 
 class GraphDesc(C.Structure):
@@ -110,6 +117,13 @@ def lib() -> C.CDLL:
         "rlpt_pair_dE": ([P, i32, i32, P, P, P, P, P], C.c_int),
         "rlpt_observables": ([P, P], C.c_int),
         "rlpt_tau_int": ([P, i64, d, P, P], C.c_int),
+        "rlpt_tune_clear": ([], C.c_int),
+        "rlpt_tune_set": ([P], C.c_int),
+        "rlpt_tune_get": ([P, i32, P], C.c_int),
+        "rlpt_tune_save": ([C.c_char_p], C.c_int),
+        "rlpt_tune_load": ([C.c_char_p], C.c_int),
+        "rlpt_autotune": ([P, P, i32, P, P, C.c_size_t, P, i32, P], C.c_int),
+        "rlpt_tile_of": ([P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -252,6 +266,13 @@ class Context:
         _check(lib().rlpt_sweep_time_get(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def tile(self):
+        """(threads per workgroup, copies per workgroup of each sample) of the sweep launch."""
+        b = C.c_int32()
+        cp = np.zeros(self.S, dtype=np.int32)
+        _check(lib().rlpt_tile_of(self._h, C.byref(b), _ptr(cp)))
+        return b.value, cp
+
     def counters(self):
         a, b, m = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().rlpt_counters(self._h, C.byref(a), C.byref(b), C.byref(m)))
@@ -306,6 +327,51 @@ class Context:
         o = Obs(**{f: _ptr(out[f]).value for f in OBS_FIELDS})
         _check(lib().rlpt_observables(self._h, C.byref(o)))
         return out
+
+
+def tune_clear():
+    _check(lib().rlpt_tune_clear())
+
+
+def tune_set(n_modes, precision, shared_pairs, block_threads, copies_per_block, ms_per_sweep):
+    t = Tile(n_modes=n_modes, precision=precision, shared_pairs=shared_pairs, block_threads=block_threads,
+             copies_per_block=copies_per_block, ms_per_sweep=ms_per_sweep)
+    _check(lib().rlpt_tune_set(C.byref(t)))
+
+
+def tune_entries() -> list:
+    n = C.c_int32()
+    _check(lib().rlpt_tune_get(None, 0, C.byref(n)))
+    arr = (Tile * max(n.value, 1))()
+    _check(lib().rlpt_tune_get(arr, n.value, C.byref(n)))
+    return [{f: getattr(arr[i], f) for f, _ in Tile._fields_ if f != "pad"} for i in range(n.value)]
+
+
+def tune_save(path: str):
+    _check(lib().rlpt_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(lib().rlpt_tune_load(path.encode()))
+
+
+def autotune(graphs, temps, config: Config | None = None, sweeps_per_trial: int = 3, device: str = "cuda:0",
+             **kw) -> int:
+    """Time every sweep tile for each N among graphs (fills the tile registry); returns trials run."""
+    import torch
+
+    cfg = config if config is not None else default_config(**kw)
+    temps = np.ascontiguousarray(temps, dtype=np.float64)
+    arr = (C.c_void_p * len(graphs))(*[g._h.value for g in graphs])
+    nbytes = C.c_size_t()
+    _check(lib().rlpt_workspace_size(C.byref(cfg), arr, len(graphs), C.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+    stream = torch.cuda.Stream(device=device)
+    n = C.c_int32()
+    _check(lib().rlpt_autotune(C.byref(cfg), arr, len(graphs), _ptr(temps), C.c_void_p(ws.data_ptr()), nbytes.value,
+                               C.c_void_p(stream.cuda_stream), sweeps_per_trial, C.byref(n)))
+    stream.synchronize()
+    return n.value
 
 
 def tau_int(x, c_window: float = 6.0):

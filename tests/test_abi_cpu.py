@@ -103,3 +103,24 @@ def test_jackknife_of_mean_is_standard_error():
     m, e = analysis.jackknife_mean_err(v)
     np.testing.assert_allclose(m, v.mean(0))
     np.testing.assert_allclose(e, v.std(0, ddof=1) / math.sqrt(50), rtol=1e-12)
+
+
+def test_tune_registry_roundtrip(tmp_path):
+    rlpt.tune_clear()
+    rlpt.tune_set(64, rlpt.FP32, 0, 256, 4, 1.5)
+    rlpt.tune_set(64, rlpt.FP32, 0, 256, 4, 1.25)  # same key: replaced
+    rlpt.tune_set(128, rlpt.FP32, 0, 512, 2, 3.0)
+    assert len(rlpt.tune_entries()) == 2
+    p = str(tmp_path / "tiles.jsonl")
+    rlpt.tune_save(p)
+    rlpt.tune_clear()
+    assert rlpt.tune_entries() == []
+    rlpt.tune_load(p)
+    e = sorted(rlpt.tune_entries(), key=lambda d: d["n_modes"])
+    assert [(d["n_modes"], d["block_threads"], d["copies_per_block"]) for d in e] == [(64, 256, 4), (128, 512, 2)]
+    assert e[0]["ms_per_sweep"] == pytest.approx(1.25)
+    with pytest.raises(rlpt.RlptError):
+        rlpt.tune_set(64, rlpt.FP32, 0, 100, 1, 1.0)  # not a power of two
+    with pytest.raises(rlpt.RlptError):
+        rlpt.tune_set(64, rlpt.FP32, 0, 128, 4, 1.0)  # more copies than waves
+    rlpt.tune_clear()
