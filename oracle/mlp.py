@@ -1,0 +1,236 @@
+"""FP64 reference of the learned global proposal (test infrastructure only).
+
+Not part of the paper, which is silent on learned moves; this is the plain
+definition of the construction the library implements, so that its kernels
+can be checked value by value:
+
+coordinates on the constraint surface sum |a_k|^4 = N (eq. SmoothedCubic):
+  w_k = |a_k|^4 / N (a point of the simplex), y = alr(w) = log(w_k / w_{N-1}),
+  k < N-1, and the phases psi_k = arg a_k.  The flat reference measure of
+  eq. ProbDistr gives w ~ Dirichlet(1/2, ..., 1/2) (squares of a uniform
+  point of the sphere), so its density in (y, psi) is proportional to
+  prod_k w_k^(1/2) (Dirichlet density prod w^(-1/2) times the alr Jacobian
+  prod w).
+network: features = Re/Im of a rotated so that a_0 is real and positive;
+  h1 = SiLU(x W1 + b1), h2 = SiLU(h1 W2 + b2), o = h2 W3 + b3; weights rounded
+  to bfloat16 (round to nearest even), arithmetic in FP64 here.
+proposal: a K-component diagonal Gaussian mixture over the displacement
+  delta = (dy, dpsi) in R^(2N-1): weights softmax(o[:K]), means o[K:K+KD],
+  widths sigma = smax * sigmoid(o[K+KD:]) with smax = 2 for y and pi/2 for
+  psi; a step scale s multiplies means and widths.  Phase displacements are
+  wrapped: their density is the sum over n of N(dpsi + 2 pi n).
+acceptance: min(1, exp(-beta dH) rho(y')/rho(y) q(y,psi|y',psi')/q(y',psi'|y,psi)).
+training loss: the mean negative log-likelihood of observed displacements
+  under the unwrapped mixture (any parameters give an exact proposal).
+Pins (tests/test_oracle_mlp.py): finite differences of the loss, the
+single-Gaussian closed form, torch's bfloat16 rounding, the proposal density
+integrating to one, and the infinite-temperature closed forms of the chain.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import oracle as O
+
+LOG2PI = math.log(2.0 * math.pi)
+SMAX_Y = 2.0
+SMAX_PSI = math.pi / 2.0
+TAG_LEARN = 0x4C4541524E  # "LEARN"
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round to bfloat16 (nearest, ties to even) and return as float64."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def sizes(N: int, K: int) -> tuple:
+    D = 2 * N - 1
+    return 2 * N, D, K * (2 * D + 1)
+
+
+def features(a: np.ndarray) -> np.ndarray:
+    """[..., N] complex -> [..., 2N]: rotate so that a_0 is real positive."""
+    a = np.asarray(a)
+    rot = np.exp(-1j * np.angle(a[..., :1]))
+    b = a * rot
+    return np.concatenate([b.real, b.imag], axis=-1)
+
+
+def silu(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def forward(params, X):
+    """params: dict W1 [2N,H], b1, W2 [H,H], b2, W3 [H,Out], b3 (weights used as given)."""
+    p1 = X @ params["W1"] + params["b1"]
+    h1 = silu(p1)
+    p2 = h1 @ params["W2"] + params["b2"]
+    h2 = silu(p2)
+    o = h2 @ params["W3"] + params["b3"]
+    return o, (X, p1, h1, p2, h2)
+
+
+def mixture(o: np.ndarray, N: int, K: int):
+    """Split outputs [..., Out] into log-weights [..., K], means and widths [..., K, D]."""
+    D = 2 * N - 1
+    logits = o[..., :K]
+    mu = o[..., K:K + K * D].reshape(o.shape[:-1] + (K, D))
+    s = o[..., K + K * D:].reshape(o.shape[:-1] + (K, D))
+    smax = np.concatenate([np.full(N - 1, SMAX_Y), np.full(N, SMAX_PSI)])
+    sigma = smax / (1.0 + np.exp(-s))
+    lw = logits - np.logaddexp.reduce(logits, axis=-1, keepdims=True)
+    return lw, mu, sigma, smax
+
+
+def nll_and_grad(o: np.ndarray, delta: np.ndarray, N: int, K: int):
+    """Mean negative log-likelihood of delta [B, D] under the unwrapped
+    mixture of o [B, Out], and its gradient with respect to o."""
+    lw, mu, sigma, smax = mixture(o, N, K)
+    z = (delta[:, None, :] - mu) / sigma
+    ell = lw - np.sum(np.log(sigma) + 0.5 * LOG2PI + 0.5 * z * z, axis=-1)
+    logp = np.logaddexp.reduce(ell, axis=-1)
+    r = np.exp(ell - logp[:, None])
+    B = o.shape[0]
+    pi = np.exp(lw)
+    d_logits = (pi - r) / B
+    d_mu = -(r[:, :, None] * z / sigma) / B
+    d_s = -(r[:, :, None] * (z * z - 1.0) * (1.0 - sigma / smax)) / B
+    g = np.concatenate([d_logits, d_mu.reshape(B, -1), d_s.reshape(B, -1)], axis=1)
+    return float(-np.mean(logp)), g
+
+
+def backward(params, cache, dO):
+    X, p1, h1, p2, h2 = cache
+    grads = {"W3": h2.T @ dO, "b3": dO.sum(0)}
+    dh2 = dO @ params["W3"].T
+    s2 = 1.0 / (1.0 + np.exp(-p2))
+    dp2 = dh2 * s2 * (1.0 + p2 * (1.0 - s2))
+    grads["W2"] = h1.T @ dp2
+    grads["b2"] = dp2.sum(0)
+    dh1 = dp2 @ params["W2"].T
+    s1 = 1.0 / (1.0 + np.exp(-p1))
+    dp1 = dh1 * s1 * (1.0 + p1 * (1.0 - s1))
+    grads["W1"] = X.T @ dp1
+    grads["b1"] = dp1.sum(0)
+    return grads
+
+
+def loss_and_grads(params, a_before, a_after, N, K):
+    """Training loss on pairs of configurations and its parameter gradients."""
+    X = features(a_before)
+    o, cache = forward(params, X)
+    delta = displacement(a_before, a_after)
+    L, dO = nll_and_grad(o, delta, N, K)
+    return L, backward(params, cache, dO)
+
+
+# ----------------------------------------------------------------- coordinates
+def coords(a: np.ndarray):
+    """(y [N-1], psi [N], w [N]) of a configuration on sum |a|^4 = N."""
+    N = a.shape[-1]
+    w = np.abs(a) ** 4 / N
+    y = np.log(w[..., :-1]) - np.log(w[..., -1:])
+    return y, np.angle(a), w
+
+
+def from_coords(y: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    N = psi.shape[-1]
+    e = np.concatenate([np.exp(y), np.ones(y.shape[:-1] + (1,))], axis=-1)
+    w = e / e.sum(axis=-1, keepdims=True)
+    return (N * w) ** 0.25 * np.exp(1j * psi)
+
+
+def wrap(x):
+    """Representative in (-pi, pi]."""
+    return x - 2.0 * math.pi * np.ceil((x - math.pi) / (2.0 * math.pi))
+
+
+def displacement(a, b):
+    """delta = (y(b) - y(a), wrap(psi(b) - psi(a)))."""
+    ya, pa, _ = coords(a)
+    yb, pb, _ = coords(b)
+    return np.concatenate([yb - ya, wrap(pb - pa)], axis=-1)
+
+
+def log_ref(w):
+    """log of the reference density in (y, psi) up to a constant: 1/2 sum log w."""
+    return 0.5 * np.sum(np.log(w), axis=-1)
+
+
+def log_q(o, dy, dpsi, N, K, scale):
+    """log density [B] of proposal displacements (dy [B, N-1], dpsi [B, N])
+    under the mixtures of outputs o [B, Out] with step scale s: unwrapped in
+    y, wrapped (|n| <= 3 images) in psi."""
+    lw, mu, sigma, _ = mixture(o, N, K)
+    mu, sigma = scale * mu, scale * sigma
+    dy, dpsi = dy[:, None, :], dpsi[:, None, :]
+    ly = -np.sum(np.log(sigma[..., :N - 1]) + 0.5 * LOG2PI + 0.5 * ((dy - mu[..., :N - 1]) / sigma[..., :N - 1]) ** 2,
+                 axis=-1)
+    d = wrap(dpsi - mu[..., N - 1:])
+    n = np.arange(-3, 4).reshape(7, 1, 1, 1)
+    t = (d[None] + 2.0 * math.pi * n) / sigma[None, ..., N - 1:]
+    lp = np.log(np.sum(np.exp(-0.5 * t * t), axis=0)) - np.log(sigma[..., N - 1:]) - 0.5 * LOG2PI
+    return np.logaddexp.reduce(lw + ly + np.sum(lp, axis=-1), axis=-1)
+
+
+# ----------------------------------------------------------------- draws and the move
+def draws(run_seed: int, move: int, copy: int, D: int):
+    """Gaussians g[D] and the component and acceptance uniforms of one move:
+    Philox block i (i < ceil(D/2)) gives g[2i] = BM(w0, w1), g[2i+1] = BM(w2, w3);
+    block ceil(D/2) gives the component uniform (w0) and the acceptance uniform (w1)."""
+    nb = (D + 1) // 2
+    g = np.zeros(2 * nb)
+    for i in range(nb):
+        w = O.philox([i, move, copy, 0], [run_seed, TAG_LEARN])
+        for h in range(2):
+            u1 = 1.0 - (int(w[2 * h]) >> 11) * 2.0 ** -53
+            u2 = (int(w[2 * h + 1]) >> 11) * 2.0 ** -53
+            g[2 * i + h] = math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+    w = O.philox([nb, move, copy, 0], [run_seed, TAG_LEARN])
+    return g[:D], (int(w[0]) >> 11) * 2.0 ** -53, (int(w[1]) >> 11) * 2.0 ** -53
+
+
+def propose(params, a, N, K, scale, g, u_comp):
+    """Batched proposal: a [B, N], g [B, D], u_comp [B] -> (a_new, delta, o_fwd, component)."""
+    o, _ = forward(params, features(a))
+    lw, mu, sigma, _ = mixture(o, N, K)
+    cw = np.cumsum(np.exp(lw), axis=-1)
+    m = np.minimum(np.sum(cw <= u_comp[:, None], axis=-1), K - 1)
+    rows = np.arange(a.shape[0])
+    delta = scale * mu[rows, m] + scale * sigma[rows, m] * g
+    y, psi, _ = coords(a)
+    a_new = from_coords(y + delta[:, :N - 1], psi + delta[:, N - 1:])
+    return a_new, delta, o, m
+
+
+def move_log_alpha(params, a, dH, beta, N, K, scale, g, u_comp, energy=None):
+    """Batched learned move.  Returns (a_new, log acceptance ratio, parts).
+    dH: callable a_new -> energy change per row, or None for infinite temperature."""
+    a_new, delta, o_fwd, m = propose(params, a, N, K, scale, g, u_comp)
+    o_rev, _ = forward(params, features(a_new))
+    lq_f = log_q(o_fwd, delta[:, :N - 1], delta[:, N - 1:], N, K, scale)
+    lq_r = log_q(o_rev, -delta[:, :N - 1], -delta[:, N - 1:], N, K, scale)
+    _, _, w = coords(a)
+    _, _, w2 = coords(a_new)
+    dref = log_ref(w2) - log_ref(w)
+    de = np.zeros(a.shape[0]) if dH is None else dH(a_new)
+    la = -beta * de + dref + lq_r - lq_f
+    return a_new, la, {"dH": de, "lq_f": lq_f, "lq_r": lq_r, "dlogref": dref, "component": m}
+
+
+def init_params(N, H, K, rng, out_scale=0.01):
+    In, D, Out = sizes(N, K)
+    return {"W1": rng.standard_normal((In, H)) / math.sqrt(In), "b1": np.zeros(H),
+            "W2": rng.standard_normal((H, H)) / math.sqrt(H), "b2": np.zeros(H),
+            "W3": out_scale * rng.standard_normal((H, Out)) / math.sqrt(H), "b3": np.zeros(Out)}
+
+
+def rounded(params):
+    """Weights as the GPU uses them: bfloat16 matrices, FP32 biases."""
+    return {k: (bf16_round(v) if k.startswith("W") else np.asarray(v, np.float32).astype(np.float64))
+            for k, v in params.items()}

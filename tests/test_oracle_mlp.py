@@ -1,0 +1,149 @@
+"""Pins of the FP64 learned-proposal reference (oracle/mlp.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from tests import brute
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.uniform(-8, 8, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.bf16_round(x), ref)
+
+
+def test_single_gaussian_nll_closed_form():
+    N, K = 3, 1
+    D = 2 * N - 1
+    rng = np.random.default_rng(1)
+    o = rng.standard_normal((4, K * (2 * D + 1)))
+    delta = rng.standard_normal((4, D))
+    L, _ = M.nll_and_grad(o, delta, N, K)
+    _, mu, sigma, _ = M.mixture(o, N, K)
+    ref = np.mean(np.sum(np.log(sigma[:, 0]) + 0.5 * math.log(2 * math.pi)
+                         + 0.5 * ((delta - mu[:, 0]) / sigma[:, 0]) ** 2, axis=1))
+    assert L == pytest.approx(ref, rel=1e-12)
+
+
+def test_nll_gradient_finite_differences():
+    N, K = 3, 3
+    rng = np.random.default_rng(2)
+    _, D, Out = M.sizes(N, K)
+    o = rng.standard_normal((5, Out))
+    delta = rng.standard_normal((5, D)) * 0.5
+    L, g = M.nll_and_grad(o, delta, N, K)
+    h = 1e-6
+    for idx in [(0, 0), (1, 2), (2, K + 3), (3, K + K * D + 4), (4, Out - 1)]:
+        op, om = o.copy(), o.copy()
+        op[idx] += h
+        om[idx] -= h
+        fd = (M.nll_and_grad(op, delta, N, K)[0] - M.nll_and_grad(om, delta, N, K)[0]) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_parameter_gradients_finite_differences(oracle):
+    N, H, K = 4, 12, 2
+    rng = np.random.default_rng(3)
+    params = M.init_params(N, H, K, rng, out_scale=0.5)
+    a = np.array([oracle.init_copy(N, 5, c) for c in range(6)])
+    b = np.array([oracle.init_copy(N, 6, c) for c in range(6)])
+    L, grads = M.loss_and_grads(params, a, b, N, K)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = params[name].reshape(-1)
+        for i in rng.choice(flat.size, 4, replace=False):
+            old = flat[i]
+            flat[i] = old + h
+            Lp, _ = M.loss_and_grads(params, a, b, N, K)
+            flat[i] = old - h
+            Lm, _ = M.loss_and_grads(params, a, b, N, K)
+            flat[i] = old
+            assert grads[name].reshape(-1)[i] == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5, abs=1e-8), name
+
+
+def test_coordinates_roundtrip_and_constraint(oracle):
+    a = np.array([oracle.init_copy(7, 3, c) for c in range(5)])
+    y, psi, w = M.coords(a)
+    b = M.from_coords(y, psi)
+    np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(np.sum(np.abs(b) ** 4, axis=1), 7.0, rtol=1e-13)
+    np.testing.assert_allclose(w.sum(axis=1), 1.0, rtol=1e-13)
+
+
+def test_wrapped_proposal_density_integrates_to_one():
+    """N = 2: one y coordinate and two phases; integrate q over R x T^2 on a grid."""
+    N, K = 2, 2
+    rng = np.random.default_rng(4)
+    _, D, Out = M.sizes(N, K)
+    o = rng.standard_normal((1, Out))
+    o[0, K + K * D:] += 1.0  # wide phase components: the wrapping matters
+    ys = np.linspace(-14, 14, 801)
+    ps = np.linspace(-math.pi, math.pi, 97)[:-1]
+    Y, P1, P2 = np.meshgrid(ys, ps, ps, indexing="ij")
+    dy = Y.reshape(-1, 1)
+    dpsi = np.stack([P1.reshape(-1), P2.reshape(-1)], axis=1)
+    lq = M.log_q(np.repeat(o, dy.shape[0], axis=0), dy, dpsi, N, K, 1.0)
+    total = np.exp(lq).sum() * (ys[1] - ys[0]) * (ps[1] - ps[0]) ** 2
+    assert total == pytest.approx(1.0, rel=2e-3)
+
+
+def _chain(oracle, N, beta, graph, n_chains, n_moves, scale, seed, H=16, K=2):
+    """Learned moves only, from exact infinite-temperature draws.  Returns the
+    history of states, of energies (None at beta = 0) and the acceptance rate."""
+    rng = np.random.default_rng(seed)
+    params = M.init_params(N, H, K, rng, out_scale=1.0)
+    a = np.array([oracle.init_copy(N, seed, c) for c in range(n_chains)])
+    _, D, _ = M.sizes(N, K)
+    acc = 0
+    hist, ehist = [], []
+    q = None if graph is None else graph.quads.astype(np.int64)
+    E = None if graph is None else brute.energy_batch(q, graph.J, a)
+    for t in range(n_moves):
+        g = rng.standard_normal((n_chains, D))
+        uc = rng.uniform(size=n_chains)
+        ua = rng.uniform(size=n_chains)
+        dH = None if graph is None else (lambda an: brute.energy_batch(q, graph.J, an) - E)  # noqa: E731
+        an, la, parts = M.move_log_alpha(params, a, dH, beta, N, K, scale, g, uc)
+        ok = np.log(ua) < la
+        a = np.where(ok[:, None], an, a)
+        if graph is not None:
+            E = np.where(ok, E + parts["dH"], E)
+            ehist.append(E.copy())
+        acc += ok.sum()
+        hist.append(a.copy())
+    return np.array(hist), (np.array(ehist) if ehist else None), acc / (n_chains * n_moves)
+
+
+def test_learned_chain_keeps_infinite_temperature_law(oracle):
+    """Starting from exact beta = 0 draws, learned moves alone must keep the
+    closed-form marginals; a wrong reference-density (Jacobian) term would not."""
+    N = 4
+    hist, _, acc = _chain(oracle, N, 0.0, None, n_chains=3000, n_moves=30, scale=0.3, seed=7)
+    assert 0.1 < acc < 0.95
+    ref = brute.beta0_moments(N)
+    u = np.abs(hist[10:]) ** 2
+    per_t = u.mean(axis=(1, 2))
+    assert per_t.mean() == pytest.approx(ref["E|a|^2"], abs=5 * u.std() / math.sqrt(3000 * N))
+    u4 = (u ** 4).mean(axis=(1, 2))
+    assert u4.mean() == pytest.approx(ref["E|a|^8"], abs=5 * (u ** 4).std() / math.sqrt(3000 * N))
+    np.testing.assert_allclose(np.sum(np.abs(hist[-1]) ** 4, axis=1), N, rtol=1e-10)
+
+
+@pytest.mark.slow
+def test_learned_chain_samples_boltzmann_law(oracle):
+    """At finite beta, learned moves alone (an untrained network) reproduce
+    the importance-sampling reference <E> of the N = 4 comb (one term)."""
+    N = 4
+    g = oracle.Graph(N, 0, oracle.OMEGA_COMB)
+    g.J = np.array([2.0])
+    _, E, acc = _chain(oracle, N, 1.0, g, n_chains=1000, n_moves=900, scale=0.4, seed=8)
+    ref, err = brute.importance_reference(g.quads.astype(np.int64), g.J, N, [1.0], M=1000000, seed=9)
+    per_chain = E[400:].mean(axis=0)
+    se = per_chain.std() / math.sqrt(len(per_chain))
+    assert 0.2 < acc < 0.9
+    assert per_chain.mean() == pytest.approx(ref["E"][0], abs=4 * math.sqrt(se ** 2 + err["E"][0] ** 2))
