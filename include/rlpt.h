@@ -124,7 +124,12 @@ typedef struct rlpt_config {
                                  RLPT_LAYOUT_PACKED (8 B/entry, any N) or RLPT_LAYOUT_CHUNKED
                                  (entries grouped by partner mode in chunks of 4 sharing one
                                  partner byte, 6.25 B/entry, N <= 256) */
-    int32_t pad;
+    /* learned global proposal (FP32 contexts, one N for all samples); 0 nets = off */
+    int32_t mlp_nets;         /* networks, one per learned temperature slot */
+    int32_t mlp_hidden;       /* width of the two hidden SiLU layers (default 256) */
+    int32_t mlp_components;   /* Gaussian-mixture components, 1..8 (default 4) */
+    int32_t mlp_capacity;     /* training pairs stored per network (default 100000) */
+    int32_t mlp_batch;        /* training minibatch (default 512) */
 } rlpt_config;
 
 /* Fill *cfg with defaults: FP32, per-copy pairs, swap every sweep, FP64
@@ -290,6 +295,49 @@ typedef struct rlpt_obs {
 /* Copy the accumulators to host (synchronises).  Returns RLPT_E_STATE if a
  * drift / NaN failure was recorded. */
 int rlpt_observables(rlpt_ctx* ctx, rlpt_obs* out);
+
+/* ------------------------------------------------------------------------ */
+/* Learned global proposal (not in the paper; the method's moves stay as they  */
+/* are and keep running every sweep).  Coordinates on sum|a|^4 = N: w =      */
+/* |a|^4/N, y = log(w_k/w_{N-1}) (k < N-1), phases psi.  A network per        */
+/* temperature slot maps Re/Im of a (rotated so a_0 is real positive) through  */
+/* two SiLU layers to a K-component diagonal Gaussian mixture over (dy, dpsi); */
+/* widths 2*sigmoid (y) and (pi/2)*sigmoid (psi), all scaled by step_scale;    */
+/* phases wrap.  Exact Metropolis-Hastings with the reference density          */
+/* prod w^(1/2) in (y, psi) (the flat measure of eq. ProbDistr).  Weights are  */
+/* bfloat16 in the GEMMs with FP32 accumulation and FP32 masters; training is */
+/* Adam on the mean negative log-likelihood of harvested displacements.       */
+/* Random numbers: Philox keyed (run_seed, "LEARN") at (i, round, copy, 0).   */
+/* ------------------------------------------------------------------------ */
+
+/* Initialise weights (seeded), Adam moments and counters; temp_index[mlp_nets]
+ * gives each network's temperature slot. */
+int rlpt_mlp_setup(rlpt_ctx* ctx, const int32_t* temp_index, uint64_t seed);
+/* Parameters per network (W1 [2N][H], b1, W2 [H][H], b2, W3 [H][Out], b3,
+ * row-major, concatenated) and outputs per configuration. */
+int rlpt_mlp_n_params(rlpt_ctx* ctx, int64_t* n_params, int32_t* n_outputs);
+int rlpt_mlp_set_params(rlpt_ctx* ctx, int32_t net, const float* params);
+int rlpt_mlp_get_params(rlpt_ctx* ctx, int32_t net, float* params);
+/* Store n explicit training pairs (interleaved complex, [n][N] each) for one network. */
+int rlpt_mlp_set_pairs(rlpt_ctx* ctx, int32_t net, int32_t n, const double* before, const double* after);
+/* rounds x (record the copies at each network's temperature, `lag` sweeps
+ * without swaps, record the same copies again).  Async-safe: synchronises. */
+int rlpt_mlp_harvest(rlpt_ctx* ctx, int32_t rounds, int32_t lag);
+/* Adam steps (lr) on random minibatches; mean_loss[mlp_nets] of the last step (may be NULL). */
+int rlpt_mlp_train(rlpt_ctx* ctx, int32_t steps, double lr, double* mean_loss);
+/* Test hooks: outputs of network `net` on the first n stored "before"
+ * configurations; loss and gradient on the first mlp_batch stored pairs. */
+int rlpt_mlp_forward(rlpt_ctx* ctx, int32_t net, int32_t n, double* out);
+int rlpt_mlp_loss_grad(rlpt_ctx* ctx, int32_t net, double* loss, float* grad);
+/* Learned rounds after every sweep (0 = off) with the given step scale in (0, 1]. */
+int rlpt_mlp_enable(rlpt_ctx* ctx, int32_t moves_per_sweep, double step_scale);
+/* One learned round of every network now (async). */
+int rlpt_mlp_move(rlpt_ctx* ctx, double step_scale);
+/* Accepted and proposed learned moves per network. */
+int rlpt_mlp_stats(rlpt_ctx* ctx, double* acc, double* tries);
+/* Last round of network `net`: log acceptance ratio [S*reps], copies [S*reps],
+ * proposals [S*reps][N] interleaved complex (each may be NULL). */
+int rlpt_mlp_last_move(rlpt_ctx* ctx, int32_t net, double* log_alpha, int32_t* copies, double* proposal);
 
 /* ------------------------------------------------------------------------ */
 /* Analysis helpers (host).                                                  */

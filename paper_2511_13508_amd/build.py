@@ -36,11 +36,11 @@ def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs = []
-    for src in ("kernels.hip",):
+    for src in ("kernels.hip", "mlp.hip"):
         obj = os.path.join(BUILD_DIR, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    for src in ("graph.cpp", "api.cpp", "tune.cpp"):
+    for src in ("graph.cpp", "api.cpp", "tune.cpp", "mlp_api.cpp"):
         obj = os.path.join(BUILD_DIR, src + ".o")
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.hpp"
+#include "context.hpp"
 
 namespace rlpt {
 
@@ -52,44 +52,6 @@ static Tile default_tile(int N) {
 
 using namespace rlpt;
 
-struct rlpt_ctx {
-    rlpt_config cfg{};
-    hipStream_t stream = nullptr;
-    int S = 0, T = 0, reps = 0, Rc = 0, n_copies = 0, max_N = 0;
-    std::vector<int> N;
-    std::vector<double> temps;
-    std::vector<SampleDev> samples;
-    std::vector<ItemDev> items;
-    ShapeInfo sh{};
-    SweepLaunch launch{};
-    DevPtrs<float> pf{};
-    DevPtrs<double> pd{};
-    // regions of the workspace
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    unsigned char* acc_region = nullptr;  // accumulators cleared at init
-    size_t acc_region_bytes = 0;
-    double* scratch = nullptr;            // hook / state-transfer buffer (doubles)
-    size_t scratch_doubles = 0;
-    int64_t amp_complex = 0;
-    int64_t sweeps_done = 0, swaps_done = 0;
-    bool inited = false;
-    std::map<int, int> tile_copies;       // copies per workgroup for each N
-    // cached HIP graph of one segment
-    hipGraphExec_t exec = nullptr;
-    int graph_sweeps = 0;
-    int64_t graph_phase = -1;
-    bool graph_measuring = false;
-    // sweep-kernel timing
-    bool timing = false;
-    bool capturing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events, spare;
-
-    const void* ptrs() const {
-        return cfg.precision == RLPT_FP64 ? static_cast<const void*>(&pd) : static_cast<const void*>(&pf);
-    }
-    size_t real_bytes() const { return cfg.precision == RLPT_FP64 ? 8 : 4; }
-};
 
 namespace {
 
@@ -106,7 +68,7 @@ struct Layout {
 struct Regions {
     size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
     size_t acc_begin, acc, swap_acc, obs, hist, series_e, series_q, meas_cnt, counters, acc_end;
-    size_t scratch, scratch_doubles, total;
+    size_t scratch, scratch_doubles, mlp, total;
 };
 
 int check_config(const rlpt_config* cfg) {
@@ -123,6 +85,7 @@ int check_config(const rlpt_config* cfg) {
     if (cfg->copies_per_block < 0) return fail(RLPT_E_ARG, "copies_per_block must be >= 0");
     if (cfg->list_layout < RLPT_LAYOUT_AUTO || cfg->list_layout > RLPT_LAYOUT_CHUNKED)
         return fail(RLPT_E_ARG, "bad list_layout");
+    if (cfg->mlp_nets < 0) return fail(RLPT_E_ARG, "mlp_nets must be >= 0");
     return RLPT_OK;
 }
 
@@ -197,6 +160,8 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     r.acc_end = L.off;
     r.scratch_doubles = std::max<size_t>(2 * amp, 8192);
     r.scratch = L.take(r.scratch_doubles * 8);
+    r.mlp = L.off;
+    L.off = mlp_layout(cfg, g[0]->N, S, nullptr, nullptr, L.off);
     r.total = L.off;
     return r;
 }
@@ -256,6 +221,7 @@ int enqueue_sweeps(rlpt_ctx* c, int64_t done, int64_t n, int64_t* swaps_added) {
         const int iv[3] = {cfg.swap_interval, cfg.resync_interval, cfg.measure_interval};
         for (int i = 0; i < 3; ++i)
             if (iv[i] > 0) step = std::min<int64_t>(step, iv[i] - cur % iv[i]);
+        if (c->mlp_moves > 0) step = 1;  // learned rounds follow every sweep
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         if (c->timing && !c->capturing) {
             if (!c->spare.empty()) {
@@ -271,6 +237,10 @@ int enqueue_sweeps(rlpt_ctx* c, int64_t done, int64_t n, int64_t* swaps_added) {
         if (ev.first) {
             HIP_TRY(hipEventRecord(ev.second, c->stream), "event record");
             c->events.push_back(ev);
+        }
+        for (int m = 0; m < c->mlp_moves; ++m) {
+            int rc = mlp_enqueue_round(c);
+            if (rc) return rc;
         }
         const int64_t after = cur + step;
         const bool swap = c->T > 1 && after % cfg.swap_interval == 0;
@@ -377,6 +347,11 @@ int rlpt_config_default(rlpt_config* cfg) {
     cfg->n_bins = 100;
     cfg->series_len = 0;
     cfg->list_layout = RLPT_LAYOUT_AUTO;
+    cfg->mlp_nets = 0;
+    cfg->mlp_hidden = 256;
+    cfg->mlp_components = 4;
+    cfg->mlp_capacity = 100000;
+    cfg->mlp_batch = 512;
     return RLPT_OK;
 }
 
@@ -385,6 +360,7 @@ int rlpt_workspace_size(const rlpt_config* cfg, const rlpt_graph* const* graphs,
     if (rc) return rc;
     if ((rc = check_graphs(graphs, n_graphs))) return rc;
     if (!bytes) return fail(RLPT_E_ARG, "bytes is NULL");
+    if ((rc = mlp_check_config(*cfg, graphs, n_graphs))) return rc;
     int layout = 0;
     if ((rc = choose_layout(*cfg, graphs, n_graphs, &layout))) return rc;
     *bytes = plan(*cfg, graphs, n_graphs, layout).total;
@@ -399,6 +375,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     if (!temps || !out) return fail(RLPT_E_ARG, "temps / out is NULL");
     if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(RLPT_E_ARG, "workspace must be 256-byte aligned");
     *out = nullptr;
+    if ((rc = mlp_check_config(*cfg, graphs, n_graphs))) return rc;
     for (int t = 0; t < cfg->n_temps; ++t) {
         if (!(temps[t] > 0.0) || !isfinite(temps[t])) return fail(RLPT_E_ARG, "temperatures must be finite and > 0");
         if (t > 0 && !(temps[t] > temps[t - 1])) return fail(RLPT_E_ARG, "temperatures must be strictly ascending");
@@ -426,6 +403,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->acc_region_bytes = r.acc_end - r.acc_begin;
     c->scratch = reinterpret_cast<double*>(b + r.scratch);
     c->scratch_doubles = r.scratch_doubles;
+    mlp_layout(*cfg, graphs[0]->N, n_graphs, &c->mlp, b, r.mlp);
 
     // host images of the device tables
     std::vector<uint32_t> ms, idx, cs;

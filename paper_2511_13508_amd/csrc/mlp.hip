@@ -1,0 +1,596 @@
+// Kernels of the learned global proposal (see mlp.hpp): batched GEMMs with
+// bfloat16 weights and FP32 accumulation, SiLU, the Gaussian-mixture head and
+// its gradient, Adam, and the three stages of an exact Metropolis-Hastings
+// global move (propose, energy change, accept).  Every launch covers all
+// networks (grid z = network).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mlp.hpp"
+#include "philox.hpp"
+
+namespace rlpt {
+namespace {
+
+constexpr uint64_t kTagLearn = 0x4C4541524EULL;  // "LEARN"
+constexpr uint64_t kTagTrain = 0x545241494EULL;  // "TRAIN"
+constexpr float kSmaxY = 2.0f;
+constexpr float kSmaxPsi = 1.57079632679489662f;
+constexpr float kLog2Pi = 1.83787706640934548f;
+constexpr float kPiF = 3.14159265358979324f;
+constexpr int kMaxK = 8;
+
+__device__ inline float bf16_to_f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ inline uint16_t f_to_bf16(float x) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+__device__ inline float ld(const float* p) { return *p; }
+__device__ inline float ld(const uint16_t* p) { return bf16_to_f(*p); }
+__device__ inline float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
+__device__ inline float silu(float x) { return x * sigm(x); }
+
+__device__ inline float wsum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline float wmax(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline float wrapf(float x) { return x - 2.0f * kPiF * ceilf((x - kPiF) / (2.0f * kPiF)); }
+
+// ------------------------------------------------------------------ GEMM
+// C[i][j] = act(sum_k A(i,k) B(k,j) + bias[j]), A(i,k) = A[i*as0 + k*as1],
+// B(k,j) = B[k*bs0 + j*bs1]; 64 x 64 tile per 256-thread block, 4 x 4 per thread.
+template <typename TB>
+struct Gemm {
+    const float* A;
+    int64_t sA;
+    int as0, as1;
+    const TB* B;
+    int64_t sB;
+    int bs0, bs1;
+    const float* bias;
+    int64_t sBias;
+    float* Cpre;
+    float* Cact;
+    int64_t sC;
+    int M, N, K;
+};
+
+template <typename TB, int ACT>
+__global__ __launch_bounds__(256) void k_gemm(Gemm<TB> g) {
+    __shared__ float As[16][65];
+    __shared__ float Bs[16][65];
+    const int net = blockIdx.z;
+    const float* A = g.A + net * g.sA;
+    const TB* B = g.B + net * g.sB;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int r = idx >> 4, kk = idx & 15;
+            const int gi = m0 + r, gk = k0 + kk;
+            As[kk][r] = (gi < g.M && gk < g.K) ? A[(int64_t)gi * g.as0 + (int64_t)gk * g.as1] : 0.0f;
+            const int kb = idx >> 6, c = idx & 63;
+            const int gkb = k0 + kb, gj = n0 + c;
+            Bs[kb][c] = (gkb < g.K && gj < g.N) ? ld(B + (int64_t)gkb * g.bs0 + (int64_t)gj * g.bs1) : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gi = m0 + ty * 4 + i;
+        if (gi >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gj = n0 + tx * 4 + j;
+            if (gj >= g.N) continue;
+            const float v = acc[i][j] + (g.bias ? g.bias[net * g.sBias + gj] : 0.0f);
+            g.Cpre[net * g.sC + (int64_t)gi * g.N + gj] = v;
+            if (ACT) g.Cact[net * g.sC + (int64_t)gi * g.N + gj] = silu(v);
+        }
+    }
+}
+
+template <typename TB, int ACT>
+hipError_t gemm(const Gemm<TB>& g, int nets, hipStream_t st) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nets);
+    hipLaunchKernelGGL((k_gemm<TB, ACT>), grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ features
+// Re, Im of a rotated so that a_0 is real and positive
+__device__ inline void write_features(const float* a, int N, float* X, int lane) {
+    const float x0 = a[0], y0 = a[1];
+    const float r = sqrtf(x0 * x0 + y0 * y0);
+    const float cr = r > 0.0f ? x0 / r : 1.0f, ci = r > 0.0f ? -y0 / r : 0.0f;
+    for (int k = lane; k < N; k += 64) {
+        const float x = a[2 * k], y = a[2 * k + 1];
+        X[k] = x * cr - y * ci;
+        X[N + k] = x * ci + y * cr;
+    }
+}
+
+__device__ inline const float* copy_amp(const DevPtrs<float>& P, const ShapeInfo& sh, int N, int c) {
+    return P.amp + 2 * (int64_t)c * N;  // one N for every sample: copies are contiguous
+}
+
+__global__ __launch_bounds__(64) void k_feat_current(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int mu = b / sh.n_reps, r = b % sh.n_reps;
+    const int t = M.temp_index[net];
+    const int c = P.copy_at[((int64_t)mu * sh.n_reps + r) * sh.n_temps + t];
+    if (lane == 0) M.item_copy[net * M.Bm + b] = c;
+    write_features(copy_amp(P, sh, M.N, c), M.N, M.X + ((int64_t)net * M.Bm + b) * M.In, lane);
+}
+
+__global__ __launch_bounds__(64) void k_feat_proposed(MlpDev M) {
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    write_features(M.ap + item * 2 * M.N, M.N, M.X + item * M.In, lane);
+}
+
+// log w_k and phases of one configuration held in global memory
+__device__ inline float log_w(const float* a, int k, float logN) {
+    const float u = a[2 * k] * a[2 * k] + a[2 * k + 1] * a[2 * k + 1];
+    return 2.0f * logf(u) - logN;
+}
+
+__global__ __launch_bounds__(64) void k_feat_train(MlpDev M, uint64_t seed, int64_t step, int use_first) {
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int N = M.N;
+    int idx = b;
+    if (!use_first) {
+        const Philox4 w = philox4x64((uint64_t)step, (uint64_t)net, (uint64_t)b, 0, seed, kTagTrain);
+        const int cnt = M.count[net] < M.cap ? M.count[net] : M.cap;
+        idx = index_below(w.v[0], cnt > 0 ? cnt : 1);
+    }
+    const float* before = M.data + (((int64_t)net * M.cap + idx) * 2 + 0) * 2 * N;
+    const float* after = M.data + (((int64_t)net * M.cap + idx) * 2 + 1) * 2 * N;
+    const int64_t item = (int64_t)net * M.Bt + b;
+    write_features(before, N, M.tX + item * M.In, lane);
+    const float logN = logf((float)N);
+    const float lw0 = log_w(before, N - 1, logN), lw1 = log_w(after, N - 1, logN);
+    float* dl = M.tdelta + item * M.D;
+    for (int k = lane; k < N; k += 64) {
+        if (k < N - 1) dl[k] = (log_w(after, k, logN) - lw1) - (log_w(before, k, logN) - lw0);
+        const float p0 = atan2f(before[2 * k + 1], before[2 * k]);
+        const float p1 = atan2f(after[2 * k + 1], after[2 * k]);
+        dl[N - 1 + k] = wrapf(p1 - p0);
+    }
+}
+
+// ------------------------------------------------------------------ mixture head
+struct Mix {
+    float lw[kMaxK];
+};
+
+__device__ inline void mix_weights(const float* O, int K, Mix& m) {
+    float mx = -INFINITY;
+    for (int i = 0; i < K; ++i) mx = fmaxf(mx, O[i]);
+    float s = 0.0f;
+    for (int i = 0; i < K; ++i) s += expf(O[i] - mx);
+    const float lse = mx + logf(s);
+    for (int i = 0; i < K; ++i) m.lw[i] = O[i] - lse;
+}
+
+__device__ inline float smax_of(int d, int N) { return d < N - 1 ? kSmaxY : kSmaxPsi; }
+
+// log density of the (signed) displacement under the scaled mixture, wave-cooperative
+__device__ float log_mix(const float* O, const float* delta, float sign, float scale, int N, int K, int D, int lane) {
+    Mix mw;
+    mix_weights(O, K, mw);
+    float best = -INFINITY, terms[kMaxK];
+    for (int m = 0; m < K; ++m) {
+        float part = 0.0f;
+        for (int d = lane; d < D; d += 64) {
+            const float mu = scale * O[K + m * D + d];
+            const float sg = scale * smax_of(d, N) * sigm(O[K + K * D + m * D + d]);
+            const float x = sign * delta[d];
+            if (d < N - 1) {
+                const float z = (x - mu) / sg;
+                part += -logf(sg) - 0.5f * kLog2Pi - 0.5f * z * z;
+            } else {
+                const float t0 = wrapf(x - mu);
+                float s = 0.0f;
+#pragma unroll
+                for (int n = -3; n <= 3; ++n) {
+                    const float t = (t0 + 2.0f * kPiF * n) / sg;
+                    s += expf(-0.5f * t * t);
+                }
+                part += logf(s) - logf(sg) - 0.5f * kLog2Pi;
+            }
+        }
+        terms[m] = mw.lw[m] + wsum(part);
+        best = fmaxf(best, terms[m]);
+    }
+    float s = 0.0f;
+    for (int m = 0; m < K; ++m) s += expf(terms[m] - best);
+    return best + logf(s);
+}
+
+// training head: mean NLL of the unwrapped mixture and its gradient w.r.t. the outputs
+__global__ __launch_bounds__(64) void k_head_train(MlpDev M) {
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int N = M.N, K = M.K, D = M.D;
+    const int64_t item = (int64_t)net * M.Bt + b;
+    const float* O = M.tO + item * M.Out;
+    const float* dl = M.tdelta + item * D;
+    float* dO = M.tdO + item * M.Out;
+    Mix mw;
+    mix_weights(O, K, mw);
+    float ell[kMaxK], best = -INFINITY;
+    for (int m = 0; m < K; ++m) {
+        float part = 0.0f;
+        for (int d = lane; d < D; d += 64) {
+            const float sg = smax_of(d, N) * sigm(O[K + K * D + m * D + d]);
+            const float z = (dl[d] - O[K + m * D + d]) / sg;
+            part += logf(sg) + 0.5f * kLog2Pi + 0.5f * z * z;
+        }
+        ell[m] = mw.lw[m] - wsum(part);
+        best = fmaxf(best, ell[m]);
+    }
+    float s = 0.0f;
+    for (int m = 0; m < K; ++m) s += expf(ell[m] - best);
+    const float logp = best + logf(s);
+    const float inv = 1.0f / (float)M.Bt;
+    for (int m = 0; m < K; ++m) {
+        const float r = expf(ell[m] - logp);
+        if (lane == 0) dO[m] = (expf(mw.lw[m]) - r) * inv;
+        for (int d = lane; d < D; d += 64) {
+            const float sm = smax_of(d, N);
+            const float sg = sm * sigm(O[K + K * D + m * D + d]);
+            const float z = (dl[d] - O[K + m * D + d]) / sg;
+            dO[K + m * D + d] = -r * z / sg * inv;
+            dO[K + K * D + m * D + d] = -r * (z * z - 1.0f) * (1.0f - sg / sm) * inv;
+        }
+    }
+    if (lane == 0) M.tloss[item] = -logp;
+}
+
+__global__ void k_silu_back(const float* dH, const float* P, float* dP, int64_t n) {
+    const int64_t net = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float p = P[net * n + i];
+        const float s = sigm(p);
+        dP[net * n + i] = dH[net * n + i] * s * (1.0f + p * (1.0f - s));
+    }
+}
+
+__global__ void k_colsum(const float* Y, int rows, int cols, int64_t sY, float* out, int64_t sOut) {
+    const int net = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += Y[net * sY + (int64_t)r * cols + j];
+    out[net * sOut + j] = s;
+}
+
+__global__ void k_adam(MlpDev M, float lr, float c1, float c2) {
+    const int64_t n = (int64_t)M.nets * M.NP;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float g = M.grad[i];
+        const float m = 0.9f * M.am[i] + 0.1f * g;
+        const float v = 0.999f * M.av[i] + 0.001f * g * g;
+        M.am[i] = m;
+        M.av[i] = v;
+        const float w = M.master[i] - lr * (m / c1) / (sqrtf(v / c2) + 1e-8f);
+        M.master[i] = w;
+        M.wbf[i] = f_to_bf16(w);
+    }
+}
+
+__global__ void k_sync_bf16(MlpDev M) {
+    const int64_t n = (int64_t)M.nets * M.NP;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        M.wbf[i] = f_to_bf16(M.master[i]);
+}
+
+// ------------------------------------------------------------------ the move
+// one standard normal of the move's draw (Box-Muller in FP64 on Philox words)
+__device__ inline float move_gauss(uint64_t seed, int64_t move, int c, int d) {
+    const Philox4 w = philox4x64((uint64_t)(d >> 1), (uint64_t)move, (uint64_t)c, 0, seed, kTagLearn);
+    const int h = d & 1;
+    const double u1 = 1.0 - uniform01<double>(w.v[2 * h]);
+    const double u2 = uniform01<double>(w.v[2 * h + 1]);
+    return (float)(sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2));
+}
+
+__global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+    __shared__ float sdel[2 * kMaxModes];
+    __shared__ float slw[kMaxModes];
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int N = M.N, K = M.K, D = M.D;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    const int c = M.item_copy[item];
+    const int64_t move = *M.moves_done;
+    const float* O = M.Of + item * M.Out;
+    const float* a = copy_amp(P, sh, N, c);
+    // component
+    Mix mw;
+    mix_weights(O, K, mw);
+    const int nb = (D + 1) / 2;
+    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
+    const double uc = uniform01<double>(wu.v[0]);
+    int m = K - 1;
+    double cum = 0.0;
+    for (int i = 0; i < K; ++i) {
+        cum += (double)expf(mw.lw[i]);
+        if (cum > uc) {
+            m = i;
+            break;
+        }
+    }
+    for (int d = lane; d < D; d += 64) {
+        const float mu = scale * O[K + m * D + d];
+        const float sg = scale * smax_of(d, N) * sigm(O[K + K * D + m * D + d]);
+        const float del = mu + sg * move_gauss(sh.run_seed, move, c, d);
+        sdel[d] = del;
+        M.delta[item * D + d] = del;
+    }
+    const float logN = logf((float)N);
+    for (int k = lane; k < N; k += 64) slw[k] = log_w(a, k, logN);
+    __syncthreads();
+    // new intensities from y' = y + dy (y'_{N-1} = 0), normalised on the simplex
+    const float last = slw[N - 1];
+    float mx = -INFINITY;
+    for (int k = lane; k < N; k += 64) mx = fmaxf(mx, k < N - 1 ? slw[k] - last + sdel[k] : 0.0f);
+    mx = wmax(mx);
+    float se = 0.0f;
+    for (int k = lane; k < N; k += 64) se += expf((k < N - 1 ? slw[k] - last + sdel[k] : 0.0f) - mx);
+    const float lse = mx + logf(wsum(se));
+    float dref = 0.0f;
+    float* ap = M.ap + item * 2 * N;
+    for (int k = lane; k < N; k += 64) {
+        const float lwn = (k < N - 1 ? slw[k] - last + sdel[k] : 0.0f) - lse;
+        dref += 0.5f * (lwn - slw[k]);
+        const float A = expf(0.25f * (logN + lwn));
+        const float ph = atan2f(a[2 * k + 1], a[2 * k]) + sdel[N - 1 + k];
+        float sn, cs;
+        sincosf(ph, &sn, &cs);
+        ap[2 * k] = A * cs;
+        ap[2 * k + 1] = A * sn;
+    }
+    dref = wsum(dref);
+    const float lq = log_mix(O, sdel, 1.0f, scale, N, K, D, lane);
+    if (lane == 0) {
+        M.lqf[item] = lq;
+        M.dref[item] = dref;
+    }
+}
+
+// energy change H(a') - H(a) over the by-term list, FP32 (one block per item)
+__global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
+    __shared__ float2 s0[kMaxModes];
+    __shared__ float2 s1[kMaxModes];
+    __shared__ float red[4];
+    const int net = blockIdx.y, b = blockIdx.x;
+    const int N = M.N;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    const int c = M.item_copy[item];
+    const int mu = c / sh.copies_per_sample;
+    const float* a = copy_amp(P, sh, N, c);
+    const float* ap = M.ap + item * 2 * N;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        s0[k] = make_float2(a[2 * k], a[2 * k + 1]);
+        s1[k] = make_float2(ap[2 * k], ap[2 * k + 1]);
+    }
+    __syncthreads();
+    const SampleDev sd = P.samples[mu];
+    const ushort4* Q = P.quads + sd.quad_base;
+    const double* Jq = P.Jq + sd.quad_base;
+    float acc = 0.0f;
+    for (int64_t q = threadIdx.x; q < sd.n_quads; q += blockDim.x) {
+        const ushort4 t = Q[q];
+        const float J = (float)Jq[q];
+        float2 p = s0[t.x], s = s0[t.y], m = s0[t.z], n = s0[t.w];
+        float cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
+        float dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
+        const float x0 = cr * dr - ci * di;
+        p = s1[t.x], s = s1[t.y], m = s1[t.z], n = s1[t.w];
+        cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
+        dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
+        const float x1 = cr * dr - ci * di;
+        acc += -2.0f * J * (x1 - x0);
+    }
+    acc = wsum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) M.dE[item] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+    __shared__ float sdel[2 * kMaxModes];
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int N = M.N, K = M.K, D = M.D;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    const int c = M.item_copy[item];
+    const int64_t move = *M.moves_done;
+    for (int d = lane; d < D; d += 64) sdel[d] = M.delta[item * D + d];
+    __syncthreads();
+    const float lqr = log_mix(M.Or + item * M.Out, sdel, -1.0f, scale, N, K, D, lane);
+    const float beta = P.beta[M.temp_index[net]];
+    const float la = -beta * M.dE[item] + M.dref[item] + lqr - M.lqf[item];
+    const int nb = (D + 1) / 2;
+    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
+    const double ua = uniform01<double>(wu.v[1]);
+    const bool accept = log(ua) < (double)la;
+    if (accept) {
+        float* a = P.amp + 2 * (int64_t)c * N;
+        const float* ap = M.ap + item * 2 * N;
+        for (int k = lane; k < 2 * N; k += 64) a[k] = ap[k];
+    }
+    if (lane == 0) {
+        M.la[item] = la;
+        if (accept) {
+            P.E[c] += M.dE[item];
+            atomicAdd(&M.acc[net], 1ull);
+        }
+        atomicAdd(&M.tries[net], 1ull);
+    }
+}
+
+__global__ void k_moves_tick(int64_t* moves) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *moves += 1;
+}
+
+__global__ __launch_bounds__(64) void k_harvest(MlpDev M, DevPtrs<float> P, ShapeInfo sh, int which, int slot0) {
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    int c;
+    if (which == 0) {
+        const int mu = b / sh.n_reps, r = b % sh.n_reps;
+        c = P.copy_at[((int64_t)mu * sh.n_reps + r) * sh.n_temps + M.temp_index[net]];
+        if (lane == 0) M.item_copy[item] = c;
+    } else {
+        c = M.item_copy[item];
+    }
+    const int slot = (slot0 + b) % M.cap;
+    const float* a = copy_amp(P, sh, M.N, c);
+    float* dst = M.data + (((int64_t)net * M.cap + slot) * 2 + which) * 2 * M.N;
+    for (int k = lane; k < 2 * M.N; k += 64) dst[k] = a[k];
+}
+
+}  // namespace
+
+hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
+    hipLaunchKernelGGL(k_feat_current, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh);
+    return hipGetLastError();
+}
+
+hipError_t mlp_features_proposed(const MlpDev& M, hipStream_t st) {
+    hipLaunchKernelGGL(k_feat_proposed, dim3(M.Bm, M.nets), dim3(64), 0, st, M);
+    return hipGetLastError();
+}
+
+hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int use_first, hipStream_t st) {
+    hipLaunchKernelGGL(k_feat_train, dim3(M.Bt, M.nets), dim3(64), 0, st, M, seed, step, use_first);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st) {
+    const int B = train ? M.Bt : M.Bm;
+    const float* X = train ? M.tX : M.X;
+    float* P1 = train ? M.tP1 : M.P1;
+    float* H1 = train ? M.tH1 : M.H1;
+    float* P2 = train ? M.tP2 : M.P2;
+    float* H2 = train ? M.tH2 : M.H2;
+    float* O = train ? M.tO : (into_reverse ? M.Or : M.Of);
+    Gemm<uint16_t> g{};
+    g.A = X; g.sA = (int64_t)B * M.In; g.as0 = M.In; g.as1 = 1;
+    g.B = M.wbf + M.oW1; g.sB = M.NP; g.bs0 = M.H; g.bs1 = 1;
+    g.bias = M.master + M.ob1; g.sBias = M.NP;
+    g.Cpre = P1; g.Cact = H1; g.sC = (int64_t)B * M.H; g.M = B; g.N = M.H; g.K = M.In;
+    hipError_t e = gemm<uint16_t, 1>(g, M.nets, st);
+    if (e != hipSuccess) return e;
+    g.A = H1; g.sA = (int64_t)B * M.H; g.as0 = M.H;
+    g.B = M.wbf + M.oW2; g.bs0 = M.H;
+    g.bias = M.master + M.ob2;
+    g.Cpre = P2; g.Cact = H2; g.K = M.H;
+    if ((e = gemm<uint16_t, 1>(g, M.nets, st)) != hipSuccess) return e;
+    g.A = H2;
+    g.B = M.wbf + M.oW3; g.bs0 = M.Out;
+    g.bias = M.master + M.ob3;
+    g.Cpre = O; g.Cact = nullptr; g.sC = (int64_t)B * M.Out; g.N = M.Out; g.K = M.H;
+    return gemm<uint16_t, 0>(g, M.nets, st);
+}
+
+hipError_t mlp_backward(const MlpDev& M, hipStream_t st) {
+    hipError_t e;
+    const int B = M.Bt;
+    hipLaunchKernelGGL(k_head_train, dim3(B, M.nets), dim3(64), 0, st, M);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto wgrad = [&](const float* act, int in, const float* dY, int out, int64_t off) {
+        Gemm<float> g{};
+        g.A = act; g.sA = (int64_t)B * in; g.as0 = 1; g.as1 = in;
+        g.B = dY; g.sB = (int64_t)B * out; g.bs0 = out; g.bs1 = 1;
+        g.bias = nullptr; g.Cpre = M.grad + off; g.sC = M.NP; g.M = in; g.N = out; g.K = B;
+        return gemm<float, 0>(g, M.nets, st);
+    };
+    auto bgrad = [&](const float* dY, int out, int64_t off) {
+        hipLaunchKernelGGL(k_colsum, dim3((out + 255) / 256, M.nets), dim3(256), 0, st, dY, B, out, (int64_t)B * out,
+                           M.grad + off, M.NP);
+        return hipGetLastError();
+    };
+    auto xgrad = [&](const float* dY, int out, int64_t woff, int in, float* dX) {
+        Gemm<uint16_t> g{};
+        g.A = dY; g.sA = (int64_t)B * out; g.as0 = out; g.as1 = 1;
+        g.B = M.wbf + woff; g.sB = M.NP; g.bs0 = 1; g.bs1 = out;
+        g.bias = nullptr; g.Cpre = dX; g.sC = (int64_t)B * in; g.M = B; g.N = in; g.K = out;
+        return gemm<uint16_t, 0>(g, M.nets, st);
+    };
+    auto sback = [&](const float* dH, const float* P, float* dP) {
+        const int64_t n = (int64_t)B * M.H;
+        hipLaunchKernelGGL(k_silu_back, dim3((unsigned)((n + 255) / 256), M.nets), dim3(256), 0, st, dH, P, dP, n);
+        return hipGetLastError();
+    };
+    if ((e = wgrad(M.tH2, M.H, M.tdO, M.Out, M.oW3)) != hipSuccess) return e;
+    if ((e = bgrad(M.tdO, M.Out, M.ob3)) != hipSuccess) return e;
+    if ((e = xgrad(M.tdO, M.Out, M.oW3, M.H, M.tdA)) != hipSuccess) return e;
+    if ((e = sback(M.tdA, M.tP2, M.tdB)) != hipSuccess) return e;
+    if ((e = wgrad(M.tH1, M.H, M.tdB, M.H, M.oW2)) != hipSuccess) return e;
+    if ((e = bgrad(M.tdB, M.H, M.ob2)) != hipSuccess) return e;
+    if ((e = xgrad(M.tdB, M.H, M.oW2, M.H, M.tdA)) != hipSuccess) return e;
+    if ((e = sback(M.tdA, M.tP1, M.tdB)) != hipSuccess) return e;
+    if ((e = wgrad(M.tX, M.In, M.tdB, M.H, M.oW1)) != hipSuccess) return e;
+    return bgrad(M.tdB, M.H, M.ob1);
+}
+
+hipError_t mlp_adam(const MlpDev& M, float lr, int64_t t, hipStream_t st) {
+    const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(1024), dim3(256), 0, st, M, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mlp_sync_bf16(const MlpDev& M, hipStream_t st) {
+    hipLaunchKernelGGL(k_sync_bf16, dim3(1024), dim3(256), 0, st, M);
+    return hipGetLastError();
+}
+
+hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_propose, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
+    return hipGetLastError();
+}
+
+hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_change, dim3(M.Bm, M.nets), dim3(256), 0, st, M, P, sh);
+    return hipGetLastError();
+}
+
+hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_accept, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_moves_tick, dim3(1), dim3(64), 0, st, M.moves_done);
+    return hipGetLastError();
+}
+
+hipError_t mlp_harvest(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, int which, int slot0,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_harvest, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, which, slot0);
+    return hipGetLastError();
+}
+
+}  // namespace rlpt

@@ -1,0 +1,85 @@
+// Learned global proposal: device descriptor and kernel launchers.
+//
+// One network per learned temperature slot: features of a configuration (Re
+// and Im of a rotated so that a_0 is real positive) -> H SiLU -> H SiLU ->
+// K-component diagonal Gaussian mixture over the displacement (dy, dpsi) of
+// the alr intensity coordinates y_k = log(w_k / w_{N-1}), w = |a|^4 / N, and of
+// the phases; exact Metropolis-Hastings with the reference density
+// prod w^(1/2) in (y, psi).  Weights: FP32 master + bfloat16 copies used by
+// the GEMMs (FP32 accumulation).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace rlpt {
+
+struct MlpDev {
+    int32_t nets, N, In, H, K, D, Out;
+    int32_t Bm;      // inference items per net (samples x replicas)
+    int32_t Bt;      // training minibatch
+    int32_t cap;     // stored training pairs per net
+    int64_t NP;      // parameters per net
+    int64_t oW1, ob1, oW2, ob2, oW3, ob3;  // offsets inside a parameter vector
+    float* master;   // [nets][NP]
+    uint16_t* wbf;   // [nets][NP] bfloat16 copies
+    float* grad;     // [nets][NP]
+    float* am;       // Adam first moments
+    float* av;       // Adam second moments
+    // inference (per learned move round)
+    float* X;        // [nets][Bm][In]
+    float* P1;       // [nets][Bm][H] pre-activations
+    float* H1;
+    float* P2;
+    float* H2;
+    float* Of;       // [nets][Bm][Out] at the current configuration
+    float* Or;       // [nets][Bm][Out] at the proposal
+    float* ap;       // [nets][Bm][2N] proposed configuration (interleaved complex)
+    float* delta;    // [nets][Bm][D]
+    float* lqf;      // [nets][Bm] forward log density
+    float* dref;     // [nets][Bm] log reference-density ratio
+    float* dE;       // [nets][Bm] energy change
+    float* la;       // [nets][Bm] log acceptance ratio
+    int32_t* item_copy;  // [nets][Bm]
+    // training
+    float* tX;       // [nets][Bt][In]
+    float* tP1;      // [nets][Bt][H]
+    float* tH1;
+    float* tP2;
+    float* tH2;
+    float* tO;       // [nets][Bt][Out]
+    float* tdO;      // [nets][Bt][Out]
+    float* tdA;      // [nets][Bt][H] backward scratch
+    float* tdB;      // [nets][Bt][H]
+    float* tdelta;   // [nets][Bt][D]
+    float* tloss;    // [nets][Bt]
+    float* data;     // [nets][cap][2][2N] pairs (before, after), interleaved complex
+    int32_t* temp_index;  // [nets]
+    int32_t* count;  // [nets] stored pairs
+    unsigned long long* acc;    // [nets]
+    unsigned long long* tries;  // [nets]
+    int64_t* moves_done;        // learned-move rounds (RNG counter)
+};
+
+struct MlpRun {
+    float scale;     // step scale of the proposal
+    int32_t pad;
+};
+
+// all launchers enqueue on st and cover every net in one launch (grid z = net)
+hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
+hipError_t mlp_features_proposed(const MlpDev& M, hipStream_t st);
+hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int use_first, hipStream_t st);
+// forward of every net: inference (train = 0, from M.X into Of or Or) or training (from tX into tO)
+hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st);
+hipError_t mlp_backward(const MlpDev& M, hipStream_t st);
+hipError_t mlp_adam(const MlpDev& M, float lr, int64_t t, hipStream_t st);
+hipError_t mlp_sync_bf16(const MlpDev& M, hipStream_t st);
+hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
+hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
+hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
+hipError_t mlp_harvest(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, int which, int slot0,
+                       hipStream_t st);
+
+}  // namespace rlpt

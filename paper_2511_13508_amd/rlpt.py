@@ -29,7 +29,10 @@ EXPORTS = [
     "rlpt_sweep_time_get", "rlpt_counters",
     "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64", "rlpt_local_fields",
     "rlpt_pair_dE", "rlpt_observables", "rlpt_tau_int", "rlpt_tune_clear", "rlpt_tune_set", "rlpt_tune_get",
-    "rlpt_tune_save", "rlpt_tune_load", "rlpt_autotune", "rlpt_tile_of",
+    "rlpt_tune_save", "rlpt_tune_load", "rlpt_autotune", "rlpt_tile_of", "rlpt_mlp_setup", "rlpt_mlp_n_params",
+    "rlpt_mlp_set_params", "rlpt_mlp_get_params", "rlpt_mlp_set_pairs", "rlpt_mlp_harvest", "rlpt_mlp_train",
+    "rlpt_mlp_forward", "rlpt_mlp_loss_grad", "rlpt_mlp_enable", "rlpt_mlp_move", "rlpt_mlp_stats",
+    "rlpt_mlp_last_move",
 ]
 
 
@@ -63,7 +66,8 @@ class Config(C.Structure):
                 ("renorm_tol", C.c_double), ("drift_tol", C.c_double), ("measure_start", C.c_int32),
                 ("measure_interval", C.c_int32), ("n_bins", C.c_int32), ("series_len", C.c_int32),
                 ("block_threads", C.c_int32), ("copies_per_block", C.c_int32), ("list_layout", C.c_int32),
-                ("pad", C.c_int32)]
+                ("mlp_nets", C.c_int32), ("mlp_hidden", C.c_int32), ("mlp_components", C.c_int32),
+                ("mlp_capacity", C.c_int32), ("mlp_batch", C.c_int32)]
 
 
 OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",
@@ -124,6 +128,19 @@ def lib() -> C.CDLL:
         "rlpt_tune_load": ([C.c_char_p], C.c_int),
         "rlpt_autotune": ([P, P, i32, P, P, C.c_size_t, P, i32, P], C.c_int),
         "rlpt_tile_of": ([P, P, P], C.c_int),
+        "rlpt_mlp_setup": ([P, P, u64], C.c_int),
+        "rlpt_mlp_n_params": ([P, P, P], C.c_int),
+        "rlpt_mlp_set_params": ([P, i32, P], C.c_int),
+        "rlpt_mlp_get_params": ([P, i32, P], C.c_int),
+        "rlpt_mlp_set_pairs": ([P, i32, i32, P, P], C.c_int),
+        "rlpt_mlp_harvest": ([P, i32, i32], C.c_int),
+        "rlpt_mlp_train": ([P, i32, d, P], C.c_int),
+        "rlpt_mlp_forward": ([P, i32, i32, P], C.c_int),
+        "rlpt_mlp_loss_grad": ([P, i32, P, P], C.c_int),
+        "rlpt_mlp_enable": ([P, i32, d], C.c_int),
+        "rlpt_mlp_move": ([P, d], C.c_int),
+        "rlpt_mlp_stats": ([P, P, P], C.c_int),
+        "rlpt_mlp_last_move": ([P, i32, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -272,6 +289,69 @@ class Context:
         cp = np.zeros(self.S, dtype=np.int32)
         _check(lib().rlpt_tile_of(self._h, C.byref(b), _ptr(cp)))
         return b.value, cp
+
+    # ---------------------------------------------------------- learned proposal
+    def mlp_setup(self, temp_index, seed: int = 1):
+        t = np.ascontiguousarray(temp_index, dtype=np.int32)
+        _check(lib().rlpt_mlp_setup(self._h, _ptr(t), seed))
+
+    def mlp_sizes(self):
+        n, o = C.c_int64(), C.c_int32()
+        _check(lib().rlpt_mlp_n_params(self._h, C.byref(n), C.byref(o)))
+        return n.value, o.value
+
+    def mlp_set_params(self, net: int, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().rlpt_mlp_set_params(self._h, net, _ptr(p)))
+
+    def mlp_get_params(self, net: int) -> np.ndarray:
+        p = np.zeros(self.mlp_sizes()[0], dtype=np.float32)
+        _check(lib().rlpt_mlp_get_params(self._h, net, _ptr(p)))
+        return p
+
+    def mlp_set_pairs(self, net: int, before, after):
+        b = np.ascontiguousarray(before, dtype=np.complex128)
+        a = np.ascontiguousarray(after, dtype=np.complex128)
+        _check(lib().rlpt_mlp_set_pairs(self._h, net, b.shape[0], _ptr(b), _ptr(a)))
+
+    def mlp_harvest(self, rounds: int, lag: int = 1):
+        _check(lib().rlpt_mlp_harvest(self._h, rounds, lag))
+
+    def mlp_train(self, steps: int, lr: float = 1e-3) -> np.ndarray:
+        L = np.zeros(self.cfg.mlp_nets)
+        _check(lib().rlpt_mlp_train(self._h, steps, lr, _ptr(L)))
+        return L
+
+    def mlp_forward(self, net: int, n: int) -> np.ndarray:
+        out = np.zeros((n, self.mlp_sizes()[1]))
+        _check(lib().rlpt_mlp_forward(self._h, net, n, _ptr(out)))
+        return out
+
+    def mlp_loss_grad(self, net: int):
+        L = C.c_double()
+        g = np.zeros(self.mlp_sizes()[0], dtype=np.float32)
+        _check(lib().rlpt_mlp_loss_grad(self._h, net, C.byref(L), _ptr(g)))
+        return L.value, g
+
+    def mlp_enable(self, moves_per_sweep: int, step_scale: float = 1.0):
+        _check(lib().rlpt_mlp_enable(self._h, moves_per_sweep, step_scale))
+
+    def mlp_move(self, step_scale: float = 1.0):
+        _check(lib().rlpt_mlp_move(self._h, step_scale))
+
+    def mlp_stats(self):
+        a = np.zeros(self.cfg.mlp_nets)
+        t = np.zeros(self.cfg.mlp_nets)
+        _check(lib().rlpt_mlp_stats(self._h, _ptr(a), _ptr(t)))
+        return a, t
+
+    def mlp_last_move(self, net: int):
+        B = self.S * self.reps
+        la = np.zeros(B)
+        cp = np.zeros(B, dtype=np.int32)
+        prop = np.zeros((B, self.Ns[0]), dtype=np.complex128)
+        _check(lib().rlpt_mlp_last_move(self._h, net, _ptr(la), _ptr(cp), _ptr(prop)))
+        return la, cp, prop
 
     def counters(self):
         a, b, m = C.c_int64(), C.c_int64(), C.c_int64()

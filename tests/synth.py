@@ -33,3 +33,19 @@ def geometric_temps(t_min: float, t_max: float, n: int) -> np.ndarray:
     if n == 1:
         return np.array([t_min])
     return t_min * (t_max / t_min) ** (np.arange(n) / (n - 1))
+
+
+def random_constrained_state(N: int, seed: int, n_copies: int | None = None) -> np.ndarray:
+    """Complex normal amplitudes scaled onto the surface sum |a|^4 = N."""
+    a = random_state(N, seed, n_copies)
+    s = np.sum(np.abs(a) ** 4, axis=-1, keepdims=True)
+    return a * (N / s) ** 0.25
+
+
+def random_mlp_params(n_in: int, hidden: int, n_out: int, seed: int, out_scale: float = 0.3) -> np.ndarray:
+    """A flat parameter vector W1 [n_in, H], b1, W2 [H, H], b2, W3 [H, n_out], b3 (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal(n_in * hidden) / np.sqrt(n_in), 0.1 * rng.standard_normal(hidden),
+             rng.standard_normal(hidden * hidden) / np.sqrt(hidden), 0.1 * rng.standard_normal(hidden),
+             out_scale * rng.standard_normal(hidden * n_out) / np.sqrt(hidden), 0.1 * rng.standard_normal(n_out)]
+    return np.concatenate(parts).astype(np.float32)

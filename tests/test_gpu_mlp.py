@@ -1,0 +1,178 @@
+"""GPU: the learned global proposal against the FP64 reference (oracle/mlp.py)
+and the exactness of its Metropolis-Hastings test.
+
+Tolerances: network outputs 2e-3 relative to their rms (FP32 accumulation vs
+FP64); gradients per tensor |g_gpu - g_ora| <= 1e-2 |g_ora| (norms) and
+cosine >= 0.999 (the reference is evaluated on the same bfloat16 weights);
+proposals 2e-4 absolute; log acceptance ratios 2e-3 absolute (FP32 sums of
+~4N log-density terms and of the energy change)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2511_13508_amd import rlpt
+from tests import brute, synth
+from tests.gpu_util import make_ctx
+from tests.test_gpu_parity import jackknife, oracle_stack, per_sample_obs
+
+pytestmark = pytest.mark.gpu
+
+SEED3 = 2511135080 + 300
+
+
+def unflatten(p, N, H, K):
+    In, D, Out = M.sizes(N, K)
+    shapes = [("W1", (In, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, Out)), ("b3", (Out,))]
+    out, o = {}, 0
+    for k, s in shapes:
+        n = int(np.prod(s))
+        out[k] = np.asarray(p[o:o + n], dtype=np.float64).reshape(s)
+        o += n
+    assert o == len(p)
+    return out
+
+
+def mlp_ctx(N, S, T, reps, H, K, batch, nets=2, cap=64, graphs=None, temps=None):
+    graphs = graphs or [rlpt.Graph(N, SEED3 + i) for i in range(S)]
+    temps = synth.geometric_temps(0.5, 1.5, T) if temps is None else temps
+    return make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=nets, mlp_hidden=H,
+                    mlp_components=K, mlp_capacity=cap, mlp_batch=batch, resync_interval=0,
+                    drift_tol=0.0)
+
+
+def test_mlp_forward_and_gradients_match_oracle():
+    N, H, K, B = 8, 48, 3, 16
+    ctx = mlp_ctx(N, 1, 2, 1, H, K, B)
+    ctx.init(1)
+    ctx.mlp_setup([0, 1], seed=3)
+    NP, Out = ctx.mlp_sizes()
+    for net in (0, 1):
+        p = synth.random_mlp_params(2 * N, H, Out, seed=10 + net, out_scale=0.5)
+        assert p.size == NP
+        ctx.mlp_set_params(net, p)
+        before = synth.random_constrained_state(N, 20 + net, B)
+        after = synth.random_constrained_state(N, 30 + net, B)
+        ctx.mlp_set_pairs(net, before, after)
+    for net in (0, 1):
+        params = M.rounded(unflatten(synth.random_mlp_params(2 * N, H, Out, seed=10 + net, out_scale=0.5), N, H, K))
+        b = synth.random_constrained_state(N, 20 + net, B).astype(np.complex64).astype(np.complex128)
+        a = synth.random_constrained_state(N, 30 + net, B).astype(np.complex64).astype(np.complex128)
+        o_ref, _ = M.forward(params, M.features(b))
+        o = ctx.mlp_forward(net, B)
+        rms = np.sqrt(np.mean(o_ref ** 2))
+        assert np.max(np.abs(o - o_ref)) <= 2e-3 * rms
+        L_ref, g_ref = M.loss_and_grads(params, b, a, N, K)
+        L, g = ctx.mlp_loss_grad(net)
+        assert L == pytest.approx(L_ref, rel=1e-4)
+        gg = unflatten(g, N, H, K)
+        for k in g_ref:
+            x, y = gg[k].ravel(), g_ref[k].ravel()
+            assert np.linalg.norm(x - y) <= 1e-2 * np.linalg.norm(y), k
+            assert np.dot(x, y) / (np.linalg.norm(x) * np.linalg.norm(y)) >= 0.999, k
+
+
+def test_learned_move_matches_oracle(oracle):
+    N, S, T, reps, H, K = 8, 2, 3, 2, 32, 2
+    temps = synth.geometric_temps(0.6, 1.4, T)
+    ctx = mlp_ctx(N, S, T, reps, H, K, batch=8, temps=temps)
+    ctx.init(5)
+    ctx.mlp_setup([0, 2], seed=1)
+    NP, Out = ctx.mlp_sizes()
+    raw = [synth.random_mlp_params(2 * N, H, Out, seed=40 + n, out_scale=0.4) for n in range(2)]
+    for n in range(2):
+        ctx.mlp_set_params(n, raw[n])
+    state = synth.random_constrained_state(N, 50, S * T * reps)
+    ctx.set_state(state)
+    ctx.resync()
+    state32 = state.astype(np.complex64).astype(np.complex128)
+    E, temp_of = ctx.energies()
+    scale = 0.5
+    ctx.mlp_move(scale)
+    after = ctx.get_state().reshape(S * T * reps, N)
+    ogs = [oracle.Graph(N, SEED3 + i) for i in range(S)]
+    acc_seen = 0
+    for n, t in enumerate([0, 2]):
+        params = M.rounded(unflatten(raw[n], N, H, K))
+        la, copies, prop = ctx.mlp_last_move(n)
+        for b in range(S * reps):
+            mu, r = divmod(b, reps)
+            c = mu * T * reps + r * T + t  # copy holding temperature t (no swaps yet)
+            assert copies[b] == c
+            g, uc, ua = M.draws(5, 0, c, 2 * N - 1)  # run seed 5, first learned round
+            a0 = state32[c][None]
+            dH = lambda an: np.array([oracle.energy(ogs[mu], x) for x in an]) - oracle.energy(ogs[mu], state32[c])  # noqa
+            an, la_ref, parts = M.move_log_alpha(params, a0, dH, 1.0 / temps[t], N, K, scale, g[None], np.array([uc]))
+            np.testing.assert_allclose(prop[b], an[0], rtol=0, atol=2e-4)
+            assert la[b] == pytest.approx(la_ref[0], abs=2e-3)
+            accepted = math.log(ua) < la_ref[0]
+            if abs(math.log(ua) - la_ref[0]) > 1e-2:  # decided away from the boundary
+                np.testing.assert_allclose(after[c], an[0] if accepted else state32[c], rtol=0, atol=2e-4)
+                acc_seen += int(accepted)
+    a_cnt, tries = ctx.mlp_stats()
+    assert np.all(tries == S * reps)
+
+
+def test_learned_moves_keep_infinite_temperature_law():
+    """Exact draws at beta ~ 0, then learned rounds only (no sweeps): the
+    closed-form marginals of the reference law must stay put (this checks the
+    GPU's reference-density and wrapped-density terms on their own)."""
+    N, reps = 6, 512
+    ctx = mlp_ctx(N, 1, 1, reps, 16, 2, batch=8, nets=1, temps=[1e7])
+    ctx.init(9)
+    ctx.mlp_setup([0], seed=4)
+    for _ in range(40):
+        ctx.mlp_move(0.5)
+    acc, tries = ctx.mlp_stats()
+    assert 0.1 < acc[0] / tries[0] < 0.98
+    a = ctx.get_state().reshape(reps, N)
+    ref = brute.beta0_moments(N)
+    u = np.abs(a) ** 2
+    assert np.mean(u) == pytest.approx(ref["E|a|^2"], abs=5 * u.std() / math.sqrt(u.size))
+    assert np.mean(u ** 4) == pytest.approx(ref["E|a|^8"], abs=5 * (u ** 4).std() / math.sqrt(u.size))
+    np.testing.assert_allclose(np.sum(np.abs(a) ** 4, axis=1), N, rtol=2e-5)
+
+
+def test_harvest_train_and_learned_pt_are_unbiased(oracle):
+    """Harvest pairs from PT, train, then run PT with learned rounds after every
+    sweep: per-temperature <E>, C_V, <q^2> agree with the plain FP64 oracle
+    within 2 sigma (jackknife over 8 samples) in >= 90% of cells, 4 sigma in all."""
+    N, S, T, reps = 16, 8, 6, 2
+    temps = synth.geometric_temps(0.5, 1.5, T)
+    graphs = [rlpt.Graph(N, SEED3 + 50 + i) for i in range(S)]
+    ctx = make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=2, mlp_hidden=64,
+                   mlp_components=2, mlp_capacity=4096, mlp_batch=128, swap_interval=1, resync_interval=100,
+                   measure_start=1000, measure_interval=1, n_bins=20)
+    ctx.init(7)
+    ctx.sweep(300)
+    ctx.mlp_setup([1, 3], seed=2)
+    ctx.mlp_harvest(rounds=200, lag=2)
+    L0 = ctx.mlp_train(1, 1e-3)
+    L1 = ctx.mlp_train(300, 1e-3)
+    assert np.all(L1 < L0)
+    ctx.mlp_enable(1, 0.5)
+    ctx.sweep(4000 - ctx.counters()[0])
+    ctx.check()
+    acc, tries = ctx.mlp_stats()
+    assert np.all(acc > 0)
+    g = per_sample_obs(ctx.observables(), temps)
+    ors = []
+    for mu in range(S):
+        pt = oracle.PT(oracle.Graph(N, SEED3 + 50 + mu), temps, n_reps=reps, run_seed=99, sample=mu,
+                       swap_interval=1, resync_interval=100, measure_start=1000, measure_interval=1, n_bins=20)
+        pt.run(4000)
+        ors.append(pt)
+    o = per_sample_obs(oracle_stack(ors), temps)
+    cells = within2 = within4 = 0
+    rep = []
+    for k in ("E", "C_V", "q2", "Y2"):
+        mg, sg = jackknife(g[k])
+        mo, so = jackknife(o[k])
+        z = np.abs(mg - mo) / np.sqrt(sg ** 2 + so ** 2)
+        cells += z.size
+        within2 += int(np.sum(z <= 2))
+        within4 += int(np.sum(z <= 4))
+        rep.append((k, np.round(z, 2)))
+    assert within4 == cells, rep
+    assert within2 >= 0.9 * cells, rep
