@@ -61,9 +61,9 @@ def traffic_for_current_kernel(launch_bytes_alg: float):
 
 PROFILE_CMDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kt -o kt -- python bench.py --steps 20 --warmup 5 "
-          "--no-cpu-baseline",
+          "--tau-sweeps 0 --no-cpu-baseline",
     "pmc": "rocprofv3 --pmc {C} --kernel-include-regex k_sweep -f csv -d gpurun_out/pmc_{C} -o pmc -- python bench.py "
-           "--steps 4 --warmup 2 --no-cpu-baseline",
+           "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline",
     "cal": "rocprofv3 --pmc {C} -f csv -d gpurun_out/cal_{C} -o cal -- python bench.py --copy-calibration",
 }
 
@@ -212,6 +212,12 @@ def main():
     ap.add_argument("--copies-per-block", type=int, default=0)
     ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 packed (8 B/entry), 2 chunked (6.25 B/entry)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--tau-sweeps", type=int, default=2500, help="extra sweeps per run for tau_int (0: skip)")
+    ap.add_argument("--learn-temps", type=lambda v: [int(x) for x in v.split(",")] if v else [],
+                    default=[25, 26, 27, 28], help="temperature indices with learned global moves")
+    ap.add_argument("--learn-scale", type=float, default=0.05)
+    ap.add_argument("--harvest-rounds", type=int, default=400)
+    ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
@@ -249,24 +255,50 @@ def main():
     log(f"building {S} graphs N={N}")
     graphs = [rlpt.Graph(N, SEED_BASE + mu) for mu in range(S)]
     infos = [g.info() for g in graphs]
-    ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32,
-                       shared_pairs=args.shared_pairs, swap_interval=1, resync_interval=100, measure_start=0,
-                       measure_interval=1, n_bins=100, block_threads=args.block,
-                       copies_per_block=args.copies_per_block, list_layout=args.layout)
-    ctx.init(1)
-    log(f"warmup {args.warmup} sweeps")
-    ctx.sweep(args.warmup)
-    ctx.check()
-    torch.cuda.synchronize()
-    ctx.sweep_timing(True)
-    log(f"timing {args.steps} sweeps")
-    t0 = time.perf_counter()
-    ctx.sweep(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ctx.check()
-    kms, launches = ctx.sweep_time()
-    ctx.sweep_timing(False)
+    series_len = args.steps + args.tau_sweeps
+    common = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=100,
+                  measure_start=args.warmup, measure_interval=1, n_bins=100, series_len=series_len,
+                  block_threads=args.block, copies_per_block=args.copies_per_block, list_layout=args.layout)
+
+    def timed(ctx, tag):
+        """warm-up, then the timed steps with sweep-kernel events; returns (s, kernel ms, launches)"""
+        ctx.init(1)
+        log(f"{tag}: warmup {args.warmup} sweeps")
+        ctx.sweep(args.warmup)
+        ctx.check()
+        torch.cuda.synchronize()
+        ctx.sweep_timing(True)
+        log(f"{tag}: timing {args.steps} sweeps")
+        t0 = time.perf_counter()
+        ctx.sweep(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.check()
+        kms, launches = ctx.sweep_time()
+        ctx.sweep_timing(False)
+        return el, kms, launches
+
+    def tau_block(ctx, sweeps_per_s, t_idx, extra_sweeps):
+        """continue extra_sweeps sweeps, then tau_int of E at the temperature
+        indices t_idx from the series (first quarter discarded), median over samples"""
+        if extra_sweeps > 0:
+            ctx.sweep(extra_sweeps)
+            ctx.check()
+        o = ctx.observables()
+        m = int(o["e_n"][0, 0] / reps)
+        m = min(m, series_len)
+        lo = m // 4
+        tau = []
+        for t in t_idx:
+            tau.append(float(np.median([rlpt.tau_int(o["series_e"][mu, t, lo:m])[0] for mu in range(S)])))
+        tau = np.array(tau)
+        return {"temperatures": [float(temps[t]) for t in t_idx], "tau_int_E": tau.round(2).tolist(),
+                "sweeps_per_s": sweeps_per_s, "eff_sweeps_per_s": (sweeps_per_s / (2 * tau)).round(3).tolist(),
+                "series_points": m - lo}
+
+    # ---------------------------------------------------------------- headline: per-copy pairs
+    ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, **common)
+    el, kms, launches = timed(ctx, "plain")
     n_copies = ctx.n_copies
     value = N * n_copies * args.steps / el
     # algorithmic bytes of one sweep launch (one sweep): every copy streams, per
@@ -281,6 +313,13 @@ def main():
     achieved = bytes_per_launch / t_launch / 1e9
     traffic = traffic_for_current_kernel(bytes_per_launch)
     log(f"{value:.4g} mode-updates/s; sweep kernel {kms / launches:.3f} ms/launch, {achieved:.0f} GB/s")
+    sweeps_per_s = args.steps / el
+    t_learn = [t for t in args.learn_temps if t < T]
+    tau_plain = None
+    if args.tau_sweeps > 0:
+        log(f"plain: {args.tau_sweeps} more sweeps for tau_int")
+        tau_plain = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps)
+    ctx.close()
     out = {
         "metric": METRIC,
         "value": value,
@@ -304,8 +343,61 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_sweep", "ms_per_launch": kms / launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
-        "sweeps_per_s": args.steps / el,
+        "sweeps_per_s": sweeps_per_s,
     }
+    if args.tau_sweeps > 0:
+        tau = {"observable": "E (energy of ladder 0 at each temperature)", "estimator": "Sokal window c=6",
+               "plain": tau_plain}
+        # ------------------------------------------------------------ shared pair schedule
+        if not args.shared_pairs:
+            ctx = rlpt.Context(graphs, temps, shared_pairs=1, **common)
+            el2, _, _ = timed(ctx, "shared pairs")
+            tau["shared_pairs"] = tau_block(ctx, args.steps / el2, t_learn, args.tau_sweeps)
+            tau["shared_pairs"]["mode_updates_per_s"] = N * n_copies * args.steps / el2
+            ctx.close()
+        # ------------------------------------------------------------ learned global moves
+        if t_learn:
+            lcommon = dict(common, series_len=series_len + 2 * args.harvest_rounds)
+            ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, mlp_nets=len(t_learn),
+                               mlp_hidden=256, mlp_components=4, mlp_capacity=8192, mlp_batch=512, **lcommon)
+            ctx.init(1)
+            ctx.sweep(args.warmup)
+            ctx.mlp_setup(t_learn, seed=1)
+            log("learned: harvest and train")
+            t0 = time.perf_counter()
+            ctx.mlp_harvest(rounds=args.harvest_rounds, lag=2)
+            loss0 = ctx.mlp_train(1, 1e-3)
+            loss = ctx.mlp_train(args.train_steps, 1e-3)
+            t_train = time.perf_counter() - t0
+            ctx.mlp_enable(1, args.learn_scale)
+            done = ctx.counters()[0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sweep(args.steps)
+            torch.cuda.synchronize()
+            el3 = time.perf_counter() - t0
+            log(f"learned: {args.steps / el3:.1f} sweeps/s; tau_int run")
+            # measurements started at the warm-up boundary: the series covers harvest + learned sweeps;
+            # tau is taken over the learned part only
+            ctx.sweep(args.tau_sweeps)
+            ctx.check()
+            o = ctx.observables()
+            m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds)
+            lo = max(done - args.warmup, 0) + (m - max(done - args.warmup, 0)) // 4
+            tl = np.array([float(np.median([rlpt.tau_int(o["series_e"][mu, t, lo:m])[0] for mu in range(S)]))
+                           for t in t_learn])
+            acc, tries = ctx.mlp_stats()
+            sps3 = args.steps / el3
+            tau["learned"] = {"temperatures": [float(temps[t]) for t in t_learn], "tau_int_E": tl.round(2).tolist(),
+                              "sweeps_per_s": sps3, "eff_sweeps_per_s": (sps3 / (2 * tl)).round(3).tolist(),
+                              "series_points": m - lo, "move_acceptance": (acc / np.maximum(tries, 1)).round(4).tolist(),
+                              "step_scale": args.learn_scale, "train_loss_first_last": [loss0.round(2).tolist(),
+                                                                                        loss.round(2).tolist()],
+                              "harvest_and_train_s": t_train}
+            ctx.close()
+            tau["learned_vs_plain_eff"] = (np.array(tau["learned"]["eff_sweeps_per_s"])
+                                           / np.array(tau_plain["eff_sweeps_per_s"])).round(3).tolist()
+        out["tau_int_corrected"] = tau
     if not args.no_cpu_baseline:
         try:
             nthr = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
