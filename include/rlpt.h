@@ -290,6 +290,7 @@ typedef struct rlpt_obs {
     double* swap_tries; /* [S][T-1] */
     double* series_e;   /* [S][T][L] energy of ladder 0's copy at bath t, per measurement */
     double* series_q;   /* [S][T][L] overlap of ladders 0 and 1 at bath t, per measurement */
+    double* hist_I;     /* [S][T][B] total intensity I/N = sum|a|^2 / N on [0, 1] (P(I), sec. II.B) */
 } rlpt_obs;
 
 /* Copy the accumulators to host (synchronises).  Returns RLPT_E_STATE if a
@@ -342,6 +343,34 @@ int rlpt_mlp_last_move(rlpt_ctx* ctx, int32_t net, double* log_alpha, int32_t* c
 /* ------------------------------------------------------------------------ */
 /* Analysis helpers (host).                                                  */
 /* ------------------------------------------------------------------------ */
+
+/* Per-temperature disorder averages over S samples of the accumulators of
+ * rlpt_observables (sec. III.B eq. DisAver; errors: jackknife over samples):
+ * <E>; specific heat per spin C_V/N = avg((<E^2> - <E>^2)/T^2)/N (eq.
+ * SpecificHeat); <q^2>; kurtosis K = avg<q^4>/(avg(<q^2> - <q>^2))^2 (eq. kurt,
+ * with the disorder-averaged mean overlap taken as 0 by the symmetry q -> -q);
+ * IPR <Y_2>, <Y_4>; pair-move acceptance per temperature and swap acceptance
+ * per neighbouring pair.  Each output array has T entries (T-1 for swap_rate);
+ * NULL skips it. */
+typedef struct rlpt_summary {
+    double *E, *E_err, *cv, *cv_err, *q2, *q2_err, *kurtosis, *kurtosis_err;
+    double *y2, *y2_err, *y4, *y4_err, *acc_rate, *swap_rate;
+} rlpt_summary;
+int rlpt_summarize(const rlpt_obs* obs, int32_t n_samples, int32_t n_temps, int32_t n_modes, const double* temps,
+                   rlpt_summary* out);
+
+/* Temperature ladder with spacing adapted to the specific heat (App. A, eq.
+ * PT_Ti): T_0 = T_min, T_i = T_{i-1} / (1 - C / sqrt(C_V(T_i))), solved for T_i
+ * by fixed-point iteration with C_V linearly interpolated on (T_grid, C_grid)
+ * (extensive specific heat, C_grid > C^2), while T_i < T_max.  Writes at most
+ * capacity temperatures; *n_out receives the count. */
+int rlpt_adaptive_ladder(const double* T_grid, const double* C_grid, int32_t n_grid, double T_min, double T_max,
+                         double C, double* temps, int32_t capacity, int32_t* n_out);
+
+/* Means of x over the doubling windows [0,1), [1,2), [2,4), [4,8), ... (clipped
+ * to n), the thermalisation check of sec. III.B; starts may be NULL. */
+int rlpt_window_means(const double* x, int64_t n, double* means, int64_t* starts, int32_t capacity,
+                      int32_t* n_windows);
 
 /* Integrated autocorrelation time of a series x[n] with Sokal's automatic
  * window: tau(W) = 1/2 + sum_{t=1..W} rho(t), smallest W >= c_window*tau(W).

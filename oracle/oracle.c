@@ -280,6 +280,7 @@ typedef struct {
     double* acc;  double* tries;                   /* [T] pair-move acceptance */
     double* swap_acc; double* swap_tries;          /* [T-1] exchange acceptance */
     double* series_e; double* series_q;            /* [T][series_len] */
+    double* hist_I;                                /* [T][n_bins] total intensity I/N on [0, 1] */
     int64_t n_meas;
 } or_pt_accum;
 
@@ -514,6 +515,12 @@ static void measure(const or_pt_params* P, const or_pt_state* S, or_pt_accum* A)
             A->e_sq[t] += S->E[c] * S->E[c];
             A->y2_sum[t] += s2 / (s1 * s1);
             A->y4_sum[t] += s4 / (s2 * s2);
+            {   /* distribution of the total intensity I = sum |a|^2 (sec. II.B, P(I)) */
+                int32_t bI = (int32_t)floor(s1 / (double)N * P->n_bins);
+                if (bI < 0) bI = 0;
+                if (bI >= P->n_bins) bI = P->n_bins - 1;
+                A->hist_I[(size_t)t * P->n_bins + bI] += 1.0;
+            }
             if (r == 0 && A->n_meas < P->series_len) A->series_e[(size_t)t * P->series_len + A->n_meas] = S->E[c];
         }
         for (int32_t r = 0; r < Rn; ++r)

@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD_DIR, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    for src in ("graph.cpp", "api.cpp", "tune.cpp", "mlp_api.cpp"):
+    for src in ("graph.cpp", "api.cpp", "tune.cpp", "mlp_api.cpp", "analysis.cpp"):
         obj = os.path.join(BUILD_DIR, src + ".o")
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -67,7 +67,7 @@ struct Layout {
 
 struct Regions {
     size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
-    size_t acc_begin, acc, swap_acc, obs, hist, series_e, series_q, meas_cnt, counters, acc_end;
+    size_t acc_begin, acc, swap_acc, obs, hist, hist_I, series_e, series_q, meas_cnt, counters, acc_end;
     size_t scratch, scratch_doubles, mlp, total;
 };
 
@@ -153,6 +153,7 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     r.swap_acc = L.take(S * reps * std::max<size_t>(T - 1, 1) * 8);
     r.obs = L.take(kNumObs * S * T * 8);
     r.hist = L.take(S * T * cfg.n_bins * 8);
+    r.hist_I = L.take(S * T * cfg.n_bins * 8);
     r.series_e = L.take(S * T * std::max(cfg.series_len, 1) * 8);
     r.series_q = L.take(S * T * std::max(cfg.series_len, 1) * 8);
     r.meas_cnt = L.take(S * T * 4);
@@ -191,6 +192,7 @@ void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
     P.swap_acc = reinterpret_cast<unsigned long long*>(b + r.swap_acc);
     P.obs = reinterpret_cast<double*>(b + r.obs);
     P.hist = reinterpret_cast<double*>(b + r.hist);
+    P.hist_I = reinterpret_cast<double*>(b + r.hist_I);
     P.series_e = reinterpret_cast<double*>(b + r.series_e);
     P.series_q = reinterpret_cast<double*>(b + r.series_q);
     P.meas_cnt = reinterpret_cast<int32_t*>(b + r.meas_cnt);
@@ -796,6 +798,9 @@ int rlpt_observables(rlpt_ctx* c, rlpt_obs* o) {
     if (o->hist)
         HIP_TRY(hipMemcpy(o->hist, f64 ? c->pd.hist : c->pf.hist, (size_t)ST * c->cfg.n_bins * 8, hipMemcpyDeviceToHost),
                 "read hist");
+    if (o->hist_I)
+        HIP_TRY(hipMemcpy(o->hist_I, f64 ? c->pd.hist_I : c->pf.hist_I, (size_t)ST * c->cfg.n_bins * 8,
+                          hipMemcpyDeviceToHost), "read intensity hist");
     if (c->cfg.series_len > 0) {
         if (o->series_e)
             HIP_TRY(hipMemcpy(o->series_e, f64 ? c->pd.series_e : c->pf.series_e, (size_t)ST * c->cfg.series_len * 8,

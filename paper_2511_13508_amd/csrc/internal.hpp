@@ -100,6 +100,7 @@ struct DevPtrs {
     double* series_e;
     double* series_q;
     double* hist;
+    double* hist_I;           // [S][T][bins] total intensity I/N on [0, 1]
     int32_t* meas_cnt;        // [S][T]
     Counters* counters;
 };

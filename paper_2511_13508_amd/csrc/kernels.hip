@@ -449,27 +449,46 @@ __global__ __launch_bounds__(256) void k_resync(DevPtrs<R> P, ShapeInfo sh, int 
 }
 
 // ---------------------------------------------------------------- replica exchange
-// one thread per ladder (sample, replica): neighbouring baths in ascending
-// order, accepted with min[1, exp((b_i - b_{i+1})(E_i - E_{i+1}))]
+// one 64-thread block per ladder (sample, replica): energies of the ladder's
+// temperatures and the pairs' uniforms are staged in LDS in parallel, then one
+// lane proposes the neighbouring baths in ascending order, each accepted with
+// min[1, exp((b_i - b_{i+1})(E_i - E_{i+1}))], and the ladder is written back
 template <typename R>
-__global__ void k_swap(DevPtrs<R> P, ShapeInfo sh) {
-    const int L = blockIdx.x * blockDim.x + threadIdx.x;
-    if (L >= sh.n_samples * sh.n_reps) return;
+__global__ __launch_bounds__(64) void k_swap(DevPtrs<R> P, ShapeInfo sh) {
+    extern __shared__ double sw[];  // [T] energies, [T] uniforms, [T] copy at temperature
+    const int L = blockIdx.x;
     const int T = sh.n_temps;
+    double* e = sw;
+    double* u = sw + T;
+    int32_t* at_s = reinterpret_cast<int32_t*>(sw + 2 * T);
     int32_t* at = P.copy_at + (size_t)L * T;
     const int64_t round = P.counters->swaps_done;
-    for (int i = 0; i + 1 < T; ++i) {
+    for (int i = threadIdx.x; i < T; i += 64) {
+        const int c = at[i];
+        at_s[i] = c;
+        e[i] = (double)P.E[c];
         const Philox4 w = philox4x64((uint64_t)i, (uint64_t)round, (uint64_t)L, 0, sh.run_seed, kTagSwap);
-        const int ci = at[i], cj = at[i + 1];
-        const double x = (P.beta64[i] - P.beta64[i + 1]) * ((double)P.E[ci] - (double)P.E[cj]);
-        const bool accept = (x >= 0.0) || (uniform01<double>(w.v[0]) < exp(x));
-        if (accept) {
-            at[i] = cj;
-            at[i + 1] = ci;
-            P.temp_of[ci] = i + 1;
-            P.temp_of[cj] = i;
-            P.swap_acc[(size_t)L * (T - 1) + i] += 1ull;
+        u[i] = uniform01<double>(w.v[0]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i + 1 < T; ++i) {
+            const double x = (P.beta64[i] - P.beta64[i + 1]) * (e[i] - e[i + 1]);
+            if ((x >= 0.0) || (u[i] < exp(x))) {
+                const int ci = at_s[i];
+                at_s[i] = at_s[i + 1];
+                at_s[i + 1] = ci;
+                const double ei = e[i];
+                e[i] = e[i + 1];
+                e[i + 1] = ei;
+                P.swap_acc[(size_t)L * (T - 1) + i] += 1ull;
+            }
         }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < T; i += 64) {
+        at[i] = at_s[i];
+        P.temp_of[at_s[i]] = i;
     }
 }
 
@@ -518,6 +537,11 @@ __global__ __launch_bounds__(64) void k_measure(DevPtrs<R> P, ShapeInfo sh) {
         eQ += E * E;
         y2S += s2 / (s1 * s1);
         y4S += s4 / (s2 * s2);
+        if (lane == 0) {  // distribution of the total intensity I = sum |a|^2
+            int bI = (int)floor(s1 / (double)N * sh.n_bins);
+            bI = bI < 0 ? 0 : (bI >= sh.n_bins ? sh.n_bins - 1 : bI);
+            P.hist_I[(size_t)st * sh.n_bins + bI] += 1.0;
+        }
     }
     double qS = 0, qQ = 0, q4 = 0, qn = 0, q01 = 0;
     for (int r = 0; r < sh.n_reps; ++r)
@@ -701,7 +725,8 @@ hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int
 template <typename R>
 static hipError_t swap_t(const void* ptrs, const ShapeInfo& sh, hipStream_t st) {
     const int n = sh.n_samples * sh.n_reps;
-    hipLaunchKernelGGL(k_swap<R>, dim3((n + 63) / 64), dim3(64), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh);
+    const size_t lds = (size_t)sh.n_temps * (2 * sizeof(double) + sizeof(int32_t)) + 16;
+    hipLaunchKernelGGL(k_swap<R>, dim3(n), dim3(64), lds, st, *static_cast<const DevPtrs<R>*>(ptrs), sh);
     return hipGetLastError();
 }
 hipError_t launch_swap(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st) {

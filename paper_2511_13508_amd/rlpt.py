@@ -32,7 +32,7 @@ EXPORTS = [
     "rlpt_tune_save", "rlpt_tune_load", "rlpt_autotune", "rlpt_tile_of", "rlpt_mlp_setup", "rlpt_mlp_n_params",
     "rlpt_mlp_set_params", "rlpt_mlp_get_params", "rlpt_mlp_set_pairs", "rlpt_mlp_harvest", "rlpt_mlp_train",
     "rlpt_mlp_forward", "rlpt_mlp_loss_grad", "rlpt_mlp_enable", "rlpt_mlp_move", "rlpt_mlp_stats",
-    "rlpt_mlp_last_move",
+    "rlpt_mlp_last_move", "rlpt_summarize", "rlpt_adaptive_ladder", "rlpt_window_means",
 ]
 
 
@@ -71,7 +71,7 @@ class Config(C.Structure):
 
 
 OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",
-              "swap_acc", "swap_tries", "series_e", "series_q"]
+              "swap_acc", "swap_tries", "series_e", "series_q", "hist_I"]
 
 
 class Obs(C.Structure):
@@ -141,6 +141,9 @@ def lib() -> C.CDLL:
         "rlpt_mlp_move": ([P, d], C.c_int),
         "rlpt_mlp_stats": ([P, P, P], C.c_int),
         "rlpt_mlp_last_move": ([P, i32, P, P, P], C.c_int),
+        "rlpt_summarize": ([P, i32, i32, i32, P, P], C.c_int),
+        "rlpt_adaptive_ladder": ([P, P, i32, d, d, d, P, i32, P], C.c_int),
+        "rlpt_window_means": ([P, i64, P, P, i32, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -401,7 +404,7 @@ class Context:
 
     def observables(self) -> dict:
         S, T, B, Lh = self.S, self.T, self.cfg.n_bins, max(self.cfg.series_len, 1)
-        shapes = {"hist": (S, T, B), "swap_acc": (S, max(T - 1, 1)), "swap_tries": (S, max(T - 1, 1)),
+        shapes = {"hist": (S, T, B), "hist_I": (S, T, B), "swap_acc": (S, max(T - 1, 1)), "swap_tries": (S, max(T - 1, 1)),
                   "series_e": (S, T, Lh), "series_q": (S, T, Lh)}
         out = {f: np.zeros(shapes.get(f, (S, T))) for f in OBS_FIELDS}
         o = Obs(**{f: _ptr(out[f]).value for f in OBS_FIELDS})
@@ -452,6 +455,47 @@ def autotune(graphs, temps, config: Config | None = None, sweeps_per_trial: int 
                                C.c_void_p(stream.cuda_stream), sweeps_per_trial, C.byref(n)))
     stream.synchronize()
     return n.value
+
+
+SUMMARY_FIELDS = ["E", "E_err", "cv", "cv_err", "q2", "q2_err", "kurtosis", "kurtosis_err", "y2", "y2_err", "y4",
+                  "y4_err", "acc_rate", "swap_rate"]
+
+
+class Summary(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in SUMMARY_FIELDS]
+
+
+def summarize(obs: dict, n_modes: int, temps) -> dict:
+    """Per-temperature disorder averages and jackknife errors (rlpt_summarize)."""
+    temps = np.ascontiguousarray(temps, dtype=np.float64)
+    S, T = obs["e_n"].shape
+    arrs = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in obs.items()}
+    o = Obs(**{f: _ptr(arrs[f]).value for f in OBS_FIELDS if f in arrs})
+    out = {f: np.zeros(max(T - 1, 1) if f == "swap_rate" else T) for f in SUMMARY_FIELDS}
+    s = Summary(**{f: _ptr(out[f]).value for f in SUMMARY_FIELDS})
+    _check(lib().rlpt_summarize(C.byref(o), S, T, n_modes, _ptr(temps), C.byref(s)))
+    return out
+
+
+def adaptive_ladder(T_grid, C_grid, T_min: float, T_max: float, c: float = 0.6, capacity: int = 1024) -> np.ndarray:
+    """Temperatures with spacing adapted to the specific heat (rlpt_adaptive_ladder; c is the
+    constant C of the rule)."""
+    Tg = np.ascontiguousarray(T_grid, dtype=np.float64)
+    Cg = np.ascontiguousarray(C_grid, dtype=np.float64)
+    out = np.zeros(capacity)
+    n = C.c_int32()
+    _check(lib().rlpt_adaptive_ladder(_ptr(Tg), _ptr(Cg), len(Tg), T_min, T_max, c, _ptr(out), capacity, C.byref(n)))
+    return out[:n.value].copy()
+
+
+def window_means(x, capacity: int = 64):
+    """Means over doubling windows [0,1), [1,2), [2,4), ... and their starts."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    m = np.zeros(capacity)
+    st = np.zeros(capacity, dtype=np.int64)
+    n = C.c_int32()
+    _check(lib().rlpt_window_means(_ptr(x), len(x), _ptr(m), _ptr(st), capacity, C.byref(n)))
+    return m[:n.value].copy(), st[:n.value].copy()
 
 
 def tau_int(x, c_window: float = 6.0):

@@ -124,3 +124,74 @@ def test_tune_registry_roundtrip(tmp_path):
     with pytest.raises(rlpt.RlptError):
         rlpt.tune_set(64, rlpt.FP32, 0, 128, 4, 1.0)  # more copies than waves
     rlpt.tune_clear()
+
+
+# ------------------------------------------------------------------ analysis (host)
+def synthetic_accumulators(S, T, seed, gaussian_q=True):
+    """Accumulators of synthetic per-sample measurement streams (test input)."""
+    rng = np.random.default_rng(seed)
+    acc = {k: np.zeros((S, T)) for k in ("e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4")}
+    raw = {"E": [], "q": []}
+    for mu in range(S):
+        E = rng.normal(-10 + mu, 2.0 + 0.1 * mu, size=(2000, T))
+        q = rng.normal(0.0, 0.2, size=(2000, T)) if gaussian_q else rng.uniform(-0.5, 0.5, size=(2000, T))
+        y2 = rng.uniform(0.05, 0.1, size=(2000, T))
+        acc["e_n"][mu] = 2000
+        acc["e_sum"][mu] = E.sum(0)
+        acc["e_sq"][mu] = (E ** 2).sum(0)
+        acc["y2_sum"][mu] = y2.sum(0)
+        acc["y4_sum"][mu] = (y2 ** 2).sum(0)
+        acc["q_n"][mu] = 2000
+        acc["q_sum"][mu] = q.sum(0)
+        acc["q_sq"][mu] = (q ** 2).sum(0)
+        acc["q_4"][mu] = (q ** 4).sum(0)
+        raw["E"].append(E)
+        raw["q"].append(q)
+    return acc, raw
+
+
+def test_summarize_matches_oracle_and_closed_forms():
+    from oracle import analysis
+    S, T, N = 6, 5, 32
+    temps = np.linspace(0.5, 1.5, T)
+    acc, raw = synthetic_accumulators(S, T, 3)
+    lib = rlpt.summarize(acc, N, temps)
+    ref = analysis.summarize(acc, N, temps)
+    for k in ("E", "E_err", "cv", "cv_err", "y2", "y2_err", "y4", "y4_err", "q2", "q2_err", "kurtosis", "kurtosis_err"):
+        np.testing.assert_allclose(lib[k], ref[k], rtol=1e-10, atol=1e-14, err_msg=k)
+    # C_V from the raw streams, kurtosis of Gaussian overlaps ~ 3, uniform overlaps 9/5
+    cv = np.mean([np.var(e, axis=0) for e in raw["E"]], axis=0) / temps ** 2 / N
+    np.testing.assert_allclose(lib["cv"], cv, rtol=1e-9)
+    assert np.all(np.abs(lib["kurtosis"] - 3.0) < 0.15)
+    acc_u, _ = synthetic_accumulators(S, T, 4, gaussian_q=False)
+    assert np.all(np.abs(rlpt.summarize(acc_u, N, temps)["kurtosis"] - 1.8) < 0.06)
+
+
+def test_adaptive_ladder_closed_form_and_oracle():
+    from oracle import analysis
+    # constant C_V: geometric ladder with ratio 1 / (1 - C / sqrt(C_V))
+    Tg = np.linspace(0.1, 3.0, 50)
+    lad = rlpt.adaptive_ladder(Tg, np.full(50, 400.0), 0.2, 1.0, c=0.6)
+    r = 1.0 / (1.0 - 0.6 / 20.0)
+    np.testing.assert_allclose(lad, 0.2 * r ** np.arange(len(lad)), rtol=1e-12)
+    assert lad[-1] < 1.0 <= lad[-1] * r
+    # a peaked C_V: denser temperatures near the peak; every step solves eq. PT_Ti
+    Cg = 300.0 + 2000.0 * np.exp(-((Tg - 0.5) / 0.08) ** 2)
+    lad = rlpt.adaptive_ladder(Tg, Cg, 0.2, 1.0, c=0.6)
+    np.testing.assert_allclose(lad, analysis.adaptive_ladder(Tg, Cg, 0.2, 1.0, C=0.6), rtol=1e-9)
+    res = lad[1:] * (1 - 0.6 / np.sqrt(np.interp(lad[1:], Tg, Cg))) - lad[:-1]
+    assert np.max(np.abs(res)) < 1e-10
+    d = np.diff(lad) / lad[:-1]
+    assert d[np.argmin(np.abs(lad[:-1] - 0.5))] < d[0]
+    with pytest.raises(rlpt.RlptError):
+        rlpt.adaptive_ladder(Tg, np.full(50, 0.3), 0.2, 1.0, c=0.6)
+
+
+def test_window_means_doubling():
+    from oracle import analysis
+    x = np.arange(100.0)
+    m, st = rlpt.window_means(x)
+    assert list(st) == [0, 1, 2, 4, 8, 16, 32, 64]
+    np.testing.assert_allclose(m, [0.0, 1.0, 2.5, 5.5, 11.5, 23.5, 47.5, 81.5])
+    y = np.random.default_rng(2).standard_normal(777)
+    np.testing.assert_allclose(rlpt.window_means(y)[0], analysis.window_means(y), rtol=1e-13)

@@ -150,6 +150,7 @@ def compare_fp64(ctx, ors, state_tol=1e-9):
         for f in ("e_sum", "e_sq", "y2_sum", "y4_sum", "q_sum", "q_sq", "q_4"):
             np.testing.assert_allclose(obs[f][mu], A[f], rtol=1e-9, atol=1e-9)
         assert np.array_equal(obs["hist"][mu], A["hist"])
+        assert np.array_equal(obs["hist_I"][mu], A["hist_I"])
 
 
 @pytest.mark.parametrize("layout", [PK, CH])
