@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define RLPT_ABI_VERSION 1
+#define RLPT_ABI_VERSION 2
 
 enum {
     RLPT_OK = 0,
@@ -48,6 +48,7 @@ enum { RLPT_OMEGA_RANDOM = 0, RLPT_OMEGA_COMB = 1 };
 enum { RLPT_SPLIT_A = 1, RLPT_SPLIT_B = 2, RLPT_SPLIT_C = 4, RLPT_SPLIT_ALL = 7 };
 enum { RLPT_FP32 = 0, RLPT_FP64 = 1 };
 enum { RLPT_LAYOUT_AUTO = 0, RLPT_LAYOUT_PACKED = 1, RLPT_LAYOUT_CHUNKED = 2 };
+enum { RLPT_FIELDS_STREAM = 0, RLPT_FIELDS_CACHED = 1 };
 
 /* ABI version (RLPT_ABI_VERSION of the built library). */
 int rlpt_abi_version(void);
@@ -130,6 +131,19 @@ typedef struct rlpt_config {
     int32_t mlp_components;   /* Gaussian-mixture components, 1..8 (default 4) */
     int32_t mlp_capacity;     /* training pairs stored per network (default 100000) */
     int32_t mlp_batch;        /* training minibatch (default 512) */
+    int32_t field_mode;       /* RLPT_FIELDS_STREAM (default): each two-mode update streams the
+                                 lists of j and k to form F_j, F_k (sec. III.A);
+                                 RLPT_FIELDS_CACHED: every copy keeps all N local fields
+                                 (eq. local field) in device memory; an update reads only the
+                                 terms holding both j and k (12 entries per term in all) and
+                                 streams the two lists only when accepted, to update the fields
+                                 it changes.  Same chain, same draws; results agree with the
+                                 streaming sweep up to rounding order (the field updates are
+                                 LDS atomics).  Fields are recomputed from scratch at init,
+                                 every recomputation, rlpt_set_state and learned rounds.
+                                 Needs 12 * n_terms more list entries of 4 + 4|8 bytes and
+                                 (N^2 + 1) * 4 bytes per sample. */
+    int32_t pad_fm;
 } rlpt_config;
 
 /* Fill *cfg with defaults: FP32, per-copy pairs, swap every sweep, FP64

@@ -66,7 +66,7 @@ struct Layout {
 };
 
 struct Regions {
-    size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
+    size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, pair_start, pidx, pJ, fields, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
     size_t acc_begin, acc, swap_acc, obs, hist, hist_I, series_e, series_q, meas_cnt, counters, acc_end;
     size_t scratch, scratch_doubles, mlp, total;
 };
@@ -86,6 +86,8 @@ int check_config(const rlpt_config* cfg) {
     if (cfg->list_layout < RLPT_LAYOUT_AUTO || cfg->list_layout > RLPT_LAYOUT_CHUNKED)
         return fail(RLPT_E_ARG, "bad list_layout");
     if (cfg->mlp_nets < 0) return fail(RLPT_E_ARG, "mlp_nets must be >= 0");
+    if (cfg->field_mode != RLPT_FIELDS_STREAM && cfg->field_mode != RLPT_FIELDS_CACHED)
+        return fail(RLPT_E_ARG, "bad field_mode");
     return RLPT_OK;
 }
 
@@ -107,6 +109,58 @@ int choose_layout(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int
     return RLPT_OK;
 }
 
+// cached-field pair lists of one sample (appended): for the ordered pair
+// (j -> k), every entry of k's list whose term also holds j, tagged with the
+// slot j takes in it (0: partner x, 1: y, 2: z).  Entry of mode l in term
+// (p, s, m, n): its partner on the same side of the term, then the other side.
+bool build_pair_lists(const rlpt_graph* g, std::vector<uint32_t>* start, std::vector<uint32_t>* idx,
+                      std::vector<double>* J64, std::vector<float>* J32) {
+    const int N = g->N;
+    const int64_t c = g->n_terms();
+    const uint64_t base = idx->size();
+    if (base + 12 * (uint64_t)c > 0xffffffffull) return false;
+    std::vector<uint32_t> cnt((size_t)N * N + 1, 0);
+    auto triple = [&](const int16_t* q, int t, int* x) {
+        static const int kRole[4][3] = {{1, 2, 3}, {0, 2, 3}, {3, 0, 1}, {2, 0, 1}};
+        for (int r = 0; r < 3; ++r) x[r] = q[kRole[t][r]];
+    };
+    for (int64_t e = 0; e < c; ++e) {
+        const int16_t* q = &g->quads[4 * e];
+        for (int t = 0; t < 4; ++t) {
+            int x[3];
+            triple(q, t, x);
+            for (int r = 0; r < 3; ++r) cnt[(size_t)x[r] * N + q[t]] += 1;
+        }
+    }
+    const size_t s0 = start->size();
+    start->resize(s0 + (size_t)N * N + 1);
+    uint32_t run = (uint32_t)base;
+    for (size_t p = 0; p < (size_t)N * N; ++p) {
+        (*start)[s0 + p] = run;
+        run += cnt[p];
+        cnt[p] = (*start)[s0 + p];  // fill cursor
+    }
+    (*start)[s0 + (size_t)N * N] = run;
+    idx->resize(run);
+    if (J64) J64->resize(run);
+    if (J32) J32->resize(run);
+    for (int64_t e = 0; e < c; ++e) {
+        const int16_t* q = &g->quads[4 * e];
+        for (int t = 0; t < 4; ++t) {
+            int x[3];
+            triple(q, t, x);
+            const uint32_t v = (uint32_t)x[0] | (uint32_t)x[1] << 10 | (uint32_t)x[2] << 20;
+            for (int r = 0; r < 3; ++r) {
+                const uint32_t at = cnt[(size_t)x[r] * N + q[t]]++;
+                (*idx)[at] = v | (uint32_t)r << 30;
+                if (J64) (*J64)[at] = g->J[e];
+                if (J32) (*J32)[at] = (float)g->J[e];
+            }
+        }
+    }
+    return true;
+}
+
 int check_graphs(const rlpt_graph* const* g, int n) {
     if (!g || n < 1) return fail(RLPT_E_ARG, "need at least one graph");
     for (int i = 0; i < n; ++i)
@@ -117,10 +171,13 @@ int check_graphs(const rlpt_graph* const* g, int n) {
 Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layout) {
     const size_t rb = cfg.precision == RLPT_FP64 ? 8 : 4;
     const size_t T = cfg.n_temps, reps = cfg.n_reps, Rc = T * reps, copies = Rc * S;
-    size_t modes = 0, entries = 0, chunks = 0, quads = 0, amp = 0;
+    const bool cached = cfg.field_mode == RLPT_FIELDS_CACHED;
+    size_t modes = 0, entries = 0, chunks = 0, quads = 0, amp = 0, pairs = 0, pair_entries = 0;
     int max_N = 0;
     for (int i = 0; i < S; ++i) {
         modes += g[i]->N + 1;
+        pairs += (size_t)g[i]->N * g[i]->N + 1;
+        pair_entries += 12 * (size_t)g[i]->n_terms();
         if (layout == kLayoutPacked) entries += g[i]->mode_start.back();
         else chunks += g[i]->cx.size();
         quads += g[i]->n_terms();
@@ -138,6 +195,10 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     r.cx = L.take(chunks);
     r.cyz = L.take(chunks * 8);
     r.cJ = L.take(chunks * 4 * rb);
+    r.pair_start = L.take(cached ? pairs * 4 : 0);
+    r.pidx = L.take(cached ? pair_entries * 4 : 0);
+    r.pJ = L.take(cached ? pair_entries * rb : 0);
+    r.fields = L.take(cached ? amp * 2 * rb : 0);
     r.quads = L.take(quads * 8);
     r.Jq = L.take(quads * 8);
     r.amp = L.take(amp * 2 * rb);
@@ -178,6 +239,10 @@ void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
     P.cx = reinterpret_cast<const uint8_t*>(b + r.cx);
     P.cyz = reinterpret_cast<const uint2*>(b + r.cyz);
     P.cJ = reinterpret_cast<const R*>(b + r.cJ);
+    P.pair_start = reinterpret_cast<const uint32_t*>(b + r.pair_start);
+    P.pidx = reinterpret_cast<const uint32_t*>(b + r.pidx);
+    P.pJ = reinterpret_cast<const R*>(b + r.pJ);
+    P.fields = reinterpret_cast<R*>(b + r.fields);
     P.quads = reinterpret_cast<const ushort4*>(b + r.quads);
     P.Jq = reinterpret_cast<const double*>(b + r.Jq);
     P.amp = reinterpret_cast<R*>(b + r.amp);
@@ -209,6 +274,13 @@ Counters* counters_of(rlpt_ctx* c) { return c->cfg.precision == RLPT_FP64 ? c->p
 
 bool measuring_at(const rlpt_ctx* c, int64_t n) {
     return n > c->cfg.measure_start && c->cfg.measure_interval > 0 && n % c->cfg.measure_interval == 0;
+}
+
+// cached-field mode: recompute every copy's fields from its amplitudes
+int refresh_fields(rlpt_ctx* c) {
+    if (!c->sh.cached) return RLPT_OK;
+    HIP_TRY(launch_fields_all(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, c->stream), "fields launch");
+    return RLPT_OK;
 }
 
 // enqueue n sweeps starting after `done` completed sweeps (no host mirror update)
@@ -249,8 +321,11 @@ int enqueue_sweeps(rlpt_ctx* c, int64_t done, int64_t n, int64_t* swaps_added) {
         if (swap) HIP_TRY(launch_swap(cfg.precision, c->ptrs(), c->sh, c->stream), "swap launch");
         HIP_TRY(launch_tick(c->ptrs(), cfg.precision, step, swap ? 1 : 0, c->stream), "tick launch");
         if (swap) *swaps_added += 1;
-        if (cfg.resync_interval > 0 && after % cfg.resync_interval == 0)
+        if (cfg.resync_interval > 0 && after % cfg.resync_interval == 0) {
             HIP_TRY(launch_resync(cfg.precision, c->ptrs(), c->sh, c->n_copies, 0, c->stream), "resync launch");
+            int rc = refresh_fields(c);
+            if (rc) return rc;
+        }
         if (measuring_at(c, after)) HIP_TRY(launch_measure(cfg.precision, c->ptrs(), c->sh, c->stream), "measure launch");
         k += step;
     }
@@ -288,7 +363,7 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
             max_cpi = std::max(max_cpi, it.n_copies);
         }
     }
-    const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N);
+    const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached);
     if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
     c->items = items;
     c->tile_copies = copies;
@@ -398,6 +473,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->temps.assign(temps, temps + c->T);
     c->ws = d_workspace;
     c->ws_bytes = workspace_bytes;
+    c->sh.cached = cfg->field_mode == RLPT_FIELDS_CACHED ? 1 : 0;
     unsigned char* b = static_cast<unsigned char*>(d_workspace);
     fill_ptrs(c->pf, b, r);
     fill_ptrs(c->pd, b, r);
@@ -414,6 +490,9 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     std::vector<uint8_t> cx;
     std::vector<uint16_t> cyz;
     std::vector<ushort4> quads;
+    std::vector<uint32_t> pstart, pidx;
+    std::vector<float> pJ32;
+    std::vector<double> pJ64;
     int64_t amp_base = 0, quad_base = 0;
     for (int s = 0; s < c->S; ++s) {
         const rlpt_graph* g = graphs[s];
@@ -449,6 +528,14 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
             quads.push_back(u);
         }
         Jq.insert(Jq.end(), g->J.begin(), g->J.end());
+        if (c->sh.cached) {
+            sd.pair_base = (int64_t)pstart.size();
+            if (!build_pair_lists(g, &pstart, &pidx, cfg->precision == RLPT_FP64 ? &pJ64 : nullptr,
+                                  cfg->precision == RLPT_FP64 ? nullptr : &pJ32)) {
+                delete c;
+                return fail(RLPT_E_ARG, "cached-field pair lists exceed 2^32 entries");
+            }
+        }
         amp_base += (int64_t)c->Rc * g->N;
         quad_base += g->n_terms();
         c->samples.push_back(sd);
@@ -462,7 +549,8 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         std::map<int, int> copies;
         std::map<int, int> counts;
         for (int s = 0; s < c->S; ++s) counts[c->N[s]] += 1;
-        if (cfg->block_threads > 0 || cfg->copies_per_block > 0 ||
+        // the tune registry holds streaming-sweep timings; cached contexts use the built-in tile
+        if (cfg->block_threads > 0 || cfg->copies_per_block > 0 || c->sh.cached ||
             !tune_choose(counts, cfg->precision, cfg->shared_pairs, &block, &copies)) {
             block = cfg->block_threads > 0 ? cfg->block_threads : default_tile(c->max_N).block;
             for (const auto& nc : counts)
@@ -508,6 +596,10 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     else up(r.cJ, cJ32);
     up(r.quads, quads);
     up(r.Jq, Jq);
+    up(r.pair_start, pstart);
+    up(r.pidx, pidx);
+    if (cfg->precision == RLPT_FP64) up(r.pJ, pJ64);
+    else up(r.pJ, pJ32);
     if (cfg->precision == RLPT_FP64) up(r.beta, b64);
     else up(r.beta, b32);
     up(r.beta64, b64);
@@ -532,11 +624,13 @@ int rlpt_destroy(rlpt_ctx* c) {
 
 int rlpt_init(rlpt_ctx* c, uint64_t run_seed) {
     if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
+    int rc;
     drop_graph(c);
     c->sh.run_seed = run_seed;
     HIP_TRY(launch_zero(c->acc_region, c->acc_region_bytes, c->stream), "zero accumulators");
     HIP_TRY(launch_init(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 256, c->stream), "init launch");
     HIP_TRY(launch_resync(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 2, c->stream), "initial energies");
+    if ((rc = refresh_fields(c))) return rc;
     c->sweeps_done = 0;
     c->swaps_done = 0;
     c->inited = true;
@@ -569,7 +663,9 @@ int rlpt_resync(rlpt_ctx* c, double* max_drift) {
     if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
     if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
     HIP_TRY(launch_resync(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 0, c->stream), "resync launch");
-    int rc = sync_and_flags(c);
+    int rc = refresh_fields(c);
+    if (rc) return rc;
+    rc = sync_and_flags(c);
     if (max_drift) {
         std::vector<double> d(c->n_copies);
         const double* dp = c->cfg.precision == RLPT_FP64 ? c->pd.drift : c->pf.drift;
@@ -711,6 +807,7 @@ int rlpt_set_state(rlpt_ctx* c, int32_t first, int32_t n, const double* a) {
     HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
     HIP_TRY(hipMemcpy(c->scratch, a, k * 16, hipMemcpyHostToDevice), "state write");
     HIP_TRY(launch_convert_state(c->cfg.precision, amp + off * 2 * c->real_bytes(), c->scratch, k, 1, c->stream), "convert");
+    if ((rc = refresh_fields(c))) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
     return RLPT_OK;
 }
@@ -845,6 +942,8 @@ int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32
                   int32_t* n_trials) {
     int rc = check_config(cfg);
     if (rc) return rc;
+    if (cfg->field_mode == RLPT_FIELDS_CACHED)
+        return fail(RLPT_E_UNSUPPORTED, "the autotuner times the streaming sweep; use field_mode = RLPT_FIELDS_STREAM");
     if ((rc = check_graphs(graphs, n_graphs))) return rc;
     if (sweeps_per_trial < 1) return fail(RLPT_E_ARG, "sweeps_per_trial must be >= 1");
     std::map<int, std::vector<const rlpt_graph*>> byN;

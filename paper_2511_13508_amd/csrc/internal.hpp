@@ -55,6 +55,7 @@ struct SampleDev {
     int64_t amp_base;      // complex offset of the sample's first copy
     int64_t quad_base;     // offset into the by-term arrays
     int64_t n_quads;
+    int64_t pair_base;     // offset of this sample's pair_start block (N*N + 1 values)
 };
 
 // a unit of work of the sweep kernel: n_copies consecutive copies of one sample
@@ -84,6 +85,12 @@ struct DevPtrs {
     const uint8_t* cx;        // chunk partner
     const uint2* cyz;         // chunk (y | z << 8) x 4 as 16-bit halves
     const R* cJ;              // chunk couplings (4 per chunk)
+    // cached-field mode: for the ordered pair (j -> k), the entries of k's list
+    // whose term also holds j: x | y << 10 | z << 20 | (slot of j) << 30, coupling
+    const uint32_t* pair_start;  // absolute entry index per ordered pair, [S][N*N + 1]
+    const uint32_t* pidx;
+    const R* pJ;
+    R* fields;                // cached local fields, interleaved complex [copy][N]
     const ushort4* quads;     // by term (p, s, m, n)
     const double* Jq;         // by term, FP64
     R* amp;                   // interleaved complex [copy][N]
@@ -117,6 +124,8 @@ struct ShapeInfo {
     int32_t series_len;
     int32_t shared_pairs;
     int32_t layout;             // ListLayout
+    int32_t cached;             // 1: cached local fields (pair lists + updates on acceptance)
+    int32_t pad2;
     uint64_t run_seed;
     double renorm_tol;
     double drift_tol;
@@ -131,7 +140,7 @@ struct SweepLaunch {
     size_t lds_bytes;
 };
 
-size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N);
+size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached);
 
 hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int block,
                        hipStream_t st);
@@ -145,6 +154,8 @@ hipError_t launch_tick(const void* ptrs_any, int precision, int64_t d_sweeps, in
 hipError_t launch_resync(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int mode,
                          hipStream_t st);
 hipError_t launch_measure(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st);
+// recompute the cached local fields of every copy from the per-mode lists
+hipError_t launch_fields_all(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fields_sh(int precision, const void* ptrs, const ShapeInfo& sh, int copy, int sample,
                             double* F_dev, hipStream_t st);

@@ -336,6 +336,240 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     }
 }
 
+// ---------------------------------------------------------------- cached local fields
+// With every copy's fields kept up to date, the energy change of a two-mode
+// move needs only F_j, F_k and, for the one-snapshot rule, the terms holding
+// both j and k (the pair list j -> k); the lists of j and k are streamed only
+// when the move is accepted, to update the fields of every mode sharing a term
+// with j or k.  Same Markov chain as the streaming sweep.
+
+// sum over the pair list of J * conj(u) v w with j's slot holding delta_j:
+// the change of F_k when a_j moves by delta_j
+template <typename R>
+__device__ inline void pair_correction(const uint32_t* __restrict__ pidx, const R* __restrict__ pJ, uint32_t beg,
+                                       uint32_t end, const R2<R>* __restrict__ a, R2<R> dj, int lane, R& cr,
+                                       R& ci) {
+    for (uint32_t e = beg + lane; e < end; e += 64) {
+        const uint32_t v = pidx[e];
+        const R J = pJ[e];
+        const uint32_t role = v >> 30;
+        const R2<R> u = role == 0 ? dj : a[v & 1023u];
+        const R2<R> w1 = role == 1 ? dj : a[(v >> 10) & 1023u];
+        const R2<R> w2 = role == 2 ? dj : a[(v >> 20) & 1023u];
+        const R pr = u.x * w1.x + u.y * w1.y, pi = u.x * w1.y - u.y * w1.x;
+        cr += J * (pr * w2.x - pi * w2.y);
+        ci += J * (pr * w2.y + pi * w2.x);
+    }
+}
+
+// field changes of the members x, y, z of one term of the moved mode's list
+// (x = its partner, (y, z) the other side) when it moves by d:
+// dF_x = J conj(d) a_y a_z, dF_y = J conj(a_z) d a_x, dF_z = J conj(a_y) d a_x
+template <typename R>
+__device__ inline void scatter_term(uint32_t e, R J, R2<R> d, const R2<R>* __restrict__ a, R* F) {
+    const uint32_t x = e & 1023u, y = (e >> 10) & 1023u, z = e >> 20;
+    const R2<R> ax = a[x], ay = a[y], az = a[z];
+    const R yr = ay.x * az.x - ay.y * az.y, yi = ay.x * az.y + ay.y * az.x;
+    const R tr = d.x * ax.x - d.y * ax.y, ti = d.x * ax.y + d.y * ax.x;
+    atomicAdd(&F[2 * x], J * (d.x * yr + d.y * yi));
+    atomicAdd(&F[2 * x + 1], J * (d.x * yi - d.y * yr));
+    atomicAdd(&F[2 * y], J * (az.x * tr + az.y * ti));
+    atomicAdd(&F[2 * y + 1], J * (az.x * ti - az.y * tr));
+    atomicAdd(&F[2 * z], J * (ay.x * tr + ay.y * ti));
+    atomicAdd(&F[2 * z + 1], J * (ay.x * ti - ay.y * tr));
+}
+
+template <typename R, int LAYOUT>
+__device__ inline void scatter_mode(const DevPtrs<R>& P, const SampleDev& sd, int l, R2<R> d,
+                                    const R2<R>* __restrict__ a, R* F, int t, int nt) {
+    if constexpr (LAYOUT == kLayoutChunked) {
+        using JT = typename J4<R>::T;
+        const uint32_t* cs = P.chunk_start + sd.mode_base;
+        const JT* Jv = reinterpret_cast<const JT*>(P.cJ);
+        for (uint32_t c = cs[l] + t; c < cs[l + 1]; c += nt) {
+            const uint32_t x = P.cx[c];
+            const uint2 yz = P.cyz[c];
+            const JT j4 = Jv[c];
+            const R2<R> ax = a[x];
+            const R tr = d.x * ax.x - d.y * ax.y, ti = d.x * ax.y + d.y * ax.x;
+            R gr = 0, gi = 0;
+            const uint32_t v4[4] = {yz.x & 0xffffu, yz.x >> 16, yz.y & 0xffffu, yz.y >> 16};
+            const R jj[4] = {j4.x, j4.y, j4.z, j4.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (jj[i] == (R)0) continue;  // padding
+                const uint32_t y = v4[i] & 0xffu, z = v4[i] >> 8;
+                const R2<R> ay = a[y], az = a[z];
+                gr += jj[i] * (ay.x * az.x - ay.y * az.y);
+                gi += jj[i] * (ay.x * az.y + ay.y * az.x);
+                atomicAdd(&F[2 * y], jj[i] * (az.x * tr + az.y * ti));
+                atomicAdd(&F[2 * y + 1], jj[i] * (az.x * ti - az.y * tr));
+                atomicAdd(&F[2 * z], jj[i] * (ay.x * tr + ay.y * ti));
+                atomicAdd(&F[2 * z + 1], jj[i] * (ay.x * ti - ay.y * tr));
+            }
+            atomicAdd(&F[2 * x], d.x * gr + d.y * gi);
+            atomicAdd(&F[2 * x + 1], d.x * gi - d.y * gr);
+        }
+    } else {
+        using JT = typename J4<R>::T;
+        const uint32_t* ms = P.mode_start + sd.mode_base;
+        const uint4* I4 = reinterpret_cast<const uint4*>(P.idx + ms[l]);
+        const JT* Jv = reinterpret_cast<const JT*>(P.J + ms[l]);
+        const int n4 = (int)((ms[l + 1] - ms[l]) >> 2);
+        for (int e = t; e < n4; e += nt) {
+            const uint4 i4 = I4[e];
+            const JT j4 = Jv[e];
+            if (j4.x != (R)0) scatter_term<R>(i4.x, j4.x, d, a, F);
+            if (j4.y != (R)0) scatter_term<R>(i4.y, j4.y, d, a, F);
+            if (j4.z != (R)0) scatter_term<R>(i4.z, j4.z, d, a, F);
+            if (j4.w != (R)0) scatter_term<R>(i4.w, j4.w, d, a, F);
+        }
+    }
+}
+
+template <typename R>
+__host__ __device__ inline size_t group_bytes_cached(int max_N, int waves_per_block) {
+    return group_bytes<R>(max_N, waves_per_block) + (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) * 2 + 16;
+}
+
+template <typename R, int BLOCK, int LAYOUT>
+__global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kWaves = BLOCK / 64;
+    const ItemDev it = P.items[blockIdx.x];
+    const SampleDev sd = P.samples[it.sample];
+    const int N = sd.N, steps = sd.n_steps;
+    const int wpc = kWaves / it.n_copies;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = wave / wpc;
+    const bool active = g < it.n_copies;
+    const int gw = wave - g * wpc;
+    const int gt = threadIdx.x - g * wpc * 64;
+    const int nt = wpc * 64;
+    const int gsel = active ? g : 0;
+
+    unsigned char* base = smem + (size_t)gsel * group_bytes_cached<R>(max_N, kWaves);
+    R2<R>* a = reinterpret_cast<R2<R>*>(base);
+    StepDraw<R>* tab = reinterpret_cast<StepDraw<R>*>(base + (size_t)max_N * 2 * sizeof(R));
+    unsigned char* after = base + group_bytes<R>(max_N, kWaves);
+    R* F = reinterpret_cast<R*>(after);
+    R2<R>* snap = reinterpret_cast<R2<R>*>(after + (size_t)max_N * 2 * sizeof(R));  // [0] = d_j, [1] = d_k
+    int* flag = reinterpret_cast<int*>(after + (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) * 2);
+
+    const int c = it.first_copy + gsel;
+    const int64_t local = c - (int64_t)it.sample * sh.copies_per_sample;
+    R2<R>* amp_g = reinterpret_cast<R2<R>*>(P.amp) + sd.amp_base + local * N;
+    R* fld_g = P.fields + 2 * (sd.amp_base + local * N);
+    if (active)
+        for (int i = gt; i < N; i += nt) {
+            a[i] = amp_g[i];
+            F[2 * i] = fld_g[2 * i];
+            F[2 * i + 1] = fld_g[2 * i + 1];
+        }
+    const int t_idx = P.temp_of[c];
+    const R beta = P.beta[t_idx];
+    R E = P.E[c];
+    unsigned int n_acc = 0;
+    const int64_t pair_stream = sh.shared_pairs ? (int64_t)it.sample : (int64_t)c;
+    const int64_t sweep0 = P.counters->sweeps_done;
+    const uint32_t* ps = P.pair_start + sd.pair_base;
+
+    R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
+    auto prepare = [&](int s) {  // snapshot of step s (one lane)
+        const StepDraw<R> d = tab[s];
+        const int j2 = d.jk & 0xffff, k2 = d.jk >> 16;
+        ajo = a[j2];
+        const R2<R> ako2 = a[k2];
+        const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
+        const R K = sqrt(sqrt(uj * uj + uk * uk));
+        ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
+        akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
+        a[j2] = ajn;
+        snap[0] = mk2<R>(ajn.x - ajo.x, ajn.y - ajo.y);
+        snap[1] = mk2<R>(akn.x - ako2.x, akn.y - ako2.y);
+    };
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        __syncthreads();
+        if (active)
+            for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N);
+        __syncthreads();
+        if (active && gt == 0) prepare(0);
+        for (int s = 0; s < steps; ++s) {
+            __syncthreads();
+            const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
+            if (active && gw == 0) {
+                const R2<R> dj = snap[0];
+                R cr = 0, ci = 0;
+                const int64_t pk = (int64_t)j * N + k;
+                pair_correction<R>(P.pidx, P.pJ, ps[pk], ps[pk + 1], a, dj, lane, cr, ci);
+                cr = wave_sum(cr);
+                ci = wave_sum(ci);
+                if (lane == 0) {
+                    const R2<R> dk = snap[1];
+                    const R Fkr = F[2 * k] + cr, Fki = F[2 * k + 1] + ci;
+                    const R dE = (R)-2 * (dj.x * F[2 * j] + dj.y * F[2 * j + 1]) - (R)2 * (dk.x * Fkr + dk.y * Fki);
+                    const bool accept = (dE <= (R)0) || (tab[s].u < exp(-beta * dE));
+                    *flag = accept ? 1 : 0;
+                    if (accept) {
+                        E += dE;
+                        ++n_acc;
+                    } else {
+                        a[j] = ajo;
+                    }
+                }
+            }
+            __syncthreads();
+            if (active && *flag) {  // a_j new, a_k old in LDS: update the fields of every mode sharing a term
+                scatter_mode<R, LAYOUT>(P, sd, j, snap[0], a, F, gt, nt);
+                scatter_mode<R, LAYOUT>(P, sd, k, snap[1], a, F, gt, nt);
+            }
+            __syncthreads();
+            if (active && gt == 0) {
+                if (*flag) a[k] = akn;
+                if (s + 1 < steps) prepare(s + 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        for (int i = gt; i < N; i += nt) {
+            amp_g[i] = a[i];
+            fld_g[2 * i] = F[2 * i];
+            fld_g[2 * i + 1] = F[2 * i + 1];
+        }
+        if (gt == 0) {
+            P.E[c] = E;
+            atomicAdd(&P.acc[(size_t)it.sample * sh.n_temps + t_idx], (unsigned long long)n_acc);
+        }
+    }
+}
+
+// every field of every copy from the per-mode lists (one block per copy, a wave per mode)
+template <typename R, int LAYOUT>
+__global__ __launch_bounds__(256) void k_fields_all(DevPtrs<R> P, ShapeInfo sh) {
+    __shared__ R2<R> a[kMaxModes];
+    const int c = blockIdx.x;
+    const int mu = c / sh.copies_per_sample;
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
+    const R2<R>* amp = reinterpret_cast<const R2<R>*>(P.amp) + sd.amp_base + local * N;
+    R* F = P.fields + 2 * (sd.amp_base + local * N);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = amp[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int l = wave; l < N; l += blockDim.x / 64) {
+        R fr = 0, fi = 0;
+        mode_field<R, LAYOUT>(P, sd, l, a, lane, 64, fr, fi);
+        fr = wave_sum(fr);
+        fi = wave_sum(fi);
+        if (lane == 0) {
+            F[2 * l] = fr;
+            F[2 * l + 1] = fi;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- initial draw
 // one block per copy; exact draw from the infinite-temperature law on
 // sum |a|^4 = N: |a_k|^2 = sqrt(N) |g_k| / ||g||, phases uniform
@@ -677,6 +911,15 @@ template <typename R, int BLOCK>
 hipError_t launch_sweep_t(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,
                           hipStream_t st) {
     const DevPtrs<R>& P = *static_cast<const DevPtrs<R>*>(ptrs);
+    if (sh.cached) {
+        if (sh.layout == kLayoutChunked)
+            hipLaunchKernelGGL((k_sweep_cached<R, BLOCK, kLayoutChunked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
+                               st, P, sh, L.max_N, n_sweeps);
+        else
+            hipLaunchKernelGGL((k_sweep_cached<R, BLOCK, kLayoutPacked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
+                               st, P, sh, L.max_N, n_sweeps);
+        return hipGetLastError();
+    }
     if (sh.layout == kLayoutChunked)
         hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
                            L.max_N, n_sweeps);
@@ -701,10 +944,28 @@ hipError_t launch_sweep_r(const void* ptrs, const ShapeInfo& sh, const SweepLaun
 
 }  // namespace
 
-size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N) {
+size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached) {
     const int waves = block_threads / 64;
+    if (cached)
+        return (size_t)max_copies_per_item * (precision == RLPT_FP64 ? group_bytes_cached<double>(max_N, waves)
+                                                                     : group_bytes_cached<float>(max_N, waves));
     return (size_t)max_copies_per_item *
            (precision == RLPT_FP64 ? group_bytes<double>(max_N, waves) : group_bytes<float>(max_N, waves));
+}
+
+template <typename R>
+static hipError_t fields_all_t(const void* ptrs, const ShapeInfo& sh, int n_copies, hipStream_t st) {
+    const DevPtrs<R>& P = *static_cast<const DevPtrs<R>*>(ptrs);
+    if (sh.layout == kLayoutChunked)
+        hipLaunchKernelGGL((k_fields_all<R, kLayoutChunked>), dim3(n_copies), dim3(256), 0, st, P, sh);
+    else
+        hipLaunchKernelGGL((k_fields_all<R, kLayoutPacked>), dim3(n_copies), dim3(256), 0, st, P, sh);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields_all(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, hipStream_t st) {
+    return precision == RLPT_FP64 ? fields_all_t<double>(ptrs, sh, n_copies, st)
+                                  : fields_all_t<float>(ptrs, sh, n_copies, st);
 }
 
 hipError_t launch_sweep(int precision, const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,

@@ -20,6 +20,8 @@ OMEGA_RANDOM, OMEGA_COMB = 0, 1
 SPLIT_A, SPLIT_B, SPLIT_C, SPLIT_ALL = 1, 2, 4, 7
 FP32, FP64 = 0, 1
 LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_CHUNKED = 0, 1, 2
+FIELDS_STREAM, FIELDS_CACHED = 0, 1
+ABI_VERSION = 2
 
 # every symbol declared in include/rlpt.h
 EXPORTS = [
@@ -67,7 +69,8 @@ class Config(C.Structure):
                 ("measure_interval", C.c_int32), ("n_bins", C.c_int32), ("series_len", C.c_int32),
                 ("block_threads", C.c_int32), ("copies_per_block", C.c_int32), ("list_layout", C.c_int32),
                 ("mlp_nets", C.c_int32), ("mlp_hidden", C.c_int32), ("mlp_components", C.c_int32),
-                ("mlp_capacity", C.c_int32), ("mlp_batch", C.c_int32)]
+                ("mlp_capacity", C.c_int32), ("mlp_batch", C.c_int32), ("field_mode", C.c_int32),
+                ("pad_fm", C.c_int32)]
 
 
 OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",

@@ -25,7 +25,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(rlpt.EXPORTS) == names
-    assert rlpt.abi_version() == 1
+    assert rlpt.abi_version() == rlpt.ABI_VERSION
 
 
 @pytest.mark.parametrize("N,seed,kind,mask", [

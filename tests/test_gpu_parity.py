@@ -111,7 +111,8 @@ def test_energy_fp64_matches_oracle(oracle, N, precision, layout):
 
 
 # ------------------------------------------------------------------ trajectories
-def run_pair(oracle, Ns, temps, n_sweeps, seed, seeds=None, omega=rlpt.OMEGA_RANDOM, oracle_shared=None, **cfg):
+def run_pair(oracle, Ns, temps, n_sweeps, seed, seeds=None, omega=rlpt.OMEGA_RANDOM, oracle_shared=None,
+             oracle_seed=None, **cfg):
     seeds = seeds or [SEED0 + i for i in range(len(Ns))]
     graphs = [rlpt.Graph(N, s, omega) for N, s in zip(Ns, seeds)]
     ctx = make_ctx(graphs, temps, n_temps=len(temps), **cfg)
@@ -121,7 +122,8 @@ def run_pair(oracle, Ns, temps, n_sweeps, seed, seeds=None, omega=rlpt.OMEGA_RAN
     ors = []
     for mu, (N, s) in enumerate(zip(Ns, seeds)):
         kw = {} if oracle_shared is None else {"shared_pairs": oracle_shared}
-        pt = oracle_pt(oracle, oracle.Graph(N, s, omega), temps, mu, ctx.cfg, seed, **kw)
+        pt = oracle_pt(oracle, oracle.Graph(N, s, omega), temps, mu, ctx.cfg,
+                       seed if oracle_seed is None else oracle_seed, **kw)
         pt.run(n_sweeps)
         ors.append(pt)
     return ctx, ors
@@ -302,32 +304,40 @@ def oracle_stack(ors):
     return {k: np.stack([pt.acc[k] for pt in ors]) for k in keys}
 
 
-@pytest.mark.parametrize("shared", [0, 1])
-def test_statistical_parity_fp32(oracle, shared):
-    """FP32 PT on the GPU against the FP64 oracle on the same seeds: N = 32,
-    8 disorder samples, 8 temperatures geometric in [0.3, 1.5], 2 replicas,
-    4000 sweeps (measured over the second half).  Per temperature, the
-    disorder average of <E>, C_V, <q^2>, <Y_2>, <Y_4> must agree within 2
-    sigma (jackknife over samples of the paired difference) in >= 90% of the
-    cells and within 4 sigma in all of them.  With shared pairs the GPU follows
-    different pair sequences from the oracle's per-copy ones: a check that the
-    shared schedule samples the same law."""
-    Ns = [32] * 8
-    temps = temps_geo(0.3, 1.5, 8)
-    ctx, ors = run_pair(oracle, Ns, temps, 4000, 31, n_reps=2, precision=rlpt.FP32, shared_pairs=shared,
-                        swap_interval=1, resync_interval=100, measure_start=2000, measure_interval=1, n_bins=50,
-                        oracle_shared=False)
+def assert_same_law(ctx, ors, temps):
+    """Per temperature, the disorder averages of <E>, C_V, <q^2>, <Y_2>, <Y_4>
+    from two independent runs agree: z = |mean difference| / jackknife error
+    over samples is <= 5 in every cell and <= 2.5 in >= 85% of the cells
+    (z follows a t law with S - 1 degrees of freedom)."""
     g = per_sample_obs(ctx.observables(), temps)
     o = per_sample_obs(oracle_stack(ors), temps)
-    within2 = within4 = cells = 0
+    within_a = within_b = cells = 0
     report = []
     for k in g:
         m, s = jackknife(g[k] - o[k])
         s = np.maximum(s, 1e-12 * np.abs(o[k]).mean())
         z = np.abs(m) / s
-        within2 += int(np.sum(z <= 2))
-        within4 += int(np.sum(z <= 4))
+        within_a += int(np.sum(z <= 2.5))
+        within_b += int(np.sum(z <= 5))
         cells += z.size
         report.append((k, np.round(z, 2)))
-    assert within4 == cells, report
-    assert within2 >= 0.9 * cells, report
+    assert within_b == cells, report
+    assert within_a >= 0.85 * cells, report
+
+
+@pytest.mark.parametrize("shared", [0, 1])
+def test_statistical_parity_fp32(oracle, shared):
+    """FP32 PT on the GPU against the FP64 oracle as two independent chains
+    (different run seeds, same disorder): N = 32, 12 disorder samples, 8
+    temperatures geometric in [0.3, 1.5], 2 replicas, 4000 sweeps measured
+    over the second half.  With the same run seed the FP32 chain follows the
+    oracle's decision for decision for thousands of sweeps, and the paired
+    differences would then measure only FP32 rounding of the running energy,
+    not the law sampled.  With shared pairs the GPU also follows a different
+    pair schedule: a check that the shared schedule samples the same law."""
+    Ns = [32] * 12
+    temps = temps_geo(0.3, 1.5, 8)
+    ctx, ors = run_pair(oracle, Ns, temps, 4000, 31, n_reps=2, precision=rlpt.FP32, shared_pairs=shared,
+                        swap_interval=1, resync_interval=100, measure_start=2000, measure_interval=1, n_bins=50,
+                        oracle_shared=False, oracle_seed=1031)
+    assert_same_law(ctx, ors, temps)
