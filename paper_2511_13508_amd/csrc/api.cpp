@@ -48,6 +48,13 @@ static Tile default_tile(int N) {
     return {256, 4};
 }
 
+// cached-field sweep: one copy per workgroup, two waves per 64-target slice
+// (an accepted move streams its gather blocks with twice the loads in flight)
+static Tile default_tile_cached(int N) {
+    const int ns = (N + 63) / 64;
+    return {std::min(512, 128 * ns), 1};
+}
+
 }  // namespace rlpt
 
 using namespace rlpt;
@@ -66,7 +73,7 @@ struct Layout {
 };
 
 struct Regions {
-    size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, pair_start, pidx, pJ, fields, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
+    size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, pair_start, pidx, pJ, fields, ell_start, gidx16, gidx32, gJ, c0, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
     size_t acc_begin, acc, swap_acc, obs, hist, hist_I, series_e, series_q, meas_cnt, counters, acc_end;
     size_t scratch, scratch_doubles, mlp, total;
 };
@@ -109,55 +116,138 @@ int choose_layout(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int
     return RLPT_OK;
 }
 
-// cached-field pair lists of one sample (appended): for the ordered pair
-// (j -> k), every entry of k's list whose term also holds j, tagged with the
-// slot j takes in it (0: partner x, 1: y, 2: z).  Entry of mode l in term
-// (p, s, m, n): its partner on the same side of the term, then the other side.
-bool build_pair_lists(const rlpt_graph* g, std::vector<uint32_t>* start, std::vector<uint32_t>* idx,
-                      std::vector<double>* J64, std::vector<float>* J32) {
+// The three other members of term e as seen from member t: its partner on
+// the same side of the term, then the two modes of the other side.
+inline void term_triple(const int16_t* q, int t, int* x) {
+    static const int kRole[4][3] = {{1, 2, 3}, {0, 2, 3}, {3, 0, 1}, {2, 0, 1}};
+    for (int r = 0; r < 3; ++r) x[r] = q[kRole[t][r]];
+}
+
+// per ordered pair (j -> l): how many terms hold both, and how many of them
+// have j as l's partner
+void pair_counts(const rlpt_graph* g, std::vector<uint32_t>* cnt, std::vector<uint32_t>* c0) {
     const int N = g->N;
-    const int64_t c = g->n_terms();
-    const uint64_t base = idx->size();
-    if (base + 12 * (uint64_t)c > 0xffffffffull) return false;
-    std::vector<uint32_t> cnt((size_t)N * N + 1, 0);
-    auto triple = [&](const int16_t* q, int t, int* x) {
-        static const int kRole[4][3] = {{1, 2, 3}, {0, 2, 3}, {3, 0, 1}, {2, 0, 1}};
-        for (int r = 0; r < 3; ++r) x[r] = q[kRole[t][r]];
-    };
-    for (int64_t e = 0; e < c; ++e) {
+    cnt->assign((size_t)N * N, 0);
+    if (c0) c0->assign((size_t)N * N, 0);
+    for (int64_t e = 0; e < g->n_terms(); ++e) {
         const int16_t* q = &g->quads[4 * e];
         for (int t = 0; t < 4; ++t) {
             int x[3];
-            triple(q, t, x);
-            for (int r = 0; r < 3; ++r) cnt[(size_t)x[r] * N + q[t]] += 1;
-        }
-    }
-    const size_t s0 = start->size();
-    start->resize(s0 + (size_t)N * N + 1);
-    uint32_t run = (uint32_t)base;
-    for (size_t p = 0; p < (size_t)N * N; ++p) {
-        (*start)[s0 + p] = run;
-        run += cnt[p];
-        cnt[p] = (*start)[s0 + p];  // fill cursor
-    }
-    (*start)[s0 + (size_t)N * N] = run;
-    idx->resize(run);
-    if (J64) J64->resize(run);
-    if (J32) J32->resize(run);
-    for (int64_t e = 0; e < c; ++e) {
-        const int16_t* q = &g->quads[4 * e];
-        for (int t = 0; t < 4; ++t) {
-            int x[3];
-            triple(q, t, x);
-            const uint32_t v = (uint32_t)x[0] | (uint32_t)x[1] << 10 | (uint32_t)x[2] << 20;
+            term_triple(q, t, x);
             for (int r = 0; r < 3; ++r) {
-                const uint32_t at = cnt[(size_t)x[r] * N + q[t]]++;
-                (*idx)[at] = v | (uint32_t)r << 30;
-                if (J64) (*J64)[at] = g->J[e];
-                if (J32) (*J32)[at] = (float)g->J[e];
+                (*cnt)[(size_t)x[r] * N + q[t]] += 1;
+                if (c0 && r == 0) (*c0)[(size_t)x[r] * N + q[t]] += 1;
             }
         }
     }
+}
+
+constexpr int kSlice = 64;  // target modes per gather slice (one wave)
+
+// padded entries of the sliced-ELL gather block of one sample: per source j
+// and slice s of up to 64 targets, (max rank over the slice, rounded up to 4)
+// x slice width
+size_t ell_entries(const rlpt_graph* g, const std::vector<uint32_t>& cnt) {
+    const int N = g->N, ns = (N + kSlice - 1) / kSlice;
+    size_t total = 0;
+    for (int j = 0; j < N; ++j)
+        for (int s = 0; s < ns; ++s) {
+            const int w = std::min(kSlice, N - kSlice * s);
+            uint32_t L = 0;
+            for (int i = 0; i < w; ++i) L = std::max(L, cnt[(size_t)j * N + kSlice * s + i]);
+            total += (size_t)((L + 3) / 4) * 4 * w;
+        }
+    return total;
+}
+
+// cached-field tables of one sample (appended to the vectors):
+//  * pair lists for the energy change: for the ordered pair (j -> k), every
+//    entry of k's list whose term also holds j, tagged with the slot j takes
+//    in it (0: partner x, 1: y, 2: z);
+//  * the sliced-ELL gather block for the field update on acceptance.
+// Returns false when an index overflows 32 bits.
+bool build_cached_tables(const rlpt_graph* g, int layout, std::vector<uint32_t>* pstart, std::vector<uint32_t>* pidx,
+                         std::vector<double>* pJ, std::vector<uint32_t>* estart, std::vector<uint16_t>* g16,
+                         std::vector<uint32_t>* g32, std::vector<double>* gJ, std::vector<uint16_t>* c0tab) {
+    const int N = g->N, ns = (N + kSlice - 1) / kSlice;
+    const int64_t c = g->n_terms();
+    std::vector<uint32_t> cnt, c0;
+    pair_counts(g, &cnt, &c0);
+    const uint64_t pbase = pidx->size();
+    const uint64_t gbase = gJ->size();
+    const size_t E = ell_entries(g, cnt);
+    if (pbase + 12 * (uint64_t)c > 0xffffffffull || gbase + E > 0xffffffffull) return false;
+    // pair lists
+    std::vector<uint32_t> cur((size_t)N * N);
+    const size_t s0 = pstart->size();
+    pstart->resize(s0 + (size_t)N * N + 1);
+    uint32_t run = (uint32_t)pbase;
+    for (size_t p = 0; p < (size_t)N * N; ++p) {
+        (*pstart)[s0 + p] = run;
+        cur[p] = run;
+        run += cnt[p];
+    }
+    (*pstart)[s0 + (size_t)N * N] = run;
+    pidx->resize(run);
+    pJ->resize(run);
+    for (int64_t e = 0; e < c; ++e) {
+        const int16_t* q = &g->quads[4 * e];
+        for (int t = 0; t < 4; ++t) {
+            int x[3];
+            term_triple(q, t, x);
+            const uint32_t v = (uint32_t)x[0] | (uint32_t)x[1] << 10 | (uint32_t)x[2] << 20;
+            for (int r = 0; r < 3; ++r) {
+                const uint32_t at = cur[(size_t)x[r] * N + q[t]]++;
+                (*pidx)[at] = v | (uint32_t)r << 30;
+                (*pJ)[at] = g->J[e];
+            }
+        }
+    }
+    // gather blocks: entry offsets per (j, s)
+    const size_t e0 = estart->size();
+    estart->resize(e0 + (size_t)N * ns + 1);
+    std::vector<uint64_t> blk((size_t)N * ns);
+    uint64_t off = gbase;
+    for (int j = 0; j < N; ++j)
+        for (int s = 0; s < ns; ++s) {
+            const int w = std::min(kSlice, N - kSlice * s);
+            uint32_t L = 0;
+            for (int i = 0; i < w; ++i) L = std::max(L, cnt[(size_t)j * N + kSlice * s + i]);
+            blk[(size_t)j * ns + s] = off;
+            (*estart)[e0 + (size_t)j * ns + s] = (uint32_t)off;
+            off += (uint64_t)((L + 3) / 4) * 4 * w;
+        }
+    (*estart)[e0 + (size_t)N * ns] = (uint32_t)off;
+    const bool narrow = layout == kLayoutChunked;
+    if (narrow) g16->resize(off, 0);
+    else g32->resize(off, 0);
+    gJ->resize(off, 0.0);
+    // rank cursors: partner entries first, then the others
+    std::vector<uint32_t> r0((size_t)N * N, 0), r1(c0);
+    for (int64_t e = 0; e < c; ++e) {
+        const int16_t* q = &g->quads[4 * e];
+        for (int t = 0; t < 4; ++t) {
+            const int l = q[t];
+            int x[3];
+            term_triple(q, t, x);
+            for (int r = 0; r < 3; ++r) {
+                const int j = x[r];
+                // r = 0: j is l's partner, change conj(d) a_y a_z; else conj(a_x) d a_(other side)
+                const int p1 = r == 0 ? x[1] : x[0];
+                const int p2 = r == 0 ? x[2] : (r == 1 ? x[2] : x[1]);
+                const size_t jl = (size_t)j * N + l;
+                const uint32_t rank = r == 0 ? r0[jl]++ : r1[jl]++;
+                const int s = l / kSlice, lane = l % kSlice, w = std::min(kSlice, N - kSlice * s);
+                const uint64_t at = blk[(size_t)j * ns + s] + ((uint64_t)(rank / 4) * w + lane) * 4 + rank % 4;
+                if (narrow) (*g16)[at] = (uint16_t)(p1 | p2 << 8);
+                else (*g32)[at] = (uint32_t)p1 | (uint32_t)p2 << 10;
+                (*gJ)[at] = g->J[e];
+            }
+        }
+    }
+    const size_t cb = c0tab->size();
+    c0tab->resize(cb + (size_t)N * N);
+    for (size_t p = 0; p < (size_t)N * N; ++p) (*c0tab)[cb + p] = (uint16_t)c0[p];
     return true;
 }
 
@@ -173,11 +263,19 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     const size_t T = cfg.n_temps, reps = cfg.n_reps, Rc = T * reps, copies = Rc * S;
     const bool cached = cfg.field_mode == RLPT_FIELDS_CACHED;
     size_t modes = 0, entries = 0, chunks = 0, quads = 0, amp = 0, pairs = 0, pair_entries = 0;
+    size_t ell_starts = 0, ell_total = 0, c0n = 0;
     int max_N = 0;
     for (int i = 0; i < S; ++i) {
         modes += g[i]->N + 1;
         pairs += (size_t)g[i]->N * g[i]->N + 1;
         pair_entries += 12 * (size_t)g[i]->n_terms();
+        if (cached) {
+            std::vector<uint32_t> cnt;
+            pair_counts(g[i], &cnt, nullptr);
+            ell_total += ell_entries(g[i], cnt);
+            ell_starts += (size_t)g[i]->N * ((g[i]->N + kSlice - 1) / kSlice) + 1;
+            c0n += (size_t)g[i]->N * g[i]->N;
+        }
         if (layout == kLayoutPacked) entries += g[i]->mode_start.back();
         else chunks += g[i]->cx.size();
         quads += g[i]->n_terms();
@@ -199,6 +297,11 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     r.pidx = L.take(cached ? pair_entries * 4 : 0);
     r.pJ = L.take(cached ? pair_entries * rb : 0);
     r.fields = L.take(cached ? amp * 2 * rb : 0);
+    r.ell_start = L.take(ell_starts * 4);
+    r.gidx16 = L.take(layout == kLayoutChunked ? ell_total * 2 : 0);
+    r.gidx32 = L.take(layout == kLayoutChunked ? 0 : ell_total * 4);
+    r.gJ = L.take(ell_total * rb);
+    r.c0 = L.take(c0n * 2);
     r.quads = L.take(quads * 8);
     r.Jq = L.take(quads * 8);
     r.amp = L.take(amp * 2 * rb);
@@ -243,6 +346,11 @@ void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
     P.pidx = reinterpret_cast<const uint32_t*>(b + r.pidx);
     P.pJ = reinterpret_cast<const R*>(b + r.pJ);
     P.fields = reinterpret_cast<R*>(b + r.fields);
+    P.ell_start = reinterpret_cast<const uint32_t*>(b + r.ell_start);
+    P.gidx16 = reinterpret_cast<const uint16_t*>(b + r.gidx16);
+    P.gidx32 = reinterpret_cast<const uint32_t*>(b + r.gidx32);
+    P.gJ = reinterpret_cast<const R*>(b + r.gJ);
+    P.c0 = reinterpret_cast<const uint16_t*>(b + r.c0);
     P.quads = reinterpret_cast<const ushort4*>(b + r.quads);
     P.Jq = reinterpret_cast<const double*>(b + r.Jq);
     P.amp = reinterpret_cast<R*>(b + r.amp);
@@ -342,7 +450,10 @@ int sync_and_flags(rlpt_ctx* c) {
 }
 
 // work items: samples ordered by decreasing N (longest work first), copies in
-// chunks of the tile's copies per workgroup; sets the launch description
+// chunks of the tile's copies per workgroup; sets the launch description.
+// Cached-field contexts name temperature slots instead, hottest first (the
+// copies with the most accepted moves, hence field updates, start first); the
+// kernel finds each slot's copy in copy_at.
 int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
     if (block < 64 || block > 1024 || (block & (block - 1))) return fail(RLPT_E_ARG, "bad workgroup size");
     std::vector<ItemDev> items;
@@ -363,6 +474,10 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
             max_cpi = std::max(max_cpi, it.n_copies);
         }
     }
+    if (c->sh.cached)  // hottest slots first across samples (stable: sample order within a rank)
+        std::stable_sort(items.begin(), items.end(), [&](const ItemDev& x, const ItemDev& y) {
+            return x.first_copy - x.sample * c->Rc < y.first_copy - y.sample * c->Rc;
+        });
     const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached);
     if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
     c->items = items;
@@ -372,6 +487,7 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
     c->launch.max_copies_per_item = max_cpi;
     c->launch.max_N = c->max_N;
     c->launch.lds_bytes = lds;
+    c->sh.by_slot = c->sh.cached;
     return RLPT_OK;
 }
 
@@ -490,9 +606,9 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     std::vector<uint8_t> cx;
     std::vector<uint16_t> cyz;
     std::vector<ushort4> quads;
-    std::vector<uint32_t> pstart, pidx;
-    std::vector<float> pJ32;
-    std::vector<double> pJ64;
+    std::vector<uint32_t> pstart, pidx, estart, g32;
+    std::vector<uint16_t> g16, c0tab;
+    std::vector<double> pJ64, gJ64;
     int64_t amp_base = 0, quad_base = 0;
     for (int s = 0; s < c->S; ++s) {
         const rlpt_graph* g = graphs[s];
@@ -530,10 +646,11 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         Jq.insert(Jq.end(), g->J.begin(), g->J.end());
         if (c->sh.cached) {
             sd.pair_base = (int64_t)pstart.size();
-            if (!build_pair_lists(g, &pstart, &pidx, cfg->precision == RLPT_FP64 ? &pJ64 : nullptr,
-                                  cfg->precision == RLPT_FP64 ? nullptr : &pJ32)) {
+            sd.ell_base = (int64_t)estart.size();
+            sd.c0_base = (int64_t)c0tab.size();
+            if (!build_cached_tables(g, layout, &pstart, &pidx, &pJ64, &estart, &g16, &g32, &gJ64, &c0tab)) {
                 delete c;
-                return fail(RLPT_E_ARG, "cached-field pair lists exceed 2^32 entries");
+                return fail(RLPT_E_ARG, "cached-field tables exceed 2^32 entries");
             }
         }
         amp_base += (int64_t)c->Rc * g->N;
@@ -552,9 +669,10 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         // the tune registry holds streaming-sweep timings; cached contexts use the built-in tile
         if (cfg->block_threads > 0 || cfg->copies_per_block > 0 || c->sh.cached ||
             !tune_choose(counts, cfg->precision, cfg->shared_pairs, &block, &copies)) {
-            block = cfg->block_threads > 0 ? cfg->block_threads : default_tile(c->max_N).block;
+            auto tile = [&](int n) { return c->sh.cached ? default_tile_cached(n) : default_tile(n); };
+            block = cfg->block_threads > 0 ? cfg->block_threads : tile(c->max_N).block;
             for (const auto& nc : counts)
-                copies[nc.first] = cfg->copies_per_block > 0 ? cfg->copies_per_block : default_tile(nc.first).copies;
+                copies[nc.first] = cfg->copies_per_block > 0 ? cfg->copies_per_block : tile(nc.first).copies;
         }
         rc = build_items(c, block, copies);
         if (rc) {
@@ -598,8 +716,21 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     up(r.Jq, Jq);
     up(r.pair_start, pstart);
     up(r.pidx, pidx);
-    if (cfg->precision == RLPT_FP64) up(r.pJ, pJ64);
-    else up(r.pJ, pJ32);
+    up(r.ell_start, estart);
+    up(r.gidx16, g16);
+    up(r.gidx32, g32);
+    up(r.c0, c0tab);
+    if (cfg->precision == RLPT_FP64) {
+        up(r.pJ, pJ64);
+        up(r.gJ, gJ64);
+    } else {
+        std::vector<float> f(pJ64.begin(), pJ64.end());
+        up(r.pJ, f);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // f is reused below
+        f.assign(gJ64.begin(), gJ64.end());
+        up(r.gJ, f);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
     if (cfg->precision == RLPT_FP64) up(r.beta, b64);
     else up(r.beta, b32);
     up(r.beta64, b64);

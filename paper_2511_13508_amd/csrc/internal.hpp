@@ -56,6 +56,8 @@ struct SampleDev {
     int64_t quad_base;     // offset into the by-term arrays
     int64_t n_quads;
     int64_t pair_base;     // offset of this sample's pair_start block (N*N + 1 values)
+    int64_t ell_base;      // offset of this sample's ell_start block (N * slices + 1 values)
+    int64_t c0_base;       // offset of this sample's c0 block (N*N values)
 };
 
 // a unit of work of the sweep kernel: n_copies consecutive copies of one sample
@@ -90,6 +92,15 @@ struct DevPtrs {
     const uint32_t* pair_start;  // absolute entry index per ordered pair, [S][N*N + 1]
     const uint32_t* pidx;
     const R* pJ;
+    // cached-field gather on acceptance: for source mode j and a slice of 64
+    // target modes, entries in sliced-ELL order [rank/4][target lane][rank%4];
+    // entry = the two other members (p1, p2) of a term holding j and the target,
+    // c0 = how many leading ranks of (j -> l) have j as l's partner
+    const uint32_t* ell_start;  // absolute entry index per (sample, source, slice), + sentinel
+    const uint16_t* gidx16;     // p1 | p2 << 8 (chunked layout, N <= 256)
+    const uint32_t* gidx32;     // p1 | p2 << 10 (packed layout)
+    const R* gJ;
+    const uint16_t* c0;         // [S][N*N]
     R* fields;                // cached local fields, interleaved complex [copy][N]
     const ushort4* quads;     // by term (p, s, m, n)
     const double* Jq;         // by term, FP64
@@ -125,6 +136,7 @@ struct ShapeInfo {
     int32_t shared_pairs;
     int32_t layout;             // ListLayout
     int32_t cached;             // 1: cached local fields (pair lists + updates on acceptance)
+    int32_t by_slot;            // items name temperature slots (hottest first), copies found via copy_at
     int32_t pad2;
     uint64_t run_seed;
     double renorm_tol;

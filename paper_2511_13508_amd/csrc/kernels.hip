@@ -338,98 +338,109 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
 
 // ---------------------------------------------------------------- cached local fields
 // With every copy's fields kept up to date, the energy change of a two-mode
-// move needs only F_j, F_k and, for the one-snapshot rule, the terms holding
-// both j and k (the pair list j -> k); the lists of j and k are streamed only
-// when the move is accepted, to update the fields of every mode sharing a term
-// with j or k.  Same Markov chain as the streaming sweep.
+// move needs F_j, F_k and, for the one-snapshot rule, the change of F_k from
+// the new a_j: a short list of the terms holding both j and k.  Only an
+// accepted move touches the other fields: every mode l sharing a term with j
+// or k gains the change of its field, gathered per target from the sliced-ELL
+// block of j (with a_k old) and of k (with a_j new), one lane per target, so
+// no two lanes ever add to the same field.  Same chain, same draws as the
+// streaming sweep.
 
-// sum over the pair list of J * conj(u) v w with j's slot holding delta_j:
-// the change of F_k when a_j moves by delta_j
+// J conj(u) v w of one pair-list entry with j's slot holding d
 template <typename R>
-__device__ inline void pair_correction(const uint32_t* __restrict__ pidx, const R* __restrict__ pJ, uint32_t beg,
-                                       uint32_t end, const R2<R>* __restrict__ a, R2<R> dj, int lane, R& cr,
-                                       R& ci) {
-    for (uint32_t e = beg + lane; e < end; e += 64) {
-        const uint32_t v = pidx[e];
-        const R J = pJ[e];
-        const uint32_t role = v >> 30;
-        const R2<R> u = role == 0 ? dj : a[v & 1023u];
-        const R2<R> w1 = role == 1 ? dj : a[(v >> 10) & 1023u];
-        const R2<R> w2 = role == 2 ? dj : a[(v >> 20) & 1023u];
-        const R pr = u.x * w1.x + u.y * w1.y, pi = u.x * w1.y - u.y * w1.x;
-        cr += J * (pr * w2.x - pi * w2.y);
-        ci += J * (pr * w2.y + pi * w2.x);
-    }
+__device__ inline void pair_term(uint32_t v, R J, const R2<R>* __restrict__ a, R2<R> d, R& cr, R& ci) {
+    const uint32_t role = v >> 30;
+    const R2<R> u = role == 0 ? d : a[v & 1023u];
+    const R2<R> w1 = role == 1 ? d : a[(v >> 10) & 1023u];
+    const R2<R> w2 = role == 2 ? d : a[(v >> 20) & 1023u];
+    const R pr = u.x * w1.x + u.y * w1.y, pi = u.x * w1.y - u.y * w1.x;
+    cr += J * (pr * w2.x - pi * w2.y);
+    ci += J * (pr * w2.y + pi * w2.x);
 }
 
-// field changes of the members x, y, z of one term of the moved mode's list
-// (x = its partner, (y, z) the other side) when it moves by d:
-// dF_x = J conj(d) a_y a_z, dF_y = J conj(a_z) d a_x, dF_z = J conj(a_y) d a_x
-template <typename R>
-__device__ inline void scatter_term(uint32_t e, R J, R2<R> d, const R2<R>* __restrict__ a, R* F) {
-    const uint32_t x = e & 1023u, y = (e >> 10) & 1023u, z = e >> 20;
-    const R2<R> ax = a[x], ay = a[y], az = a[z];
-    const R yr = ay.x * az.x - ay.y * az.y, yi = ay.x * az.y + ay.y * az.x;
-    const R tr = d.x * ax.x - d.y * ax.y, ti = d.x * ax.y + d.y * ax.x;
-    atomicAdd(&F[2 * x], J * (d.x * yr + d.y * yi));
-    atomicAdd(&F[2 * x + 1], J * (d.x * yi - d.y * yr));
-    atomicAdd(&F[2 * y], J * (az.x * tr + az.y * ti));
-    atomicAdd(&F[2 * y + 1], J * (az.x * ti - az.y * tr));
-    atomicAdd(&F[2 * z], J * (ay.x * tr + ay.y * ti));
-    atomicAdd(&F[2 * z + 1], J * (ay.x * ti - ay.y * tr));
-}
+constexpr int kPairPrefetch = 8;  // pair-list entries per lane loaded one step ahead
 
+// groups of 4 gather entries loaded before any is used (fewer with the wider
+// 32-bit indices of the packed layout, to stay within three waves per SIMD)
+template <int LAYOUT>
+constexpr int kGatherBatch = LAYOUT == kLayoutChunked ? 8 : 4;
+
+template <int LAYOUT>
+struct GatherIdx;
+template <>
+struct GatherIdx<kLayoutChunked> {
+    using T = uint2;  // 4 x (p1 | p2 << 8)
+    __device__ static uint32_t p1(const T& v, int i) { return (i < 2 ? v.x : v.y) >> (16 * (i & 1)) & 0xffu; }
+    __device__ static uint32_t p2(const T& v, int i) { return (i < 2 ? v.x : v.y) >> (16 * (i & 1) + 8) & 0xffu; }
+};
+template <>
+struct GatherIdx<kLayoutPacked> {
+    using T = uint4;  // 4 x (p1 | p2 << 10)
+    __device__ static uint32_t word(const T& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+    __device__ static uint32_t p1(const T& v, int i) { return word(v, i) & 1023u; }
+    __device__ static uint32_t p2(const T& v, int i) { return word(v, i) >> 10; }
+};
+
+// change of the field of target l = 64 * slice + lane from source mode src
+// moving by d: over the ranks of (src -> l), J conj(d) a_p1 a_p2 when src is
+// l's partner (the first c0 ranks), else J conj(a_p1) d a_p2.  With
+// P = conj(d) a_p1 the second form is conj(P) a_p2, so each entry costs one
+// sign flip instead of a choice of operands.  Loads go out kGatherBatch
+// groups at a time, ahead of every use.
 template <typename R, int LAYOUT>
-__device__ inline void scatter_mode(const DevPtrs<R>& P, const SampleDev& sd, int l, R2<R> d,
-                                    const R2<R>* __restrict__ a, R* F, int t, int nt) {
-    if constexpr (LAYOUT == kLayoutChunked) {
-        using JT = typename J4<R>::T;
-        const uint32_t* cs = P.chunk_start + sd.mode_base;
-        const JT* Jv = reinterpret_cast<const JT*>(P.cJ);
-        for (uint32_t c = cs[l] + t; c < cs[l + 1]; c += nt) {
-            const uint32_t x = P.cx[c];
-            const uint2 yz = P.cyz[c];
-            const JT j4 = Jv[c];
-            const R2<R> ax = a[x];
-            const R tr = d.x * ax.x - d.y * ax.y, ti = d.x * ax.y + d.y * ax.x;
-            R gr = 0, gi = 0;
-            const uint32_t v4[4] = {yz.x & 0xffffu, yz.x >> 16, yz.y & 0xffffu, yz.y >> 16};
-            const R jj[4] = {j4.x, j4.y, j4.z, j4.w};
+__device__ inline void gather_slice(const DevPtrs<R>& P, const SampleDev& sd, int N, int src, R2<R> d, int slice,
+                                    int part, int parts, int lane, const R2<R>* __restrict__ a, R& fr, R& fi) {
+    const int ns = (N + 63) >> 6;
+    const int w = min(64, N - 64 * slice);
+    if (lane >= w) return;
+    const uint32_t* es = P.ell_start + sd.ell_base + (int64_t)src * ns + slice;
+    const uint32_t nall = (es[1] - es[0]) / (4u * (uint32_t)w);
+    // this part's share of the groups: [part, part + 1) * nall / parts
+    const uint32_t qb = (uint32_t)part * nall / (uint32_t)parts, qe = (uint32_t)(part + 1) * nall / (uint32_t)parts;
+    const uint32_t b0 = es[0] + 4u * (uint32_t)w * qb, nq = qe - qb;
+    const int l = 64 * slice + lane;
+    const uint32_t c0 = P.c0[sd.c0_base + (int64_t)src * N + l];
+    using JT = typename J4<R>::T;
+    using GI = GatherIdx<LAYOUT>;
+    using IT = typename GI::T;
+    const IT* ip = reinterpret_cast<const IT*>(LAYOUT == kLayoutChunked ? (const void*)P.gidx16 : (const void*)P.gidx32);
+    const JT* jp = reinterpret_cast<const JT*>(P.gJ);
+    const uint32_t g0 = b0 / 4u + (uint32_t)lane;  // this lane's group q sits at g0 + q * w
+    if (nq == 0) return;
+    for (uint32_t q0 = 0; q0 < nq; q0 += kGatherBatch<LAYOUT>) {
+        IT iv[kGatherBatch<LAYOUT>];
+        JT jv[kGatherBatch<LAYOUT>];
+#pragma unroll
+        for (int u = 0; u < kGatherBatch<LAYOUT>; ++u) {
+            const uint32_t q = q0 + u < nq ? q0 + u : nq - 1;
+            iv[u] = ip[g0 + q * (uint32_t)w];
+            jv[u] = jp[g0 + q * (uint32_t)w];
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherBatch<LAYOUT>; ++u) {
+            // past the end: the clamped group again, weighted 0 (no branch, so the
+            // loads above stay ahead of every use)
+            const R m = q0 + u < nq ? (R)1 : (R)0;
+            const R jj[4] = {m * jv[u].x, m * jv[u].y, m * jv[u].z, m * jv[u].w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (jj[i] == (R)0) continue;  // padding
-                const uint32_t y = v4[i] & 0xffu, z = v4[i] >> 8;
-                const R2<R> ay = a[y], az = a[z];
-                gr += jj[i] * (ay.x * az.x - ay.y * az.y);
-                gi += jj[i] * (ay.x * az.y + ay.y * az.x);
-                atomicAdd(&F[2 * y], jj[i] * (az.x * tr + az.y * ti));
-                atomicAdd(&F[2 * y + 1], jj[i] * (az.x * ti - az.y * tr));
-                atomicAdd(&F[2 * z], jj[i] * (ay.x * tr + ay.y * ti));
-                atomicAdd(&F[2 * z + 1], jj[i] * (ay.x * ti - ay.y * tr));
+                const R2<R> x1 = a[GI::p1(iv[u], i)], x2 = a[GI::p2(iv[u], i)];
+                const R pr = d.x * x1.x + d.y * x1.y;
+                const R pim = d.x * x1.y - d.y * x1.x;
+                const R pi = 4 * (qb + q0 + u) + (uint32_t)i < c0 ? pim : -pim;
+                fr += jj[i] * (pr * x2.x - pi * x2.y);
+                fi += jj[i] * (pr * x2.y + pi * x2.x);
             }
-            atomicAdd(&F[2 * x], d.x * gr + d.y * gi);
-            atomicAdd(&F[2 * x + 1], d.x * gi - d.y * gr);
-        }
-    } else {
-        using JT = typename J4<R>::T;
-        const uint32_t* ms = P.mode_start + sd.mode_base;
-        const uint4* I4 = reinterpret_cast<const uint4*>(P.idx + ms[l]);
-        const JT* Jv = reinterpret_cast<const JT*>(P.J + ms[l]);
-        const int n4 = (int)((ms[l + 1] - ms[l]) >> 2);
-        for (int e = t; e < n4; e += nt) {
-            const uint4 i4 = I4[e];
-            const JT j4 = Jv[e];
-            if (j4.x != (R)0) scatter_term<R>(i4.x, j4.x, d, a, F);
-            if (j4.y != (R)0) scatter_term<R>(i4.y, j4.y, d, a, F);
-            if (j4.z != (R)0) scatter_term<R>(i4.z, j4.z, d, a, F);
-            if (j4.w != (R)0) scatter_term<R>(i4.w, j4.w, d, a, F);
         }
     }
 }
 
+// LDS bytes of one copy group of the cached sweep: the streaming group plus
+// the fields, the per-step pair-list ranges, d_j, d_k and the decision flag
 template <typename R>
 __host__ __device__ inline size_t group_bytes_cached(int max_N, int waves_per_block) {
-    return group_bytes<R>(max_N, waves_per_block) + (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) * 2 + 16;
+    const size_t extra = (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) + (size_t)(max_N / 2 + 1) * sizeof(uint2) + 16;
+    return (group_bytes<R>(max_N, waves_per_block) + extra + 15) & ~(size_t)15;
 }
 
 template <typename R, int BLOCK, int LAYOUT>
@@ -447,16 +458,29 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
     const int gt = threadIdx.x - g * wpc * 64;
     const int nt = wpc * 64;
     const int gsel = active ? g : 0;
+    const int ns = (N + 63) >> 6;
+    // field update of an accepted move: `parts` waves share each slice when
+    // the group has waves to spare
+    const int parts = max(1, wpc / ns);
 
     unsigned char* base = smem + (size_t)gsel * group_bytes_cached<R>(max_N, kWaves);
     R2<R>* a = reinterpret_cast<R2<R>*>(base);
     StepDraw<R>* tab = reinterpret_cast<StepDraw<R>*>(base + (size_t)max_N * 2 * sizeof(R));
     unsigned char* after = base + group_bytes<R>(max_N, kWaves);
     R* F = reinterpret_cast<R*>(after);
-    R2<R>* snap = reinterpret_cast<R2<R>*>(after + (size_t)max_N * 2 * sizeof(R));  // [0] = d_j, [1] = d_k
-    int* flag = reinterpret_cast<int*>(after + (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) * 2);
+    after += (size_t)max_N * 2 * sizeof(R);
+    R2<R>* snap = reinterpret_cast<R2<R>*>(after);  // [0] = d_j, [1] = d_k
+    after += 4 * sizeof(R);
+    uint2* pr = reinterpret_cast<uint2*>(after);  // pair-list range of each step
+    after += (size_t)(max_N / 2 + 1) * sizeof(uint2);
+    int* flag = reinterpret_cast<int*>(after);  // decisions of even and odd steps
 
-    const int c = it.first_copy + gsel;
+    int c = it.first_copy + gsel;
+    if (sh.by_slot) {  // slot order within the sample: temperature descending, then ladder
+        const int idx = c - it.sample * sh.copies_per_sample;
+        const int t = sh.n_temps - 1 - idx / sh.n_reps, r = idx % sh.n_reps;
+        c = P.copy_at[((size_t)it.sample * sh.n_reps + r) * sh.n_temps + t];
+    }
     const int64_t local = c - (int64_t)it.sample * sh.copies_per_sample;
     R2<R>* amp_g = reinterpret_cast<R2<R>*>(P.amp) + sd.amp_base + local * N;
     R* fld_g = P.fields + 2 * (sd.amp_base + local * N);
@@ -474,7 +498,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
     const int64_t sweep0 = P.counters->sweeps_done;
     const uint32_t* ps = P.pair_start + sd.pair_base;
 
-    R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
+    // wave 0 keeps the next step's pair-list entries in registers
+    uint32_t pv[kPairPrefetch];
+    R pj[kPairPrefetch];
+    auto prefetch = [&](int s) {
+        const uint2 r = pr[s];
+#pragma unroll
+        for (int i = 0; i < kPairPrefetch; ++i) {
+            const uint32_t e = r.x + (uint32_t)(lane + 64 * i);
+            const bool in = e < r.y;
+            pv[i] = in ? P.pidx[e] : 0u;
+            pj[i] = in ? P.pJ[e] : (R)0;
+        }
+    };
+    R2<R> ajo = mk2<R>(0, 0), akn = mk2<R>(0, 0);
     auto prepare = [&](int s) {  // snapshot of step s (one lane)
         const StepDraw<R> d = tab[s];
         const int j2 = d.jk & 0xffff, k2 = d.jk >> 16;
@@ -482,26 +519,42 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
         const R2<R> ako2 = a[k2];
         const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
         const R K = sqrt(sqrt(uj * uj + uk * uk));
-        ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
+        const R2<R> ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
         akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
         a[j2] = ajn;
         snap[0] = mk2<R>(ajn.x - ajo.x, ajn.y - ajo.y);
         snap[1] = mk2<R>(akn.x - ako2.x, akn.y - ako2.y);
     };
+    // One barrier per rejected step: wave 0 decides, prepares the next
+    // snapshot and decides again without waiting; the other waves only learn
+    // each decision (flags alternate between two slots, so a fast wave 0
+    // never overwrites one still being read).  An accepted step adds the
+    // field update and one more barrier; with several copies per workgroup
+    // that barrier is taken every step, keeping barriers block-uniform.
+    const bool lone = it.n_copies == 1;
     for (int sw = 0; sw < n_sweeps; ++sw) {
         __syncthreads();
         if (active)
-            for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N);
+            for (int s = gt; s < steps; s += nt) {
+                const StepDraw<R> d = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N);
+                tab[s] = d;
+                const int64_t pk = (int64_t)(d.jk & 0xffff) * N + (d.jk >> 16);
+                pr[s] = make_uint2(ps[pk], ps[pk + 1]);
+            }
         __syncthreads();
         if (active && gt == 0) prepare(0);
+        __builtin_amdgcn_wave_barrier();
+        if (active && gw == 0) prefetch(0);
         for (int s = 0; s < steps; ++s) {
-            __syncthreads();
             const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
             if (active && gw == 0) {
                 const R2<R> dj = snap[0];
                 R cr = 0, ci = 0;
-                const int64_t pk = (int64_t)j * N + k;
-                pair_correction<R>(P.pidx, P.pJ, ps[pk], ps[pk + 1], a, dj, lane, cr, ci);
+#pragma unroll
+                for (int i = 0; i < kPairPrefetch; ++i) pair_term<R>(pv[i], pj[i], a, dj, cr, ci);
+                const uint2 r = pr[s];
+                for (uint32_t e = r.x + 64 * kPairPrefetch + lane; e < r.y; e += 64) pair_term<R>(P.pidx[e], P.pJ[e], a, dj, cr, ci);
+                if (s + 1 < steps) prefetch(s + 1);
                 cr = wave_sum(cr);
                 ci = wave_sum(ci);
                 if (lane == 0) {
@@ -509,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
                     const R Fkr = F[2 * k] + cr, Fki = F[2 * k + 1] + ci;
                     const R dE = (R)-2 * (dj.x * F[2 * j] + dj.y * F[2 * j + 1]) - (R)2 * (dk.x * Fkr + dk.y * Fki);
                     const bool accept = (dE <= (R)0) || (tab[s].u < exp(-beta * dE));
-                    *flag = accept ? 1 : 0;
+                    flag[s & 1] = accept ? 1 : 0;
                     if (accept) {
                         E += dE;
                         ++n_acc;
@@ -519,15 +572,32 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
                 }
             }
             __syncthreads();
-            if (active && *flag) {  // a_j new, a_k old in LDS: update the fields of every mode sharing a term
-                scatter_mode<R, LAYOUT>(P, sd, j, snap[0], a, F, gt, nt);
-                scatter_mode<R, LAYOUT>(P, sd, k, snap[1], a, F, gt, nt);
+            const bool acc_s = active && flag[s & 1];
+            if (acc_s) {  // a_j new, a_k old in LDS: field changes of every target
+                const R2<R> dj = snap[0], dk = snap[1];
+                const int part = gw / ns;
+                for (int sl = gw % ns; sl < ns && part < parts; sl += parts == 1 ? wpc : ns) {
+                    R fr = 0, fi = 0;
+                    gather_slice<R, LAYOUT>(P, sd, N, j, dj, sl, part, parts, lane, a, fr, fi);
+                    gather_slice<R, LAYOUT>(P, sd, N, k, dk, sl, part, parts, lane, a, fr, fi);
+                    const int l = 64 * sl + lane;
+                    if (l < N) {
+                        if (parts == 1) {
+                            F[2 * l] += fr;
+                            F[2 * l + 1] += fi;
+                        } else {  // `parts` lanes add to each field: atomics, distinct targets per wave
+                            atomicAdd(&F[2 * l], fr);
+                            atomicAdd(&F[2 * l + 1], fi);
+                        }
+                    }
+                }
             }
-            __syncthreads();
+            if (!lone || acc_s) __syncthreads();
             if (active && gt == 0) {
-                if (*flag) a[k] = akn;
+                if (acc_s) a[k] = akn;
                 if (s + 1 < steps) prepare(s + 1);
             }
+            __builtin_amdgcn_wave_barrier();  // wave 0 reads lane 0's snapshot next: keep the LDS order
         }
     }
     __syncthreads();
