@@ -62,8 +62,8 @@ def traffic_for_current_kernel(launch_bytes_alg: float):
 PROFILE_CMDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kt -o kt -- python bench.py --steps 20 --warmup 5 "
           "--tau-sweeps 0 --no-cpu-baseline",
-    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex k_sweep -f csv -d gpurun_out/pmc_{C} -o pmc -- python bench.py "
-           "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline",
+    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d gpurun_out/pmc_{C} -o pmc -- python bench.py "
+           "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
     "cal": "rocprofv3 --pmc {C} -f csv -d gpurun_out/cal_{C} -o cal -- python bench.py --copy-calibration",
 }
 
@@ -90,8 +90,8 @@ def summarize_profiles(d):
         name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
         lines.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
                      f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
-    sweep = [r for r in stats if "k_sweep" in r["Name"]][0]
-    is_sweep = lambda n: "k_sweep" in n  # noqa: E731
+    sweep = [r for r in stats if "k_sweep<" in r["Name"]][0]
+    is_sweep = lambda n: "k_sweep<" in n  # noqa: E731
     is_copy = lambda n: "copyBuffer" in n  # noqa: E731
     fetch_kib, nf = mean_counter(os.path.join(d, "pmc_FETCH_SIZE", "pmc_counter_collection.csv"), is_sweep)
     write_kib, nw = mean_counter(os.path.join(d, "pmc_WRITE_SIZE", "pmc_counter_collection.csv"), is_sweep)
@@ -194,6 +194,49 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
+def cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out):
+    """The headline workload with cached local fields (field_mode = FIELDS_CACHED):
+    the same chain as the streaming run; reports its rate, the speedup, the
+    acceptance and an algorithmic byte count per launch."""
+    N, S, T, reps = args.n_modes, args.samples, args.temps, args.reps
+    ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, field_mode=rlpt.FIELDS_CACHED, **common)
+    ctx.init(1)
+    log("cached fields: warmup")
+    ctx.sweep(args.warmup)
+    ctx.check()
+    torch.cuda.synchronize()
+    acc0 = ctx.observables()["acc"].sum()
+    ctx.sweep_timing(True)
+    t0 = time.perf_counter()
+    ctx.sweep(args.steps)
+    torch.cuda.synchronize()
+    el4 = time.perf_counter() - t0
+    ctx.check()
+    kms4, launches4 = ctx.sweep_time()
+    ctx.sweep_timing(False)
+    accepted = ctx.observables()["acc"].sum() - acc0
+    steps_total = n_copies * (N // 2) * args.steps
+    idx_b = 2 if chunked else 4
+    pair_b = sum(inf["pair_entries"] / (N * (N - 1)) * 8.0 for inf in infos) / S  # per step
+    gather_b = sum(inf["gather_entries"] for inf in infos) / (S * N) * (idx_b + 4)
+    bytes4 = (steps_total * pair_b + accepted * 2 * gather_b) / launches4
+    tile4 = ctx.tile()
+    ctx.close()
+    out["cached_fields"] = {
+        "mode_updates_per_s": N * n_copies * args.steps / el4,
+        "speedup_vs_streaming": el / el4,
+        "ms_per_launch": kms4 / launches4,
+        "acceptance": accepted / steps_total,
+        "tile": {"block_threads": int(tile4[0]), "copies_per_block": int(tile4[1][0])},
+        "algorithmic_bytes_per_launch": bytes4,
+        "achieved_GBs": bytes4 / (kms4 / launches4 * 1e-3) / 1e9,
+        "note": "bytes: per step the (j->k) pair list (8 B/entry), per accepted step the padded gather "
+                "blocks of j and k; the launch is bound by the hottest copies' accepted steps, not by HBM",
+    }
+    log(f"cached fields: {out['cached_fields']['mode_updates_per_s']:.4g} mode-updates/s "
+        f"({out['cached_fields']['speedup_vs_streaming']:.2f}x streaming)")
+
+
 def per_N_copies(per_N_count, T, reps):
     return per_N_count * T * reps
 
@@ -219,6 +262,7 @@ def main():
     ap.add_argument("--harvest-rounds", type=int, default=400)
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cached", action="store_true", help="skip the cached-field run")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
     ap.add_argument("--workload", choices=["n256", "batched"], default="n256",
@@ -345,6 +389,11 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "sweeps_per_s": sweeps_per_s,
     }
+    # ---------------------------------------------------------------- cached local fields
+    # same chain, fields kept per copy; per step the pair list of (j -> k), per
+    # accepted step the gather blocks of j and k
+    if not args.no_cached:
+        cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out)
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature)", "estimator": "Sokal window c=6",
                "plain": tau_plain}

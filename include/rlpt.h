@@ -83,6 +83,9 @@ typedef struct rlpt_graph_info {
     int64_t list_bytes;  /* packed layout: bytes of all per-mode lists in an FP32 context (8 B/entry) */
     int64_t chunk_entries;/* chunked layout (N <= 256): entries after padding each partner group to 4 */
     int64_t chunk_bytes; /* chunked layout: bytes of all lists in an FP32 context (25 B per 4 entries) */
+    int64_t pair_entries;   /* cached-field mode: entries of the per-pair lists (12 c; 4 B index + J) */
+    int64_t gather_entries; /* cached-field mode: padded entries of the sliced-ELL field-update blocks
+                               (2 B index in the chunked layout, 4 B in the packed one, + J) */
 } rlpt_graph_info;
 
 /* Build one disorder sample: frequencies; every split of every i<j<k<l into a

@@ -116,50 +116,6 @@ int choose_layout(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int
     return RLPT_OK;
 }
 
-// The three other members of term e as seen from member t: its partner on
-// the same side of the term, then the two modes of the other side.
-inline void term_triple(const int16_t* q, int t, int* x) {
-    static const int kRole[4][3] = {{1, 2, 3}, {0, 2, 3}, {3, 0, 1}, {2, 0, 1}};
-    for (int r = 0; r < 3; ++r) x[r] = q[kRole[t][r]];
-}
-
-// per ordered pair (j -> l): how many terms hold both, and how many of them
-// have j as l's partner
-void pair_counts(const rlpt_graph* g, std::vector<uint32_t>* cnt, std::vector<uint32_t>* c0) {
-    const int N = g->N;
-    cnt->assign((size_t)N * N, 0);
-    if (c0) c0->assign((size_t)N * N, 0);
-    for (int64_t e = 0; e < g->n_terms(); ++e) {
-        const int16_t* q = &g->quads[4 * e];
-        for (int t = 0; t < 4; ++t) {
-            int x[3];
-            term_triple(q, t, x);
-            for (int r = 0; r < 3; ++r) {
-                (*cnt)[(size_t)x[r] * N + q[t]] += 1;
-                if (c0 && r == 0) (*c0)[(size_t)x[r] * N + q[t]] += 1;
-            }
-        }
-    }
-}
-
-constexpr int kSlice = 64;  // target modes per gather slice (one wave)
-
-// padded entries of the sliced-ELL gather block of one sample: per source j
-// and slice s of up to 64 targets, (max rank over the slice, rounded up to 4)
-// x slice width
-size_t ell_entries(const rlpt_graph* g, const std::vector<uint32_t>& cnt) {
-    const int N = g->N, ns = (N + kSlice - 1) / kSlice;
-    size_t total = 0;
-    for (int j = 0; j < N; ++j)
-        for (int s = 0; s < ns; ++s) {
-            const int w = std::min(kSlice, N - kSlice * s);
-            uint32_t L = 0;
-            for (int i = 0; i < w; ++i) L = std::max(L, cnt[(size_t)j * N + kSlice * s + i]);
-            total += (size_t)((L + 3) / 4) * 4 * w;
-        }
-    return total;
-}
-
 // cached-field tables of one sample (appended to the vectors):
 //  * pair lists for the energy change: for the ordered pair (j -> k), every
 //    entry of k's list whose term also holds j, tagged with the slot j takes

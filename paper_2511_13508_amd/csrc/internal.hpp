@@ -42,6 +42,15 @@ enum ListLayout { kLayoutPacked = 1, kLayoutChunked = 2 };
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 
+// cached-field tables (graph.cpp): the other members of a term seen from
+// member t (its partner, then the other side); per ordered pair (j -> l) the
+// number of terms holding both (and, in c0, those with j as l's partner);
+// padded entries of the sliced-ELL gather blocks of one sample
+constexpr int kSlice = 64;
+void term_triple(const int16_t* q, int t, int* x);
+void pair_counts(const rlpt_graph* g, std::vector<uint32_t>* cnt, std::vector<uint32_t>* c0);
+size_t ell_entries(const rlpt_graph* g, const std::vector<uint32_t>& cnt);
+
 void tune_record(const rlpt_tile& t);
 bool tune_choose(const std::map<int, int>& counts, int precision, int shared, int* block,
                  std::map<int, int>* copies);

@@ -59,7 +59,7 @@ class GraphInfo(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("pad", C.c_int32), ("n_terms", C.c_int64), ("deg_min", C.c_int64),
                 ("deg_max", C.c_int64), ("deg_sum", C.c_int64), ("gamma", C.c_double), ("sigma2", C.c_double),
                 ("list_entries", C.c_int64), ("list_bytes", C.c_int64), ("chunk_entries", C.c_int64),
-                ("chunk_bytes", C.c_int64)]
+                ("chunk_bytes", C.c_int64), ("pair_entries", C.c_int64), ("gather_entries", C.c_int64)]
 
 
 class Config(C.Structure):
