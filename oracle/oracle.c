@@ -244,7 +244,7 @@ double or_pair_dE(int32_t N, int64_t n_terms, const int16_t* quads, const double
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int32_t n_modes;           /* N */
-    int32_t pad0;
+    int32_t rho;               /* constraint sum |a|^rho = N, eq. SmoothedCubic: 4 (0 reads as 4) or 2 */
     int64_t n_terms;           /* c */
     const int16_t* quads;      /* [c][4] (p, s, m, n) */
     const double* J;           /* [c] */
@@ -320,26 +320,34 @@ static cplx field_from_lists(const or_pt_params* P, const or_lists* L, const dou
 }
 
 /* Initial configuration: an exact draw from the beta = 0 law of eq. ProbDistr
- * (flat measure on the constraint surface sum_k |a_k|^4 = N of eq.
- * SmoothedCubic after the rescaling of sec. II.B).  With u_k = |a_k|^2 the
- * surface is the sphere sum u^2 = N restricted to u >= 0 and the flat measure
- * on it is uniform, so u = sqrt(N) |g| / ||g|| with g standard normal, and the
- * phases are uniform.  Counter (k, copy id, 0, 0). */
-void or_init_copy(int32_t N, uint64_t run_seed, int64_t copy_id, double* a)
+ * (flat measure on the constraint surface of eq. SmoothedCubic after the
+ * rescaling of sec. II.B), phases uniform.  Counter (k, copy id, 0, 0).
+ *  rho = 4: with u_k = |a_k|^2 the surface sum u^2 = N, u >= 0, is a sphere
+ *    sector and the flat measure on it is uniform: u = sqrt(N) |g| / ||g||
+ *    with g standard normal.
+ *  rho = 2 (the spherical constraint sum |a|^2 = N of sec. II.B): the
+ *    intensities I_k = |a_k|^2 of a uniform point of the complex sphere are
+ *    N times a flat Dirichlet vector: I = N e / sum e with e_k ~ Exp(1). */
+void or_init_copy_rho(int32_t N, uint64_t run_seed, int64_t copy_id, int32_t rho, double* a)
 {
     double* g = (double*)malloc(sizeof(double) * (size_t)N);
     double* ph = (double*)malloc(sizeof(double) * (size_t)N);
-    double norm2 = 0.0;
+    double norm = 0.0;
     for (int32_t k = 0; k < N; ++k) {
         uint64_t w[4];
         draw(run_seed, OR_TAG_INIT, (uint64_t)k, (uint64_t)copy_id, 0, 0, w);
-        g[k] = gauss(w[0], w[1]);
+        if (rho == 2) {
+            g[k] = -log(1.0 - u53(w[0]));
+            norm += g[k];
+        } else {
+            g[k] = gauss(w[0], w[1]);
+            norm += g[k] * g[k];
+        }
         ph[k] = 2.0 * OR_PI * u53(w[2]);
-        norm2 += g[k] * g[k];
     }
     for (int32_t k = 0; k < N; ++k) {
-        double u = sqrt((double)N) * fabs(g[k]) / sqrt(norm2);
-        double A = sqrt(u);
+        double I = rho == 2 ? (double)N * g[k] / norm : sqrt((double)N) * fabs(g[k]) / sqrt(norm);
+        double A = sqrt(I);
         a[2 * k] = A * cos(ph[k]);
         a[2 * k + 1] = A * sin(ph[k]);
     }
@@ -347,12 +355,19 @@ void or_init_copy(int32_t N, uint64_t run_seed, int64_t copy_id, double* a)
     free(ph);
 }
 
+void or_init_copy(int32_t N, uint64_t run_seed, int64_t copy_id, double* a)
+{
+    or_init_copy_rho(N, run_seed, copy_id, 4, a);
+}
+
+static int32_t rho_of(const or_pt_params* P) { return P->rho == 2 ? 2 : 4; }
+
 void or_pt_init(const or_pt_params* P, or_pt_state* S)
 {
     int32_t N = P->n_modes, R = P->n_temps * P->n_reps;
     for (int32_t c = 0; c < R; ++c) {
         int64_t id = (int64_t)P->sample * R + c;
-        or_init_copy(N, P->run_seed, id, &S->a[(size_t)2 * N * c]);
+        or_init_copy_rho(N, P->run_seed, id, rho_of(P), &S->a[(size_t)2 * N * c]);
         S->E[c] = or_energy(P->n_terms, P->quads, P->J, &S->a[(size_t)2 * N * c]);
         S->temp_of[c] = c % P->n_temps;
     }
@@ -361,13 +376,20 @@ void or_pt_init(const or_pt_params* P, or_pt_state* S)
 }
 
 /* One proposal of the two-mode move, sec. III.A "Single Metropolis update":
- * random distinct j, k; K^4 = |a_j|^4 + |a_k|^4; fresh phases in [0, 2 pi);
- * theta in [0, pi/2); A_j' = K sqrt(cos theta), A_k' = K sqrt(sin theta).
- * Returns j, k and the proposed values; the pair comes from the pair stream,
- * everything else from the copy's move stream. */
-static void propose(int32_t N, uint64_t run_seed, int64_t pair_stream, int64_t copy_id, int64_t sweep,
-                    int32_t step, const double* a, int32_t* j_out, int32_t* k_out, double* aj_new,
-                    double* ak_new, double* u_acc)
+ * random distinct j, k; fresh phases in [0, 2 pi); new magnitudes on the
+ * pair's share of the constraint, with the third uniform u:
+ *  rho = 4: K^4 = |a_j|^4 + |a_k|^4, theta = (pi/2) u,
+ *    A_j' = K sqrt(cos theta), A_k' = K sqrt(sin theta) (as printed);
+ *  rho = 2: K^2 = |a_j|^2 + |a_k|^2, A_j' = K cos theta, A_k' = K sin theta
+ *    with sin^2 theta = u uniform, i.e. A_j' = K sqrt(1 - u), A_k' = K sqrt(u).
+ * In both cases the new intensities are uniform on the pair's constraint curve
+ * under the flat measure, so the proposal is the reference law there and the
+ * Metropolis test on the energy alone is exact.  Returns j, k and the proposed
+ * values; the pair comes from the pair stream, everything else from the
+ * copy's move stream. */
+static void propose(int32_t N, int32_t rho, uint64_t run_seed, int64_t pair_stream, int64_t copy_id,
+                    int64_t sweep, int32_t step, const double* a, int32_t* j_out, int32_t* k_out,
+                    double* aj_new, double* ak_new, double* u_acc)
 {
     uint64_t wp[4], wm[4];
     draw(run_seed, OR_TAG_PAIR, (uint64_t)step, (uint64_t)sweep, (uint64_t)pair_stream, 0, wp);
@@ -377,13 +399,21 @@ static void propose(int32_t N, uint64_t run_seed, int64_t pair_stream, int64_t c
     if (k >= j) k += 1;
     double aj2 = a[2 * j] * a[2 * j] + a[2 * j + 1] * a[2 * j + 1];
     double ak2 = a[2 * k] * a[2 * k] + a[2 * k + 1] * a[2 * k + 1];
-    double K = pow(aj2 * aj2 + ak2 * ak2, 0.25);
     double phj = 2.0 * OR_PI * u53(wm[0]);
     double phk = 2.0 * OR_PI * u53(wm[1]);
-    double theta = 0.5 * OR_PI * u53(wm[2]);
-    double cj = cos(theta), sk = sin(theta);
-    double Aj = K * sqrt(cj > 0.0 ? cj : 0.0);
-    double Ak = K * sqrt(sk > 0.0 ? sk : 0.0);
+    double Aj, Ak;
+    if (rho == 2) {
+        double K = sqrt(aj2 + ak2);
+        double u = u53(wm[2]);
+        Aj = K * sqrt(1.0 - u);
+        Ak = K * sqrt(u);
+    } else {
+        double K = pow(aj2 * aj2 + ak2 * ak2, 0.25);
+        double theta = 0.5 * OR_PI * u53(wm[2]);
+        double cj = cos(theta), sk = sin(theta);
+        Aj = K * sqrt(cj > 0.0 ? cj : 0.0);
+        Ak = K * sqrt(sk > 0.0 ? sk : 0.0);
+    }
     aj_new[0] = Aj * cos(phj);
     aj_new[1] = Aj * sin(phj);
     ak_new[0] = Ak * cos(phk);
@@ -403,7 +433,7 @@ static int32_t sweep_copy(const or_pt_params* P, const or_lists* L, double* a, d
     for (int32_t step = 0; step < N / 2; ++step) {
         int32_t j, k;
         double aj_new[2], ak_new[2], u;
-        propose(N, P->run_seed, pair_stream, copy_id, sweep, step, a, &j, &k, aj_new, ak_new, &u);
+        propose(N, rho_of(P), P->run_seed, pair_stream, copy_id, sweep, step, a, &j, &k, aj_new, ak_new, &u);
         double aj_old[2] = {a[2 * j], a[2 * j + 1]};
         /* snapshot: a_j replaced by its proposal, a_k old */
         a[2 * j] = aj_new[0];
@@ -462,27 +492,27 @@ static void swap_round(const or_pt_params* P, or_pt_state* S, or_pt_accum* A)
 
 /* Recompute every energy from scratch and restore the constraint if it has
  * drifted by more than renorm_tol (H is homogeneous of degree 4, so scaling a
- * by (N/S)^(1/4) scales H by N/S).  Returns the largest relative difference
- * between the running and recomputed energies. */
+ * by f = (N/S)^(1/rho), S = sum |a|^rho, scales H by f^4).  Returns the
+ * largest relative difference between the running and recomputed energies. */
 static double resync(const or_pt_params* P, or_pt_state* S)
 {
-    int32_t N = P->n_modes, R = P->n_temps * P->n_reps;
+    int32_t N = P->n_modes, R = P->n_temps * P->n_reps, rho = rho_of(P);
     double worst = 0.0;
     for (int32_t c = 0; c < R; ++c) {
         double* a = &S->a[(size_t)2 * N * c];
         double H = or_energy(P->n_terms, P->quads, P->J, a);
-        double S4 = 0.0;
+        double Sr = 0.0;
         for (int32_t k = 0; k < N; ++k) {
             double u = a[2 * k] * a[2 * k] + a[2 * k + 1] * a[2 * k + 1];
-            S4 += u * u;
+            Sr += rho == 2 ? u : u * u;
         }
         double scale = fabs(H) > 1.0 ? fabs(H) : 1.0;
         double d = fabs(S->E[c] - H) / scale;
         if (d > worst) worst = d;
-        if (fabs(S4 / N - 1.0) > P->renorm_tol) {
-            double f = pow((double)N / S4, 0.25);
+        if (fabs(Sr / N - 1.0) > P->renorm_tol) {
+            double f = pow((double)N / Sr, 1.0 / rho);
             for (int32_t k = 0; k < 2 * N; ++k) a[k] *= f;
-            H *= (double)N / S4;
+            H *= f * f * f * f;
         }
         S->E[c] = H;
     }

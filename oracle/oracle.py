@@ -51,7 +51,7 @@ def build(force: bool = True) -> str:
 
 class PTParams(C.Structure):
     _fields_ = [
-        ("n_modes", C.c_int32), ("pad0", C.c_int32), ("n_terms", C.c_int64),
+        ("n_modes", C.c_int32), ("rho", C.c_int32), ("n_terms", C.c_int64),
         ("quads", C.c_void_p), ("J", C.c_void_p),
         ("n_temps", C.c_int32), ("n_reps", C.c_int32), ("temps", C.c_void_p),
         ("run_seed", C.c_uint64), ("sample", C.c_int32), ("shared_pairs", C.c_int32),
@@ -95,6 +95,7 @@ def lib():
             L.or_pair_dE.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_int32, P, P]
             L.or_pair_dE.restype = C.c_double
             L.or_init_copy.argtypes = [C.c_int32, C.c_uint64, C.c_int64, P]
+            L.or_init_copy_rho.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_int32, P]
             L.or_pt_init.argtypes = [P, P]
             L.or_pt_run.argtypes = [P, P, P, C.c_int64]
             L.or_pt_run.restype = C.c_double
@@ -166,9 +167,13 @@ def pair_dE(g: Graph, a: np.ndarray, j: int, k: int, aj_new: complex, ak_new: co
     return lib().or_pair_dE(g.N, g.n_terms, _p(g.quads), _p(g.J), _p(a), j, k, _p(x), _p(y))
 
 
-def init_copy(N: int, run_seed: int, copy_id: int) -> np.ndarray:
+def init_copy(N: int, run_seed: int, copy_id: int, rho: int = 4) -> np.ndarray:
+    """beta = 0 draw on the constraint surface sum |a|^rho = N (rho = 4 or 2)."""
     a = np.zeros(N, dtype=np.complex128)
-    lib().or_init_copy(N, run_seed, copy_id, _p(a))
+    if rho == 4:
+        lib().or_init_copy(N, run_seed, copy_id, _p(a))
+    else:
+        lib().or_init_copy_rho(N, run_seed, copy_id, rho, _p(a))
     return a
 
 
@@ -178,14 +183,17 @@ class PT:
     def __init__(self, g: Graph, temps, n_reps: int = 2, run_seed: int = 1, sample: int = 0,
                  shared_pairs: bool = False, swap_interval: int = 1, resync_interval: int = 100,
                  renorm_tol: float = 1e-6, measure_start: int = 0, measure_interval: int = 1,
-                 n_bins: int = 100, series_len: int = 0, n_threads: int = 0):
+                 n_bins: int = 100, series_len: int = 0, n_threads: int = 0, rho: int = 4):
+        if rho not in (2, 4):
+            raise ValueError("rho must be 4 (smoothed cubic) or 2 (spherical)")
         self.g = g
         self.temps = np.ascontiguousarray(temps, dtype=np.float64)
         if np.any(np.diff(self.temps) <= 0):
             raise ValueError("temperatures must be strictly ascending")
         T = len(self.temps)
         self.T, self.n_reps, self.R = T, n_reps, T * n_reps
-        self.P = PTParams(n_modes=g.N, n_terms=g.n_terms, quads=_p(g.quads).value, J=_p(g.J).value,
+        self.rho = rho
+        self.P = PTParams(n_modes=g.N, rho=rho, n_terms=g.n_terms, quads=_p(g.quads).value, J=_p(g.J).value,
                           n_temps=T, n_reps=n_reps, temps=_p(self.temps).value, run_seed=run_seed,
                           sample=sample, shared_pairs=int(shared_pairs), swap_interval=swap_interval,
                           resync_interval=resync_interval, renorm_tol=renorm_tol,

@@ -72,6 +72,32 @@ def beta0_draw(N: int, M: int, rng: np.random.Generator) -> np.ndarray:
     return np.sqrt(u) * np.exp(1j * ph)
 
 
+def beta0_draw_sphere(N: int, M: int, rng: np.random.Generator) -> np.ndarray:
+    """M i.i.d. configurations of the infinite-temperature law on the complex
+    sphere sum |a|^2 = N: a = sqrt(N) z / ||z|| with z complex standard normal."""
+    z = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
+    return math.sqrt(N) * z / np.linalg.norm(z, axis=1, keepdims=True)
+
+
+def beta0_moments_sphere(N: int) -> dict:
+    """Closed forms on the complex sphere: the intensities are N times a flat
+    Dirichlet vector, so |a|^2 / N ~ Beta(1, N - 1) with E x^m = m! (N-1)! / (N+m-1)!;
+    q = Re <a, b> / N is the cosine of two independent uniform directions of
+    R^(2N), variance 1 / (2N)."""
+    return {
+        "E|a|^2": 1.0,
+        "E|a|^4": 2.0 * N / (N + 1.0),
+        "E|a|^8": 24.0 * N ** 3 / ((N + 1.0) * (N + 2.0) * (N + 3.0)),
+        "Var q": 1.0 / (2.0 * N),
+    }
+
+
+def var0_energy_sphere(N: int, J: np.ndarray) -> float:
+    """Var of H at infinite temperature on the sphere: 2 sum J^2 E[I_p I_s I_m I_n]
+    with E[I_p I_s I_m I_n] = N^4 (N-1)! / (N+3)!."""
+    return 2.0 * N ** 3 / ((N + 1.0) * (N + 2.0) * (N + 3.0)) * float(np.sum(J ** 2))
+
+
 def beta0_moments(N: int) -> dict:
     """Closed forms at infinite temperature."""
     ex1 = math.exp(math.lgamma(N / 2) - math.lgamma((N + 1) / 2)) / math.sqrt(math.pi)
@@ -95,18 +121,19 @@ def comb_count(N: int) -> int:
     return (N - 1) * (N - 3) * (2 * N - 1) // 24
 
 
-def importance_reference(quads, J, N, temps, M, seed, chunk=200000):
+def importance_reference(quads, J, N, temps, M, seed, chunk=200000, draw=None):
     """Thermal averages at each temperature by reweighting i.i.d. infinite-
     temperature draws: <O>_beta = E0[O w] / E0[w], w = exp(-beta H).  Two
     independent draws give the overlap.  Returns (mean, stderr) dicts of
     arrays over temps; the error is the delta-method error of a ratio
     estimator, sqrt(sum w^2 (O - mean)^2) / sum w."""
     rng = np.random.default_rng(seed)
+    draw = draw or beta0_draw
     cols = {k: [] for k in ("Ha", "Hb", "y2", "y4", "q")}
     for start in range(0, M, chunk):
         m = min(chunk, M - start)
-        a = beta0_draw(N, m, rng)
-        b = beta0_draw(N, m, rng)
+        a = draw(N, m, rng)
+        b = draw(N, m, rng)
         cols["Ha"].append(energy_batch(quads, J, a))
         cols["Hb"].append(energy_batch(quads, J, b))
         I = np.sum(np.abs(a) ** 2, axis=1)

@@ -336,3 +336,100 @@ def test_pt_is_deterministic_and_thread_independent(oracle):
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][2], out[1][2])
+
+
+# --------------------------------------------------------------------------- spherical constraint (rho = 2)
+def test_rho2_init_on_sphere_and_beta0_law(oracle):
+    """rho = 2 (sum |a|^2 = N, the spherical constraint the paper compares
+    with): the initial draw is the uniform law on the complex sphere."""
+    N = 12
+    M = 20000
+    a = np.array([oracle.init_copy(N, 78, c, rho=2) for c in range(M)])
+    s2 = np.sum(np.abs(a) ** 2, axis=1)
+    assert np.max(np.abs(s2 - N)) < 1e-12 * N
+    ref = brute.beta0_moments_sphere(N)
+    u = np.abs(a) ** 2
+    assert np.mean(u ** 2) == pytest.approx(ref["E|a|^4"], abs=4 * np.std(u ** 2) / math.sqrt(u.size))
+    assert np.mean(u ** 4) == pytest.approx(ref["E|a|^8"], abs=4 * np.std(u ** 4) / math.sqrt(u.size) * 3)
+    assert abs(np.mean(a / np.abs(a))) < 5.0 / math.sqrt(a.size)
+
+
+def test_rho2_beta0_chain_preserves_law_and_constraint(oracle):
+    """rho = 2 at infinite temperature: the chain keeps sum |a|^2 = N and the
+    uniform law on the sphere (intensity moments, overlap variance 1/(2N)).
+    Drawing theta uniform with A' = (K cos theta, K sin theta) instead would
+    put the pair's intensity split on the arcsine law, E|a|^4 -> 3N / (N+2)
+    instead of 2N / (N+1): this pin tells the two apart."""
+    N = 8
+    g = oracle.Graph(N, 5)
+    pt = oracle.PT(g, [1e12], n_reps=64, run_seed=3, swap_interval=1, resync_interval=0,
+                   measure_start=0, measure_interval=1, rho=2)
+    ref = brute.beta0_moments_sphere(N)
+    us, qs = [], []
+    for _ in range(400):
+        pt.run(5)
+        u = np.abs(pt.a) ** 2
+        us.append(u.copy())
+        qs.append(np.sum(np.conj(pt.a[0::2]) * pt.a[1::2], axis=1).real / N)
+    us = np.array(us)
+    assert np.max(np.abs(np.sum(us, axis=2) - N)) < 1e-10
+    assert np.all(pt.acc["acc"] == pt.acc["tries"])
+    per_copy4 = (us ** 2).mean(axis=(0, 2))
+    assert np.mean(per_copy4) == pytest.approx(ref["E|a|^4"], abs=5 * per_copy4.std() / 8)
+    assert abs(np.mean(per_copy4) - 3.0 * N / (N + 2.0)) > 5 * per_copy4.std() / 8
+    per_copy8 = (us ** 4).mean(axis=(0, 2))
+    assert np.mean(per_copy8) == pytest.approx(ref["E|a|^8"], abs=5 * per_copy8.std() / 8)
+    q2 = (np.array(qs) ** 2).mean(axis=0)
+    assert np.mean(q2) == pytest.approx(ref["Var q"], abs=5 * q2.std() / math.sqrt(len(q2)))
+
+
+def test_rho2_high_temperature_expansion(oracle):
+    """rho = 2: <H>_beta = -beta Var0(H) + O(beta^2), Var0 on the sphere."""
+    N = 10
+    g = oracle.Graph(N, 8)
+    v0 = brute.var0_energy_sphere(N, g.J)
+    T = 20.0
+    pt = oracle.PT(g, [T], n_reps=32, run_seed=4, swap_interval=1000000, resync_interval=0,
+                   measure_start=200, measure_interval=2, rho=2)
+    pt.run(4200)
+    mean = pt.acc["e_sum"][0] / pt.acc["e_n"][0]
+    var = pt.acc["e_sq"][0] / pt.acc["e_n"][0] - mean ** 2
+    assert var == pytest.approx(v0, rel=0.05)
+    err = math.sqrt(v0 / pt.acc["e_n"][0]) * 3.0
+    assert mean == pytest.approx(-v0 / T, abs=4 * err + 0.05 * v0 / T)
+
+
+def test_rho2_resync_restores_sphere(oracle):
+    """A state off the sphere by 3% keeps its norm through the moves (each
+    preserves |a_j|^2 + |a_k|^2) and is rescaled onto sum |a|^2 = N at the
+    recomputation, with the running energy reset to H of the rescaled state."""
+    N = 9
+    g = oracle.Graph(N, 6)
+    pt = oracle.PT(g, [0.7], n_reps=1, run_seed=2, resync_interval=1, renorm_tol=1e-9, rho=2)
+    pt.a[:] *= 1.015
+    pt.E[0] = oracle.energy(g, pt.a[0])
+    pt.run(1)
+    assert np.sum(np.abs(pt.a[0]) ** 2) == pytest.approx(N, rel=1e-12)
+    assert pt.E[0] == pytest.approx(oracle.energy(g, pt.a[0]), rel=1e-10, abs=1e-12)
+
+
+@pytest.mark.slow
+def test_rho2_pt_matches_importance_sampling(oracle):
+    """rho = 2 PT against importance sampling from uniform draws on the sphere."""
+    N = 8
+    g = oracle.Graph(N, 31)
+    temps = np.array([1.0, 1.4, 2.0])
+    ref, ref_err = brute.importance_reference(g.quads.astype(np.int64), g.J, N, temps, M=600000, seed=6,
+                                              draw=brute.beta0_draw_sphere)
+    rows = []
+    for s in range(1, 7):
+        pt = oracle.PT(g, temps, n_reps=2, run_seed=s, swap_interval=1, resync_interval=100,
+                       measure_start=1000, measure_interval=1, n_bins=40, rho=2)
+        pt.run(10000)
+        A = pt.acc
+        rows.append(dict(E=A["e_sum"] / A["e_n"], y2=A["y2_sum"] / A["e_n"], q2=A["q_sq"] / A["q_n"]))
+    for key in ("E", "y2", "q2"):
+        vals = np.array([r[key] for r in rows])
+        m, se = vals.mean(axis=0), vals.std(axis=0, ddof=1) / math.sqrt(len(rows))
+        tol = 4.5 * np.sqrt(se ** 2 + ref_err[key] ** 2)
+        assert np.all(np.abs(m - ref[key]) < tol), (key, m, ref[key], se, ref_err[key])
