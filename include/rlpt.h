@@ -146,7 +146,13 @@ typedef struct rlpt_config {
                                  every recomputation, rlpt_set_state and learned rounds.
                                  Needs 12 * n_terms more list entries of 4 + 4|8 bytes and
                                  (N^2 + 1) * 4 bytes per sample. */
-    int32_t pad_fm;
+    int32_t rho;              /* global constraint sum_k |a_k|^rho = N (eq. SmoothedCubic): 4 (default;
+                                 0 reads as 4), or 2 for the spherical constraint of fixed total
+                                 intensity that sec. II.B compares with.  rho = 2 draws the new
+                                 magnitudes as A_j' = K cos theta, A_k' = K sin theta with
+                                 K^2 = |a_j|^2 + |a_k|^2 and sin^2 theta uniform, the flat law on the
+                                 pair's circle, so the energy-only Metropolis test stays exact.
+                                 Learned moves need rho = 4. */
 } rlpt_config;
 
 /* Fill *cfg with defaults: FP32, per-copy pairs, swap every sweep, FP64

@@ -95,6 +95,9 @@ int check_config(const rlpt_config* cfg) {
     if (cfg->mlp_nets < 0) return fail(RLPT_E_ARG, "mlp_nets must be >= 0");
     if (cfg->field_mode != RLPT_FIELDS_STREAM && cfg->field_mode != RLPT_FIELDS_CACHED)
         return fail(RLPT_E_ARG, "bad field_mode");
+    if (cfg->rho != 0 && cfg->rho != 2 && cfg->rho != 4) return fail(RLPT_E_ARG, "rho must be 4 or 2");
+    if (cfg->rho == 2 && cfg->mlp_nets > 0)
+        return fail(RLPT_E_UNSUPPORTED, "learned moves work on the rho = 4 constraint only");
     return RLPT_OK;
 }
 
@@ -501,6 +504,8 @@ int rlpt_config_default(rlpt_config* cfg) {
     cfg->mlp_components = 4;
     cfg->mlp_capacity = 100000;
     cfg->mlp_batch = 512;
+    cfg->field_mode = RLPT_FIELDS_STREAM;
+    cfg->rho = 4;
     return RLPT_OK;
 }
 
@@ -546,6 +551,8 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->ws = d_workspace;
     c->ws_bytes = workspace_bytes;
     c->sh.cached = cfg->field_mode == RLPT_FIELDS_CACHED ? 1 : 0;
+    c->sh.rho = cfg->rho == 2 ? 2 : 4;
+    c->cfg.rho = c->sh.rho;
     unsigned char* b = static_cast<unsigned char*>(d_workspace);
     fill_ptrs(c->pf, b, r);
     fill_ptrs(c->pd, b, r);

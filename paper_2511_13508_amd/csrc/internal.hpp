@@ -146,7 +146,7 @@ struct ShapeInfo {
     int32_t layout;             // ListLayout
     int32_t cached;             // 1: cached local fields (pair lists + updates on acceptance)
     int32_t by_slot;            // items name temperature slots (hottest first), copies found via copy_at
-    int32_t pad2;
+    int32_t rho;                // constraint sum |a|^rho = N: 4 (smoothed cubic) or 2 (spherical)
     uint64_t run_seed;
     double renorm_tol;
     double drift_tol;

@@ -193,7 +193,7 @@ struct StepDraw {
 
 template <typename R>
 __device__ inline StepDraw<R> draw_step(uint64_t seed, int64_t pair_stream, int64_t copy_id, int64_t sweep,
-                                        int step, int N) {
+                                        int step, int N, int rho) {
     const Philox4 wp = philox4x64((uint64_t)step, (uint64_t)sweep, (uint64_t)pair_stream, 0, seed, kTagPair);
     const Philox4 wm = philox4x64((uint64_t)step, (uint64_t)sweep, (uint64_t)copy_id, 0, seed, kTagMove);
     const int j = index_below(wp.v[0], N);
@@ -209,9 +209,15 @@ __device__ inline StepDraw<R> draw_step(uint64_t seed, int64_t pair_stream, int6
     sincos_r(two_pi * uniform01<R>(wm.v[1]), &s, &c);
     d.ekr = c;
     d.eki = s;
-    sincos_r((R)0.5 * pi_v<R>() * uniform01<R>(wm.v[2]), &s, &c);
-    d.cj = sqrt(c > (R)0 ? c : (R)0);
-    d.sk = sqrt(s > (R)0 ? s : (R)0);
+    if (rho == 2) {  // sin^2 theta uniform: A_j' = K sqrt(1 - u), A_k' = K sqrt(u)
+        const R u = uniform01<R>(wm.v[2]);
+        d.cj = sqrt((R)1 - u);
+        d.sk = sqrt(u);
+    } else {  // theta uniform: A_j' = K sqrt(cos theta), A_k' = K sqrt(sin theta)
+        sincos_r((R)0.5 * pi_v<R>() * uniform01<R>(wm.v[2]), &s, &c);
+        d.cj = sqrt(c > (R)0 ? c : (R)0);
+        d.sk = sqrt(s > (R)0 ? s : (R)0);
+    }
     d.u = uniform01<R>(wm.v[3]);
     return d;
 }
@@ -262,14 +268,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     for (int sw = 0; sw < n_sweeps; ++sw) {
         __syncthreads();
         if (active)
-            for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N);
+            for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N, sh.rho);
         __syncthreads();
         if (active && gt == 0) {  // snapshot of step 0
             const int j = tab[0].jk & 0xffff, k = tab[0].jk >> 16;
             ajo = a[j];
             const R2<R> ako = a[k];
             const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako.x * ako.x + ako.y * ako.y;
-            const R K = sqrt(sqrt(uj * uj + uk * uk));
+            const R K = sh.rho == 2 ? sqrt(uj + uk) : sqrt(sqrt(uj * uj + uk * uk));
             ajn = mk2<R>(K * tab[0].cj * tab[0].ejr, K * tab[0].cj * tab[0].eji);
             akn = mk2<R>(K * tab[0].sk * tab[0].ekr, K * tab[0].sk * tab[0].eki);
             a[j] = ajn;
@@ -318,7 +324,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
                     ajo = a[j2];
                     const R2<R> ako2 = a[k2];
                     const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
-                    const R K = sqrt(sqrt(uj * uj + uk * uk));
+                    const R K = sh.rho == 2 ? sqrt(uj + uk) : sqrt(sqrt(uj * uj + uk * uk));
                     ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
                     akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
                     a[j2] = ajn;
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
         ajo = a[j2];
         const R2<R> ako2 = a[k2];
         const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
-        const R K = sqrt(sqrt(uj * uj + uk * uk));
+        const R K = sh.rho == 2 ? sqrt(uj + uk) : sqrt(sqrt(uj * uj + uk * uk));
         const R2<R> ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
         akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
         a[j2] = ajn;
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
         __syncthreads();
         if (active)
             for (int s = gt; s < steps; s += nt) {
-                const StepDraw<R> d = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N);
+                const StepDraw<R> d = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N, sh.rho);
                 tab[s] = d;
                 const int64_t pk = (int64_t)(d.jk & 0xffff) * N + (d.jk >> 16);
                 pr[s] = make_uint2(ps[pk], ps[pk + 1]);
@@ -652,23 +658,29 @@ __global__ __launch_bounds__(256) void k_init(DevPtrs<R> P, ShapeInfo sh) {
     const int N = sd.N;
     const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
     R* amp = P.amp + 2 * (sd.amp_base + local * N);
+    // rho = 4: a normal g_k per mode, intensity sqrt(N) |g_k| / ||g||;
+    // rho = 2: an exponential e_k per mode, intensity N e_k / sum e
+    auto weight = [&](const Philox4& w) {
+        const double u1 = 1.0 - uniform01<double>(w.v[0]);
+        if (sh.rho == 2) return -log(u1);
+        const double u2 = uniform01<double>(w.v[1]);
+        return sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+    };
     double part = 0.0;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const Philox4 w = philox4x64((uint64_t)k, (uint64_t)c, 0, 0, sh.run_seed, kTagInit);
-        const double u1 = 1.0 - uniform01<double>(w.v[0]), u2 = uniform01<double>(w.v[1]);
-        const double gk = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
-        part += gk * gk;
+        const double gk = weight(w);
+        part += sh.rho == 2 ? gk : gk * gk;
     }
     part = wave_sum(part);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
     __syncthreads();
-    const double norm2 = red[0] + red[1] + red[2] + red[3];
+    const double norm = red[0] + red[1] + red[2] + red[3];
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const Philox4 w = philox4x64((uint64_t)k, (uint64_t)c, 0, 0, sh.run_seed, kTagInit);
-        const double u1 = 1.0 - uniform01<double>(w.v[0]), u2 = uniform01<double>(w.v[1]);
-        const double gk = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+        const double gk = weight(w);
         const double ph = 2.0 * 3.14159265358979323846 * uniform01<double>(w.v[2]);
-        const double u = sqrt((double)N) * fabs(gk) / sqrt(norm2);
+        const double u = sh.rho == 2 ? (double)N * gk / norm : sqrt((double)N) * fabs(gk) / sqrt(norm);
         const double A = sqrt(u);
         amp[2 * k] = (R)(A * cos(ph));
         amp[2 * k + 1] = (R)(A * sin(ph));
@@ -695,12 +707,12 @@ __global__ __launch_bounds__(256) void k_resync(DevPtrs<R> P, ShapeInfo sh, int 
     const int N = sd.N;
     const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
     R* amp = P.amp + 2 * (sd.amp_base + local * N);
-    double s4 = 0.0;
+    double s4 = 0.0;  // sum |a|^rho
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const double x = (double)amp[2 * k], y = (double)amp[2 * k + 1];
         a[k] = make_double2(x, y);
         const double u = x * x + y * y;
-        s4 += u * u;
+        s4 += sh.rho == 2 ? u : u * u;
     }
     __syncthreads();
     double H = 0.0;
@@ -734,8 +746,9 @@ __global__ __launch_bounds__(256) void k_resync(DevPtrs<R> P, ShapeInfo sh, int 
             if (!isfinite(Ht) || !isfinite(St) || !isfinite(Er)) atomicOr(&P.counters->error_flags, 2);
             else if (sh.drift_tol > 0.0 && d > sh.drift_tol) atomicOr(&P.counters->error_flags, 1);
             if (fabs(St / (double)N - 1.0) > sh.renorm_tol && St > 0.0) {
-                f = pow((double)N / St, 0.25);
-                Ht *= (double)N / St;
+                // H is homogeneous of degree 4 in a
+                f = sh.rho == 2 ? sqrt((double)N / St) : pow((double)N / St, 0.25);
+                Ht *= f * f * f * f;
             }
             P.E[c] = (R)Ht;
         }

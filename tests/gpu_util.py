@@ -17,6 +17,7 @@ def oracle_pt(oracle, og, temps, sample, ctx_cfg, run_seed, **kw):
     """An oracle PT run mirroring a library context's schedule for one sample."""
     c = ctx_cfg
     kw.setdefault("shared_pairs", bool(c.shared_pairs))
+    kw.setdefault("rho", c.rho if c.rho else 4)
     return oracle.PT(og, temps, n_reps=c.n_reps, run_seed=run_seed, sample=sample,
                      swap_interval=c.swap_interval, resync_interval=c.resync_interval, renorm_tol=c.renorm_tol,
                      measure_start=c.measure_start, measure_interval=c.measure_interval, n_bins=c.n_bins,
