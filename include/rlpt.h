@@ -68,7 +68,15 @@ typedef struct rlpt_graph_desc {
     int32_t omega_kind;  /* RLPT_OMEGA_RANDOM: sorted uniforms on [0,1); RLPT_OMEGA_COMB: k/(N-1) */
     uint64_t seed;       /* disorder seed: frequencies and couplings */
     int32_t split_mask;  /* which splits of each i<j<k<l are tested (RLPT_SPLIT_*) */
-    int32_t pad;
+    int32_t mean_degree; /* 0: the complete mode-locked graph (every matched term).  z > 0: a sparse
+                            mode-locked graph with finite connectivity per mode (the dilution sec. II.D
+                            and the conclusions propose), c = floor(z N / 4) terms drawn uniformly
+                            without replacement from the matched terms: attempt t takes Philox
+                            counter (t, 2, 0, 0) -> four indices (top 32 bits of each word times N),
+                            a split from the low 32 bits of word 0 times 3 (0: (a,d|b,c), 1:
+                            (a,c|b,d), 2: (a,b|c,d) on the sorted indices a<b<c<d), kept if the
+                            indices are distinct, the split is in split_mask, the term is matched
+                            and new.  Terms in acceptance order; J as for the complete graph. */
     double gamma;        /* linewidth; <= 0 selects 1/(2(N-1)) (eq. gamma_scaling) */
 } rlpt_graph_desc;
 

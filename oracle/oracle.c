@@ -154,6 +154,51 @@ int64_t or_graph_terms(int32_t N, const double* omega, double gamma, int32_t pai
 
 double or_default_gamma(int32_t N) { return 1.0 / (2.0 * (double)(N - 1)); }
 
+/* Sparse mode-locked graph (finite connectivity per mode, the dilution the
+ * paper proposes in sec. II.D and its conclusions; the construction is this
+ * library's reading): c = floor(z N / 4) terms drawn uniformly without
+ * replacement from the matched terms of the complete graph, by rejection.
+ * Attempt t reads Philox counter (t, 2, 0, 0): four modes (top 32 bits of
+ * each word times N), a split from the low 32 bits of word 0 times 3.  The
+ * attempt is kept when the four modes are distinct, the split (A, B, C on the
+ * sorted modes, as above) is in pair_mask, the split is matched and the term
+ * was not kept before.  Terms in acceptance order.  Returns c, or -1 when the
+ * attempt budget (64 N c + 10^6) runs out. */
+int64_t or_graph_terms_sparse(int32_t N, const double* omega, double gamma, int32_t pair_mask, int32_t z,
+                              uint64_t seed, int16_t* quads)
+{
+    int64_t c = (int64_t)z * N / 4, kept = 0;
+    uint64_t budget = 64ull * (uint64_t)N * (uint64_t)c + 1000000ull;
+    for (uint64_t t = 0; t < budget && kept < c; ++t) {
+        uint64_t w[4];
+        draw(seed, OR_TAG_GRAPH, t, 2, 0, 0, w);
+        int32_t v[4];
+        for (int r = 0; r < 4; ++r) v[r] = pick(w[r], N);
+        int split = (int)(((w[0] & 0xffffffffULL) * 3ULL) >> 32);
+        /* sort the four modes (insertion sort) */
+        for (int a = 1; a < 4; ++a)
+            for (int b = a; b > 0 && v[b - 1] > v[b]; --b) {
+                int32_t x = v[b];
+                v[b] = v[b - 1];
+                v[b - 1] = x;
+            }
+        if (v[0] == v[1] || v[1] == v[2] || v[2] == v[3]) continue;
+        if (!(pair_mask & (1 << split))) continue;
+        int32_t t4[3][4] = {{v[0], v[3], v[1], v[2]}, {v[0], v[2], v[1], v[3]}, {v[0], v[1], v[2], v[3]}};
+        int32_t* q = t4[split];
+        double mismatch = (omega[q[0]] + omega[q[1]]) - (omega[q[2]] + omega[q[3]]);
+        if (!(fabs(mismatch) < gamma)) continue;
+        int dup = 0;
+        for (int64_t e = 0; e < kept && !dup; ++e)
+            dup = quads[4 * e] == q[0] && quads[4 * e + 1] == q[1] && quads[4 * e + 2] == q[2] &&
+                  quads[4 * e + 3] == q[3];
+        if (dup) continue;
+        for (int r = 0; r < 4; ++r) quads[4 * kept + r] = (int16_t)q[r];
+        ++kept;
+    }
+    return kept == c ? c : -1;
+}
+
 /* J_q = sigma * g_q, g_q standard normal from counter (q, 1, 0, 0) */
 void or_couplings(int32_t N, uint64_t seed, int64_t n_terms, double* J)
 {

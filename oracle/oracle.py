@@ -86,6 +86,8 @@ def lib():
             L.or_frequencies.argtypes = [C.c_int32, C.c_uint64, C.c_int32, P]
             L.or_graph_terms.argtypes = [C.c_int32, P, C.c_double, C.c_int32, P, C.c_int64]
             L.or_graph_terms.restype = C.c_int64
+            L.or_graph_terms_sparse.argtypes = [C.c_int32, P, C.c_double, C.c_int32, C.c_int32, C.c_uint64, P]
+            L.or_graph_terms_sparse.restype = C.c_int64
             L.or_default_gamma.argtypes = [C.c_int32]
             L.or_default_gamma.restype = C.c_double
             L.or_couplings.argtypes = [C.c_int32, C.c_uint64, C.c_int64, P]
@@ -129,17 +131,24 @@ class Graph:
     """One disorder sample: frequencies, kept terms (p, s, m, n) and couplings."""
 
     def __init__(self, N: int, seed: int, omega_kind: int = OMEGA_RANDOM, split_mask: int = SPLIT_ALL,
-                 gamma: float | None = None):
+                 gamma: float | None = None, mean_degree: int = 0):
         if N < 4:
             raise ValueError("N must be >= 4")
         self.N, self.seed = N, seed
         self.omega = frequencies(N, seed, omega_kind)
         self.gamma = default_gamma(N) if gamma is None or gamma <= 0 else float(gamma)
         L = lib()
-        c = L.or_graph_terms(N, _p(self.omega), self.gamma, split_mask, None, 0)
-        self.quads = np.zeros((max(c, 1), 4), dtype=np.int16)
-        c2 = L.or_graph_terms(N, _p(self.omega), self.gamma, split_mask, _p(self.quads), c)
-        assert c2 == c
+        if mean_degree > 0:
+            cap = max(mean_degree * N // 4, 1)
+            self.quads = np.zeros((cap, 4), dtype=np.int16)
+            c = L.or_graph_terms_sparse(N, _p(self.omega), self.gamma, split_mask, mean_degree, seed, _p(self.quads))
+            if c < 0:
+                raise ValueError("could not draw the sparse graph's terms")
+        else:
+            c = L.or_graph_terms(N, _p(self.omega), self.gamma, split_mask, None, 0)
+            self.quads = np.zeros((max(c, 1), 4), dtype=np.int16)
+            c2 = L.or_graph_terms(N, _p(self.omega), self.gamma, split_mask, _p(self.quads), c)
+            assert c2 == c
         self.quads = self.quads[:c].copy()
         self.n_terms = int(c)
         self.J = np.zeros(max(c, 1), dtype=np.float64)

@@ -102,8 +102,8 @@ int check_config(const rlpt_config* cfg) {
 }
 
 // list layout of a context: chunked needs N <= 256 everywhere; the automatic
-// choice also avoids it for small N, where padding partner groups to 4
-// entries inflates the lists
+// choice also avoids it for small N and sparse graphs, where padding partner
+// groups to 4 entries inflates the lists
 int choose_layout(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int* layout) {
     int max_N = 0, min_N = 1 << 30;
     for (int i = 0; i < S; ++i) {
@@ -114,8 +114,17 @@ int choose_layout(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int
     else if (cfg.list_layout == RLPT_LAYOUT_CHUNKED) {
         if (max_N > kMaxChunkModes) return fail(RLPT_E_ARG, "the chunked list layout needs N <= 256");
         *layout = kLayoutChunked;
-    } else
-        *layout = (max_N <= kMaxChunkModes && min_N >= 32) ? kLayoutChunked : kLayoutPacked;
+    } else {
+        // chunked pays when partner groups are long: dense graphs, not sparse ones,
+        // whose groups of about one entry would be padded to four
+        size_t chunk_entries = 0, list_entries = 0;
+        for (int i = 0; i < S; ++i) {
+            chunk_entries += 4 * g[i]->cx.size();
+            list_entries += g[i]->mode_start.back();
+        }
+        const bool dense = 4 * chunk_entries <= 5 * list_entries;
+        *layout = (max_N <= kMaxChunkModes && min_N >= 32 && dense) ? kLayoutChunked : kLayoutPacked;
+    }
     return RLPT_OK;
 }
 
@@ -420,10 +429,15 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
     std::vector<int> order(c->S);
     for (int s = 0; s < c->S; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return c->N[a] > c->N[b2]; });
+    // every copy group is sized for the largest N of the context: cap the copies
+    // per workgroup so that the groups fit in 64 KiB of LDS
+    const size_t per_copy = sweep_lds_bytes(c->cfg.precision, block, 1, c->max_N, c->sh.cached, c->sh.short_lists);
+    const int lds_cap = (int)std::max<size_t>(1, (64 * 1024) / per_copy);
     for (int s : order) {
         auto it_c = copies.find(c->N[s]);
         int cpw = it_c == copies.end() ? 1 : it_c->second;
-        cpw = std::max(1, std::min(cpw, block / 64));
+        cpw = std::max(1, std::min({cpw, block / 64, lds_cap}));
+        if (c->sh.short_lists) cpw = std::min(block / 64, lds_cap);  // one wave per copy
         for (int first = 0; first < c->Rc; first += cpw) {
             ItemDev it{};
             it.first_copy = s * c->Rc + first;
@@ -437,7 +451,7 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
         std::stable_sort(items.begin(), items.end(), [&](const ItemDev& x, const ItemDev& y) {
             return x.first_copy - x.sample * c->Rc < y.first_copy - y.sample * c->Rc;
         });
-    const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached);
+    const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached, c->sh.short_lists);
     if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
     c->items = items;
     c->tile_copies = copies;
@@ -553,6 +567,14 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->sh.cached = cfg->field_mode == RLPT_FIELDS_CACHED ? 1 : 0;
     c->sh.rho = cfg->rho == 2 ? 2 : 4;
     c->cfg.rho = c->sh.rho;
+    // short lists (sparse graphs): every padded list fits in one wave's registers
+    if (layout == kLayoutPacked && !c->sh.cached) {
+        uint32_t longest = 0;
+        for (int s = 0; s < n_graphs; ++s)
+            for (int l = 0; l < graphs[s]->N; ++l)
+                longest = std::max(longest, graphs[s]->mode_start[l + 1] - graphs[s]->mode_start[l]);
+        c->sh.short_lists = longest <= 128 ? 1 : 0;
+    }
     unsigned char* b = static_cast<unsigned char*>(d_workspace);
     fill_ptrs(c->pf, b, r);
     fill_ptrs(c->pd, b, r);

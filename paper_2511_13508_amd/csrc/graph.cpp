@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <new>
+#include <unordered_set>
 
 #include "internal.hpp"
 #include "philox.hpp"
@@ -39,6 +40,38 @@ void window(const std::vector<double>& w, int k, double lo, double hi, int* firs
     auto b = w.begin() + (k + 1);
     *first = (int)(std::lower_bound(b, w.end(), lo) - w.begin());
     *last = (int)(std::upper_bound(b, w.end(), hi) - w.begin());
+}
+
+// Sparse mode-locked graph: c = floor(z N / 4) matched terms drawn uniformly
+// without replacement (rejection sampling over random quadruplets and splits,
+// in the attempt order of the Philox stream (t, 2, 0, 0)).
+bool sparse_terms(rlpt_graph* g, const rlpt_graph_desc* d) {
+    const int N = g->N;
+    const int64_t c = (int64_t)d->mean_degree * N / 4;
+    if (c < 1) return false;
+    const double* w = g->omega.data();
+    std::unordered_set<uint64_t> seen;
+    g->quads.reserve(4 * c);
+    const uint64_t cap = 64ull * (uint64_t)N * (uint64_t)c + 1000000ull;
+    int64_t kept = 0;
+    for (uint64_t t = 0; t < cap && kept < c; ++t) {
+        const rlpt::Philox4 r = rlpt::philox4x64(t, 2, 0, 0, d->seed, rlpt::kTagGraph);
+        int v[4];
+        for (int i = 0; i < 4; ++i) v[i] = rlpt::index_below(r.v[i], N);
+        const int split = (int)(((r.v[0] & 0xffffffffull) * 3ull) >> 32);
+        std::sort(v, v + 4);
+        if (v[0] == v[1] || v[1] == v[2] || v[2] == v[3]) continue;
+        if (!(d->split_mask & (1 << split))) continue;
+        const int t4[3][4] = {{v[0], v[3], v[1], v[2]}, {v[0], v[2], v[1], v[3]}, {v[0], v[1], v[2], v[3]}};
+        const int* q = t4[split];
+        if (!matched(w, q[0], q[1], q[2], q[3], g->gamma)) continue;
+        const uint64_t key = (uint64_t)v[0] | (uint64_t)v[1] << 10 | (uint64_t)v[2] << 20 | (uint64_t)v[3] << 30 |
+                             (uint64_t)split << 40;
+        if (!seen.insert(key).second) continue;
+        for (int i = 0; i < 4; ++i) g->quads.push_back((int16_t)q[i]);
+        ++kept;
+    }
+    return kept == c;
 }
 
 }  // namespace
@@ -67,33 +100,42 @@ extern "C" int rlpt_graph_build(const rlpt_graph_desc* d, rlpt_graph** out) {
             std::sort(g->omega.begin(), g->omega.end());
         }
         const double* w = g->omega.data();
-        const double gam = g->gamma, margin = 4.0 * gam + 1e-9;
-        std::vector<int> cand;
-        for (int i = 0; i < N; ++i)
-            for (int j = i + 1; j < N; ++j)
-                for (int k = j + 1; k < N; ++k) {
-                    // A: w_l ~ w_j + w_k - w_i ; B: w_l ~ w_i + w_k - w_j ; C: w_l ~ w_i + w_j - w_k
-                    const double centre[3] = {w[j] + w[k] - w[i], w[i] + w[k] - w[j], w[i] + w[j] - w[k]};
-                    cand.clear();
-                    for (int s = 0; s < 3; ++s) {
-                        if (!(d->split_mask & (1 << s))) continue;
-                        int f, l;
-                        window(g->omega, k, centre[s] - margin, centre[s] + margin, &f, &l);
-                        for (int x = f; x < l; ++x) cand.push_back(x);
-                    }
-                    if (cand.empty()) continue;
-                    std::sort(cand.begin(), cand.end());
-                    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-                    for (int l : cand) {
-                        const int split[3][4] = {{i, l, j, k}, {i, k, j, l}, {i, j, k, l}};
+        const double gam = g->gamma;
+        if (d->mean_degree > 0) {
+            if (!sparse_terms(g, d)) {
+                delete g;
+                return fail(RLPT_E_ARG, "rlpt_graph_build: could not draw floor(mean_degree N / 4) distinct matched "
+                                        "terms; lower mean_degree");
+            }
+        } else {
+            const double margin = 4.0 * gam + 1e-9;
+            std::vector<int> cand;
+            for (int i = 0; i < N; ++i)
+                for (int j = i + 1; j < N; ++j)
+                    for (int k = j + 1; k < N; ++k) {
+                        // A: w_l ~ w_j + w_k - w_i ; B: w_l ~ w_i + w_k - w_j ; C: w_l ~ w_i + w_j - w_k
+                        const double centre[3] = {w[j] + w[k] - w[i], w[i] + w[k] - w[j], w[i] + w[j] - w[k]};
+                        cand.clear();
                         for (int s = 0; s < 3; ++s) {
                             if (!(d->split_mask & (1 << s))) continue;
-                            const int* t = split[s];
-                            if (matched(w, t[0], t[1], t[2], t[3], gam))
-                                for (int r = 0; r < 4; ++r) g->quads.push_back((int16_t)t[r]);
+                            int f, l;
+                            window(g->omega, k, centre[s] - margin, centre[s] + margin, &f, &l);
+                            for (int x = f; x < l; ++x) cand.push_back(x);
+                        }
+                        if (cand.empty()) continue;
+                        std::sort(cand.begin(), cand.end());
+                        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+                        for (int l : cand) {
+                            const int split[3][4] = {{i, l, j, k}, {i, k, j, l}, {i, j, k, l}};
+                            for (int s = 0; s < 3; ++s) {
+                                if (!(d->split_mask & (1 << s))) continue;
+                                const int* t = split[s];
+                                if (matched(w, t[0], t[1], t[2], t[3], gam))
+                                    for (int r = 0; r < 4; ++r) g->quads.push_back((int16_t)t[r]);
+                            }
                         }
                     }
-                }
+        }
         const int64_t c = (int64_t)g->quads.size() / 4;
         if (c == 0) {
             delete g;

@@ -147,6 +147,8 @@ struct ShapeInfo {
     int32_t cached;             // 1: cached local fields (pair lists + updates on acceptance)
     int32_t by_slot;            // items name temperature slots (hottest first), copies found via copy_at
     int32_t rho;                // constraint sum |a|^rho = N: 4 (smoothed cubic) or 2 (spherical)
+    int32_t short_lists;        // every list fits one wave's registers: the one-wave-per-copy sweep
+    int32_t pad3;
     uint64_t run_seed;
     double renorm_tol;
     double drift_tol;
@@ -161,7 +163,8 @@ struct SweepLaunch {
     size_t lds_bytes;
 };
 
-size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached);
+size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached,
+                       int short_lists);
 
 hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int block,
                        hipStream_t st);

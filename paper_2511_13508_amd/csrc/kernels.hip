@@ -54,11 +54,45 @@ __device__ inline R pi_v() {
 __device__ inline void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ inline void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 
+// cross-lane moves within rows of 16 lanes (DPP: quad_perm [1,0,3,2] = 0xB1,
+// [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140) and reads of
+// one lane's value into every lane (v_readlane, the lane index wave-uniform)
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ inline float read_lane(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double read_lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline uint32_t read_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+// sum over each row of 16 lanes, in every lane of the row
+template <typename R>
+__device__ inline R row_sum(R v) {
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    return v;
+}
+
+// sum over the wave, the same value in every lane (all lanes active)
 template <typename R>
 __device__ inline R wave_sum(R v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = row_sum(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // contribution J conj(a_x) a_y a_z of one packed entry
@@ -342,6 +376,183 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     }
 }
 
+// ---------------------------------------------------------------- short lists (sparse graphs)
+// When every mode's list is short (sparse mode-locked graphs, a few dozen
+// terms per mode) a step is pure latency: load two lists, reduce, decide.
+// One wave runs one copy with no workgroup barrier: lanes 0-31 sum F_j, lanes
+// 32-63 F_k, each from kShortSlots entries per lane held in registers and
+// loaded two steps ahead; each lane keeps the draws of one step of the
+// current and the next 64-step chunk in registers, and every lane reads a
+// step's draws from the lane holding them.  Same chain, same draws as the
+// streaming sweep.  The host takes this path only when no padded list is
+// longer than 32 * kShortSlots entries.
+constexpr int kShortSlots = 4;
+
+// keep the compiler from moving LDS accesses across a write by one lane that
+// all lanes then read (the hardware runs one wave's LDS accesses in order);
+// emits no wait, so global loads in flight stay in flight
+__device__ inline void wave_sync() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// a step's draws plus the list bounds of its two modes
+template <typename R>
+struct ShortStep {
+    StepDraw<R> d;
+    uint32_t bj, ej, bk, ek;
+};
+
+template <typename R>
+__device__ inline ShortStep<R> step_from_lane(const ShortStep<R>& x, int src) {  // src wave-uniform
+    ShortStep<R> o;
+    o.d.jk = read_lane(x.d.jk, src);
+    o.d.ejr = read_lane(x.d.ejr, src);
+    o.d.eji = read_lane(x.d.eji, src);
+    o.d.ekr = read_lane(x.d.ekr, src);
+    o.d.eki = read_lane(x.d.eki, src);
+    o.d.cj = read_lane(x.d.cj, src);
+    o.d.sk = read_lane(x.d.sk, src);
+    o.d.u = read_lane(x.d.u, src);
+    o.bj = read_lane(x.bj, src);
+    o.ej = read_lane(x.ej, src);
+    o.bk = read_lane(x.bk, src);
+    o.ek = read_lane(x.ek, src);
+    return o;
+}
+
+template <typename R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_sweep_short(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const ItemDev it = P.items[blockIdx.x];
+    const SampleDev sd = P.samples[it.sample];
+    const int N = sd.N, steps = sd.n_steps;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= it.n_copies) return;  // no workgroup barrier below: idle waves may leave
+    R2<R>* a = reinterpret_cast<R2<R>*>(smem) + (size_t)wave * max_N;
+    const int c = it.first_copy + wave;
+    const int64_t local = c - (int64_t)it.sample * sh.copies_per_sample;
+    R2<R>* amp_g = reinterpret_cast<R2<R>*>(P.amp) + sd.amp_base + local * N;
+    for (int i = lane; i < N; i += 64) a[i] = amp_g[i];
+    wave_sync();
+    const int t_idx = P.temp_of[c];
+    const R beta = P.beta[t_idx];
+    R E = P.E[c];
+    unsigned int n_acc = 0;
+    const int64_t pair_stream = sh.shared_pairs ? (int64_t)it.sample : (int64_t)c;
+    const int64_t sweep0 = P.counters->sweeps_done;
+    const uint32_t* ms = P.mode_start + sd.mode_base;
+    const uint32_t first = ms[0];
+    const int half = lane >> 5, hl = lane & 31;
+
+    // list entries two steps ahead: even steps use buffer A, odd steps B; the
+    // loads for step s + 2 go into the buffer step s has just used, so each
+    // load has two steps to arrive and no register is copied
+    uint32_t pvA[kShortSlots], pvB[kShortSlots];
+    R pjA[kShortSlots], pjB[kShortSlots];
+    uint32_t inA = 0, inB = 0;  // slots holding a real entry (bit i)
+    auto load = [&](const ShortStep<R>& t, uint32_t* pv, R* pj, uint32_t& in) {  // lanes 0-31: list of j, 32-63: of k
+        const uint32_t b = half ? t.bk : t.bj, e = half ? t.ek : t.ej;
+        in = 0;
+#pragma unroll
+        for (int i = 0; i < kShortSlots; ++i) {
+            // past the end: the sample's first entry (its modes are < N, so the
+            // amplitudes read are this copy's), masked out where it is used, so
+            // that nothing here waits for the load
+            const uint32_t x = b + (uint32_t)(hl + 32 * i);
+            const uint32_t xs = x < e ? x : first;
+            in |= (x < e ? 1u : 0u) << i;
+            pv[i] = P.idx[xs];
+            pj[i] = P.J[xs];
+        }
+    };
+    // draws of the current and the next 64-step chunk, one step per lane (a
+    // lane past the last step draws the last step again: every lane loads on
+    // every path, so the wait counts stay exact and nothing waits early)
+    ShortStep<R> mine, mine2;
+    auto draw_chunk = [&](ShortStep<R>& x, int sw, int base) {
+        const int t = min(base + lane, steps - 1);
+        x.d = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, t, N, sh.rho);
+        const int j = x.d.jk & 0xffff, k = x.d.jk >> 16;
+        x.bj = ms[j];
+        x.ej = ms[j + 1];
+        x.bk = ms[k];
+        x.ek = ms[k + 1];
+    };
+    R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
+    auto snapshot = [&](const StepDraw<R>& d) {  // every lane computes it; lane 0 stores a_j'
+        const int j = d.jk & 0xffff, k = d.jk >> 16;
+        ajo = a[j];
+        const R2<R> ako = a[k];
+        const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako.x * ako.x + ako.y * ako.y;
+        const R K = sh.rho == 2 ? sqrt(uj + uk) : sqrt(sqrt(uj * uj + uk * uk));
+        ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
+        akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
+        wave_sync();
+        if (lane == 0) a[j] = ajn;
+        wave_sync();
+    };
+    ShortStep<R> cur, nxt;
+    // one step: fields from (pv, pj), then the loads of step s + 2 into them
+    auto step = [&](int s, int base, uint32_t* pv, R* pj, uint32_t& in) {
+        const int j = cur.d.jk & 0xffff, k = cur.d.jk >> 16;
+        // fields on the snapshot (a_j new, a_k old): lanes 0-31 F_j, 32-63 F_k
+        R fr = 0, fi = 0;
+#pragma unroll
+        for (int i = 0; i < kShortSlots; ++i) field_term<R>(pv[i], (in >> i) & 1u ? pj[i] : (R)0, a, fr, fi);
+        // step s + 2 (past the last step: the last step again, loaded harmlessly)
+        const int t = min(s + 2, steps - 1);
+        const ShortStep<R> nxt2 = step_from_lane(t < base + 64 ? mine : mine2, t & 63);
+        load(nxt2, pv, pj, in);
+        fr = row_sum(fr);
+        fi = row_sum(fi);
+        const R Fjr = read_lane(fr, 0) + read_lane(fr, 16), Fji = read_lane(fi, 0) + read_lane(fi, 16);
+        const R Fkr = read_lane(fr, 32) + read_lane(fr, 48), Fki = read_lane(fi, 32) + read_lane(fi, 48);
+        // every lane takes the same decision; lane 0 writes LDS
+        const R2<R> ako = a[k];
+        const R dE = pair_delta<R>(ajo, ajn, ako, akn, mk2<R>(Fjr, Fji), mk2<R>(Fkr, Fki));
+        const bool accept = (dE <= (R)0) || (cur.d.u < exp(-beta * dE));
+        wave_sync();
+        if (lane == 0) {
+            if (accept) a[k] = akn;
+            else a[j] = ajo;
+        }
+        if (accept) {
+            E += dE;
+            ++n_acc;
+        }
+        wave_sync();
+        if (s + 1 < steps) snapshot(nxt.d);
+        cur = nxt;
+        nxt = nxt2;
+    };
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        draw_chunk(mine, sw, 0);
+        draw_chunk(mine2, sw, 64);
+        cur = step_from_lane(mine, 0);
+        nxt = step_from_lane(mine, min(1, steps - 1));
+        load(cur, pvA, pjA, inA);
+        load(nxt, pvB, pjB, inB);
+        snapshot(cur.d);
+        for (int base = 0; base < steps; base += 64) {
+            const int end = min(base + 64, steps);
+            for (int s = base; s < end; s += 2) {  // base is even: step s uses A, s + 1 uses B
+                step(s, base, pvA, pjA, inA);
+                if (s + 1 < end) step(s + 1, base, pvB, pjB, inB);
+            }
+            mine = mine2;
+            draw_chunk(mine2, sw, base + 128);
+        }
+    }
+    wave_sync();
+    for (int i = lane; i < N; i += 64) amp_g[i] = a[i];
+    if (lane == 0) {
+        P.E[c] = E;
+        atomicAdd(&P.acc[(size_t)it.sample * sh.n_temps + t_idx], (unsigned long long)n_acc);
+    }
+}
+
 // ---------------------------------------------------------------- cached local fields
 // With every copy's fields kept up to date, the energy change of a two-mode
 // move needs F_j, F_k and, for the one-snapshot rule, the change of F_k from
@@ -507,14 +718,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
     // wave 0 keeps the next step's pair-list entries in registers
     uint32_t pv[kPairPrefetch];
     R pj[kPairPrefetch];
+    uint32_t pin = 0;
     auto prefetch = [&](int s) {
         const uint2 r = pr[s];
+        pin = 0;
 #pragma unroll
         for (int i = 0; i < kPairPrefetch; ++i) {
+            // past the end: the sample's first pair-list entry (modes < N, so the
+            // amplitudes read are this copy's), masked out where it is used
+            // (nothing here waits for the loads)
             const uint32_t e = r.x + (uint32_t)(lane + 64 * i);
-            const bool in = e < r.y;
-            pv[i] = in ? P.pidx[e] : 0u;
-            pj[i] = in ? P.pJ[e] : (R)0;
+            const uint32_t es = e < r.y ? e : ps[0];
+            pin |= (e < r.y ? 1u : 0u) << i;
+            pv[i] = P.pidx[es];
+            pj[i] = P.pJ[es];
         }
     };
     R2<R> ajo = mk2<R>(0, 0), akn = mk2<R>(0, 0);
@@ -557,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
                 const R2<R> dj = snap[0];
                 R cr = 0, ci = 0;
 #pragma unroll
-                for (int i = 0; i < kPairPrefetch; ++i) pair_term<R>(pv[i], pj[i], a, dj, cr, ci);
+                for (int i = 0; i < kPairPrefetch; ++i) pair_term<R>(pv[i], (pin >> i) & 1u ? pj[i] : (R)0, a, dj, cr, ci);
                 const uint2 r = pr[s];
                 for (uint32_t e = r.x + 64 * kPairPrefetch + lane; e < r.y; e += 64) pair_term<R>(P.pidx[e], P.pJ[e], a, dj, cr, ci);
                 if (s + 1 < steps) prefetch(s + 1);
@@ -994,6 +1211,11 @@ template <typename R, int BLOCK>
 hipError_t launch_sweep_t(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int n_sweeps,
                           hipStream_t st) {
     const DevPtrs<R>& P = *static_cast<const DevPtrs<R>*>(ptrs);
+    if (sh.short_lists) {
+        hipLaunchKernelGGL((k_sweep_short<R, BLOCK>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh, L.max_N,
+                           n_sweeps);
+        return hipGetLastError();
+    }
     if (sh.cached) {
         if (sh.layout == kLayoutChunked)
             hipLaunchKernelGGL((k_sweep_cached<R, BLOCK, kLayoutChunked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
@@ -1027,8 +1249,10 @@ hipError_t launch_sweep_r(const void* ptrs, const ShapeInfo& sh, const SweepLaun
 
 }  // namespace
 
-size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached) {
+size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached,
+                       int short_lists) {
     const int waves = block_threads / 64;
+    if (short_lists) return (size_t)max_copies_per_item * max_N * 2 * (precision == RLPT_FP64 ? 8 : 4);
     if (cached)
         return (size_t)max_copies_per_item * (precision == RLPT_FP64 ? group_bytes_cached<double>(max_N, waves)
                                                                      : group_bytes_cached<float>(max_N, waves));

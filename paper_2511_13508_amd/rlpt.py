@@ -52,7 +52,7 @@ class Tile(C.Structure):
 
 class GraphDesc(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("omega_kind", C.c_int32), ("seed", C.c_uint64),
-                ("split_mask", C.c_int32), ("pad", C.c_int32), ("gamma", C.c_double)]
+                ("split_mask", C.c_int32), ("mean_degree", C.c_int32), ("gamma", C.c_double)]
 
 
 class GraphInfo(C.Structure):
@@ -173,9 +173,10 @@ class Graph:
     """A disorder sample built by rlpt_graph_build (host memory)."""
 
     def __init__(self, n_modes: int, seed: int, omega_kind: int = OMEGA_RANDOM, split_mask: int = SPLIT_ALL,
-                 gamma: float = 0.0):
+                 gamma: float = 0.0, mean_degree: int = 0):
         self._h = C.c_void_p()
-        desc = GraphDesc(n_modes=n_modes, omega_kind=omega_kind, seed=seed, split_mask=split_mask, gamma=gamma)
+        desc = GraphDesc(n_modes=n_modes, omega_kind=omega_kind, seed=seed, split_mask=split_mask, gamma=gamma,
+                         mean_degree=mean_degree)
         _check(lib().rlpt_graph_build(C.byref(desc), C.byref(self._h)))
         self.N = n_modes
         self.seed = seed

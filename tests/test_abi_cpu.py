@@ -59,6 +59,27 @@ def test_graph_builder_large_n_count(oracle):
     np.testing.assert_allclose(J, go.J, rtol=1e-15)
 
 
+@pytest.mark.parametrize("N,z,seed,mask", [(32, 8, 1, rlpt.SPLIT_ALL), (256, 16, 2, rlpt.SPLIT_ALL),
+                                           (1024, 32, 3, rlpt.SPLIT_ALL), (100, 10, 4, rlpt.SPLIT_A)])
+def test_sparse_graph_builder_matches_oracle(oracle, N, z, seed, mask):
+    """Sparse mode-locked graphs: the library's sampler (hash-set dedup) and the
+    oracle's (linear scan) keep the same terms in the same order."""
+    g = rlpt.Graph(N, seed, split_mask=mask, mean_degree=z)
+    omega, quads, J = g.export()
+    go = oracle.Graph(N, seed, split_mask=mask, mean_degree=z)
+    assert np.array_equal(omega, go.omega)
+    assert np.array_equal(quads, go.quads)
+    np.testing.assert_allclose(J, go.J, rtol=1e-15, atol=0)
+    assert g.info()["n_terms"] == z * N // 4
+
+
+def test_sparse_graph_too_dense_is_an_error():
+    """Asking for more terms than the complete graph holds fails cleanly."""
+    with pytest.raises(rlpt.RlptError) as e:
+        rlpt.Graph(8, 1, mean_degree=40)
+    assert e.value.code == rlpt.RLPT_E_ARG
+
+
 def test_graph_builder_rejects_bad_input():
     with pytest.raises(rlpt.RlptError) as e:
         rlpt.Graph(3, 0)

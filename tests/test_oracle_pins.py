@@ -433,3 +433,56 @@ def test_rho2_pt_matches_importance_sampling(oracle):
         m, se = vals.mean(axis=0), vals.std(axis=0, ddof=1) / math.sqrt(len(rows))
         tol = 4.5 * np.sqrt(se ** 2 + ref_err[key] ** 2)
         assert np.all(np.abs(m - ref[key]) < tol), (key, m, ref[key], se, ref_err[key])
+
+
+# --------------------------------------------------------------------------- sparse mode-locked graphs
+@pytest.mark.parametrize("N,z,seed", [(16, 8, 1), (64, 8, 2), (200, 12, 3)])
+def test_sparse_graph_terms(oracle, N, z, seed):
+    """floor(z N / 4) terms, each with four distinct modes, frequency matched
+    and kept once; mean degree z."""
+    g = oracle.Graph(N, seed, mean_degree=z)
+    assert g.n_terms == z * N // 4
+    q = g.quads.astype(np.int64)
+    assert np.all(np.sort(q, axis=1)[:, 1:] != np.sort(q, axis=1)[:, :-1])
+    w = g.omega
+    assert np.all(np.abs(w[q[:, 0]] + w[q[:, 1]] - w[q[:, 2]] - w[q[:, 3]]) < g.gamma)
+    assert len({tuple(t) for t in q.tolist()}) == g.n_terms
+    deg = np.bincount(q.ravel(), minlength=N)
+    assert deg.sum() == 4 * g.n_terms
+
+
+def test_sparse_graph_is_uniform_subset_of_complete_graph(oracle):
+    """Every sparse term is a term of the complete mode-locked graph of the
+    same frequencies, and the kept terms are a uniform sample of it: their
+    normalised ranks in the complete graph's term order are uniform on [0, 1)
+    (Kolmogorov-Smirnov over 300 disorder samples)."""
+    from scipy import stats
+    N, z = 14, 8
+    ranks = []
+    for seed in range(300):
+        dense = oracle.Graph(N, seed)
+        sparse = oracle.Graph(N, seed, mean_degree=z)
+        index = {tuple(t): i for i, t in enumerate(dense.quads.tolist())}
+        assert sparse.n_terms <= dense.n_terms
+        for t in sparse.quads.tolist():
+            assert tuple(t) in index
+            ranks.append((index[tuple(t)] + 0.5) / dense.n_terms)
+    assert stats.kstest(ranks, "uniform").pvalue > 1e-3
+
+
+def test_sparse_graph_high_temperature_expansion(oracle):
+    """PT on a sparse graph obeys the same high-temperature law as on the
+    complete graph: Var0(H) = 8N / (pi^2 (N+2)) sum J^2 depends only on the
+    term set being distinct quadruplets."""
+    N = 48
+    g = oracle.Graph(N, 9, mean_degree=6)
+    v0 = brute.var0_energy(N, g.J)
+    T = 20.0
+    pt = oracle.PT(g, [T], n_reps=32, run_seed=4, swap_interval=1000000, resync_interval=0,
+                   measure_start=200, measure_interval=2)
+    pt.run(3200)
+    mean = pt.acc["e_sum"][0] / pt.acc["e_n"][0]
+    var = pt.acc["e_sq"][0] / pt.acc["e_n"][0] - mean ** 2
+    assert var == pytest.approx(v0, rel=0.05)
+    err = math.sqrt(v0 / pt.acc["e_n"][0]) * 3.0
+    assert mean == pytest.approx(-v0 / T, abs=4 * err + 0.05 * v0 / T)
