@@ -388,6 +388,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
 // longer than 32 * kShortSlots entries.
 constexpr int kShortSlots = 4;
 
+// workgroup barrier that waits for LDS operations only (s_waitcnt lgkmcnt(0)
+// with vmcnt and expcnt at their maxima, 0xC07F): global loads issued before
+// it stay in flight.  Only for loops whose global memory traffic is loads.
+__device__ inline void block_sync_lds() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // keep the compiler from moving LDS accesses across a write by one lane that
 // all lanes then read (the hardware runs one wave's LDS accesses in order);
 // emits no wait, so global loads in flight stay in flight
@@ -714,6 +724,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
     const int64_t pair_stream = sh.shared_pairs ? (int64_t)it.sample : (int64_t)c;
     const int64_t sweep0 = P.counters->sweeps_done;
     const uint32_t* ps = P.pair_start + sd.pair_base;
+    const uint32_t pfirst = ps[0];  // the sample's first pair-list entry
 
     // wave 0 keeps the next step's pair-list entries in registers
     uint32_t pv[kPairPrefetch];
@@ -728,7 +739,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
             // amplitudes read are this copy's), masked out where it is used
             // (nothing here waits for the loads)
             const uint32_t e = r.x + (uint32_t)(lane + 64 * i);
-            const uint32_t es = e < r.y ? e : ps[0];
+            const uint32_t es = e < r.y ? e : pfirst;
             pin |= (e < r.y ? 1u : 0u) << i;
             pv[i] = P.pidx[es];
             pj[i] = P.pJ[es];
@@ -794,7 +805,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
                     }
                 }
             }
-            __syncthreads();
+            block_sync_lds();
             const bool acc_s = active && flag[s & 1];
             if (acc_s) {  // a_j new, a_k old in LDS: field changes of every target
                 const R2<R> dj = snap[0], dk = snap[1];
@@ -815,7 +826,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
                     }
                 }
             }
-            if (!lone || acc_s) __syncthreads();
+            if (!lone || acc_s) block_sync_lds();
             if (active && gt == 0) {
                 if (acc_s) a[k] = akn;
                 if (s + 1 < steps) prepare(s + 1);
