@@ -237,6 +237,31 @@ def cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies,
         f"({out['cached_fields']['speedup_vs_streaming']:.2f}x streaming)")
 
 
+def sparse_graphs(args, rlpt, torch, temps, out, N=1024, z=32):
+    """Sparse mode-locked graphs (finite connectivity, c = z N / 4 matched
+    terms per sample) with the ladder and copies of the headline workload:
+    the one-wave-per-copy short-list sweep, latency-bound."""
+    S, T, reps = args.samples, args.temps, args.reps
+    graphs = [rlpt.Graph(N, SEED_BASE + 900 + mu, mean_degree=z) for mu in range(S)]
+    ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1,
+                       resync_interval=100, measure_start=args.warmup, measure_interval=1, n_bins=100)
+    ctx.init(1)
+    ctx.sweep(args.warmup)
+    torch.cuda.synchronize()
+    ctx.sweep_timing(True)
+    t0 = time.perf_counter()
+    ctx.sweep(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.check()
+    kms, launches = ctx.sweep_time()
+    out["sparse_graph"] = {"n_modes": N, "mean_degree": z, "terms_per_sample": z * N // 4,
+                           "copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.steps / el,
+                           "ms_per_launch": kms / launches, "sweeps_per_s": args.steps / el}
+    ctx.close()
+    log(f"sparse N={N} z={z}: {out['sparse_graph']['mode_updates_per_s']:.4g} mode-updates/s")
+
+
 def per_N_copies(per_N_count, T, reps):
     return per_N_count * T * reps
 
@@ -394,6 +419,7 @@ def main():
     # accepted step the gather blocks of j and k
     if not args.no_cached:
         cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out)
+        sparse_graphs(args, rlpt, torch, temps, out)
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature)", "estimator": "Sokal window c=6",
                "plain": tau_plain}

@@ -280,6 +280,21 @@ int rlpt_counters(rlpt_ctx* ctx, int64_t* sweeps_done, int64_t* swaps_done, int6
 int rlpt_get_state(rlpt_ctx* ctx, int32_t first_copy, int32_t n_copies, double* a);
 int rlpt_set_state(rlpt_ctx* ctx, int32_t first_copy, int32_t n_copies, const double* a);
 
+/* Checkpoint and resume (host file I/O, synchronous).  rlpt_checkpoint_save
+ * writes everything a run changes on the device: amplitudes, running and FP64
+ * energies, drift, the temperature permutation of every ladder, the cached
+ * fields (field_mode CACHED), all accumulators, histograms, series and
+ * counters, plus the run seed and the sweep and swap counts.
+ * rlpt_checkpoint_load restores them into a context created with the same
+ * graphs, ladder and configuration (checked by a fingerprint; RLPT_E_ARG
+ * otherwise, or for a truncated file), after which the run continues exactly
+ * as the saved one would have: same draws, same decisions, same bits.  The
+ * learned proposal's networks and training buffers are not included (use
+ * rlpt_mlp_get_params / rlpt_mlp_set_params).  Errors: RLPT_E_ARG (I/O,
+ * mismatch), RLPT_E_STATE (save before rlpt_init), RLPT_E_HIP. */
+int rlpt_checkpoint_save(rlpt_ctx* ctx, const char* path);
+int rlpt_checkpoint_load(rlpt_ctx* ctx, const char* path);
+
 /* Running energies E[n_copies], temperature index of each copy temp_of[n_copies]. */
 int rlpt_get_energies(rlpt_ctx* ctx, double* E, int32_t* temp_of);
 

@@ -4,6 +4,7 @@
 // graph replay of whole segments, observables read-back and host analysis.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -565,6 +566,33 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->ws = d_workspace;
     c->ws_bytes = workspace_bytes;
     c->sh.cached = cfg->field_mode == RLPT_FIELDS_CACHED ? 1 : 0;
+    c->layout = layout;
+    // everything a run changes, for checkpoints: amplitudes, energies, drift,
+    // temperature permutation, cached fields, accumulators and counters
+    c->state_regions = {{r.amp, r.E - r.amp}, {r.E, r.E64 - r.E}, {r.E64, r.drift - r.E64},
+                        {r.drift, r.temp_of - r.drift}, {r.temp_of, r.copy_at - r.temp_of},
+                        {r.copy_at, r.beta - r.copy_at}, {r.fields, r.ell_start - r.fields},
+                        {r.acc_begin, r.acc_end - r.acc_begin}};
+    {
+        uint64_t h = 1469598103934665603ull;  // FNV-1a over the samples' shapes and the ladder
+        auto mix = [&](uint64_t v) {
+            for (int b = 0; b < 8; ++b) {
+                h ^= (v >> (8 * b)) & 0xff;
+                h *= 1099511628211ull;
+            }
+        };
+        for (int s = 0; s < n_graphs; ++s) {
+            mix((uint64_t)graphs[s]->N);
+            mix((uint64_t)graphs[s]->n_terms());
+            mix(graphs[s]->seed);
+        }
+        for (int t = 0; t < cfg->n_temps; ++t) {
+            uint64_t bits;
+            memcpy(&bits, &temps[t], 8);
+            mix(bits);
+        }
+        c->fingerprint = h;
+    }
     c->sh.rho = cfg->rho == 2 ? 2 : 4;
     c->cfg.rho = c->sh.rho;
     // short lists (sparse graphs): every padded list fits in one wave's registers
@@ -1050,6 +1078,98 @@ int rlpt_tile_of(rlpt_ctx* c, int32_t* block_threads, int32_t* copies_per_block)
     if (block_threads) *block_threads = c->launch.block_threads;
     if (copies_per_block)
         for (int s = 0; s < c->S; ++s) copies_per_block[s] = c->tile_copies.count(c->N[s]) ? c->tile_copies[c->N[s]] : 1;
+    return RLPT_OK;
+}
+
+namespace {
+
+struct CkptHeader {
+    char magic[8];  // "RLPTCKP1"
+    int32_t version, S, T, reps, precision, rho, field_mode, layout, shared_pairs, n_regions;
+    uint64_t fingerprint, run_seed;
+    int64_t sweeps_done, swaps_done;
+};
+
+void ckpt_header(const rlpt_ctx* c, CkptHeader* h) {
+    memset(h, 0, sizeof(*h));
+    memcpy(h->magic, "RLPTCKP1", 8);
+    h->version = 1;
+    h->S = c->S;
+    h->T = c->T;
+    h->reps = c->reps;
+    h->precision = c->cfg.precision;
+    h->rho = c->sh.rho;
+    h->field_mode = c->cfg.field_mode;
+    h->layout = c->layout;
+    h->shared_pairs = c->cfg.shared_pairs;
+    h->n_regions = (int32_t)c->state_regions.size();
+    h->fingerprint = c->fingerprint;
+    h->run_seed = c->sh.run_seed;
+    h->sweeps_done = c->sweeps_done;
+    h->swaps_done = c->swaps_done;
+}
+
+}  // namespace
+
+int rlpt_checkpoint_save(rlpt_ctx* c, const char* path) {
+    if (!c || !path) return fail(RLPT_E_ARG, "NULL argument");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    CkptHeader h;
+    ckpt_header(c, &h);
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(RLPT_E_ARG, std::string("cannot open ") + path + " for writing");
+    bool ok = fwrite(&h, sizeof(h), 1, f) == 1;
+    unsigned char* b = static_cast<unsigned char*>(c->ws);
+    std::vector<unsigned char> buf;
+    for (const auto& reg : c->state_regions) {
+        const uint64_t n = reg.second;
+        buf.resize(n);
+        if (n && hipMemcpy(buf.data(), b + reg.first, n, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        ok = ok && fwrite(&n, sizeof(n), 1, f) == 1 && (n == 0 || fwrite(buf.data(), 1, n, f) == n);
+    }
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(RLPT_E_ARG, std::string("writing the checkpoint ") + path + " failed");
+    return RLPT_OK;
+}
+
+int rlpt_checkpoint_load(rlpt_ctx* c, const char* path) {
+    if (!c || !path) return fail(RLPT_E_ARG, "NULL argument");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(RLPT_E_ARG, std::string("cannot open ") + path);
+    CkptHeader h, mine;
+    ckpt_header(c, &mine);
+    std::vector<std::vector<unsigned char>> data;
+    const char* err = nullptr;
+    if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "RLPTCKP1", 8) != 0 || h.version != 1)
+        err = "not a checkpoint of this library";
+    else if (h.S != mine.S || h.T != mine.T || h.reps != mine.reps || h.precision != mine.precision ||
+             h.rho != mine.rho || h.field_mode != mine.field_mode || h.layout != mine.layout ||
+             h.shared_pairs != mine.shared_pairs || h.n_regions != mine.n_regions ||
+             h.fingerprint != mine.fingerprint)
+        err = "checkpoint of a different context (samples, terms, ladder or configuration)";
+    for (size_t i = 0; !err && i < c->state_regions.size(); ++i) {
+        uint64_t n = 0;
+        if (fread(&n, sizeof(n), 1, f) != 1 || n != c->state_regions[i].second) {
+            err = "checkpoint regions do not match this context";
+            break;
+        }
+        data.emplace_back(n);
+        if (n && fread(data.back().data(), 1, n, f) != n) err = "truncated checkpoint";
+    }
+    fclose(f);
+    if (err) return fail(RLPT_E_ARG, std::string(err) + ": " + path);
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    drop_graph(c);
+    unsigned char* b = static_cast<unsigned char*>(c->ws);
+    for (size_t i = 0; i < c->state_regions.size(); ++i)
+        if (!data[i].empty())
+            HIP_TRY(hipMemcpy(b + c->state_regions[i].first, data[i].data(), data[i].size(), hipMemcpyHostToDevice),
+                    "checkpoint upload");
+    c->sh.run_seed = h.run_seed;
+    c->sweeps_done = h.sweeps_done;
+    c->swaps_done = h.swaps_done;
+    c->inited = true;
     return RLPT_OK;
 }
 

@@ -35,6 +35,9 @@ struct rlpt_ctx {
     double* scratch = nullptr;            // hook / state-transfer buffer (doubles)
     size_t scratch_doubles = 0;
     int64_t amp_complex = 0;
+    std::vector<std::pair<size_t, size_t>> state_regions;  // (offset, bytes) saved by a checkpoint
+    uint64_t fingerprint = 0;                               // samples, terms and ladder of the context
+    int layout = 0;
     int64_t sweeps_done = 0, swaps_done = 0;
     bool inited = false;
     std::map<int, int> tile_copies;       // copies per workgroup for each N

@@ -666,7 +666,9 @@ __device__ inline void gather_slice(const DevPtrs<R>& P, const SampleDev& sd, in
 // the fields, the per-step pair-list ranges, d_j, d_k and the decision flag
 template <typename R>
 __host__ __device__ inline size_t group_bytes_cached(int max_N, int waves_per_block) {
-    const size_t extra = (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) + (size_t)(max_N / 2 + 1) * sizeof(uint2) + 16;
+    // fields, d_j and d_k, per-step pair-list ranges, flags, second part's sums
+    const size_t extra = (size_t)max_N * 2 * sizeof(R) + 4 * sizeof(R) + (size_t)(max_N / 2 + 1) * sizeof(uint2) + 16 +
+                         (size_t)max_N * 2 * sizeof(R);
     return (group_bytes<R>(max_N, waves_per_block) + extra + 15) & ~(size_t)15;
 }
 
@@ -686,9 +688,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
     const int nt = wpc * 64;
     const int gsel = active ? g : 0;
     const int ns = (N + 63) >> 6;
-    // field update of an accepted move: `parts` waves share each slice when
-    // the group has waves to spare
-    const int parts = max(1, wpc / ns);
+    // field update of an accepted move: two waves share each slice when the
+    // group has the waves to spare; the second leaves its sums in LDS and the
+    // first adds both in a fixed order (runs are bitwise reproducible)
+    const int parts = max(1, min(2, wpc / ns));
 
     unsigned char* base = smem + (size_t)gsel * group_bytes_cached<R>(max_N, kWaves);
     R2<R>* a = reinterpret_cast<R2<R>*>(base);
@@ -701,6 +704,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
     uint2* pr = reinterpret_cast<uint2*>(after);  // pair-list range of each step
     after += (size_t)(max_N / 2 + 1) * sizeof(uint2);
     int* flag = reinterpret_cast<int*>(after);  // decisions of even and odd steps
+    after += 16;
+    R2<R>* pbuf = reinterpret_cast<R2<R>*>(after);  // second part's field changes
 
     int c = it.first_copy + gsel;
     if (sh.by_slot) {  // slot order within the sample: temperature descending, then ladder
@@ -807,6 +812,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
             }
             block_sync_lds();
             const bool acc_s = active && flag[s & 1];
+            R acc_r = 0, acc_i = 0;
             if (acc_s) {  // a_j new, a_k old in LDS: field changes of every target
                 const R2<R> dj = snap[0], dk = snap[1];
                 const int part = gw / ns;
@@ -816,17 +822,30 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cached(DevPtrs<R> P, ShapeInfo 
                     gather_slice<R, LAYOUT>(P, sd, N, k, dk, sl, part, parts, lane, a, fr, fi);
                     const int l = 64 * sl + lane;
                     if (l < N) {
-                        if (parts == 1) {
+                        if (parts == 1) {  // the slice's only wave: add directly
                             F[2 * l] += fr;
                             F[2 * l + 1] += fi;
-                        } else {  // `parts` lanes add to each field: atomics, distinct targets per wave
-                            atomicAdd(&F[2 * l], fr);
-                            atomicAdd(&F[2 * l + 1], fi);
+                        } else if (part == 0) {  // one slice per wave when parts > 1
+                            acc_r = fr;
+                            acc_i = fi;
+                        } else {
+                            pbuf[l] = mk2<R>(fr, fi);
                         }
                     }
                 }
             }
             if (!lone || acc_s) block_sync_lds();
+            if (parts > 1) {  // first part adds its sums and the second's, then all wait
+                if (acc_s && gw < ns) {
+                    const int l = 64 * gw + lane;
+                    if (l < N) {
+                        const R2<R> v = pbuf[l];
+                        F[2 * l] += acc_r + v.x;
+                        F[2 * l + 1] += acc_i + v.y;
+                    }
+                }
+                if (!lone || acc_s) block_sync_lds();
+            }
             if (active && gt == 0) {
                 if (acc_s) a[k] = akn;
                 if (s + 1 < steps) prepare(s + 1);

@@ -35,7 +35,7 @@ EXPORTS = [
     "rlpt_mlp_set_params", "rlpt_mlp_get_params", "rlpt_mlp_set_pairs", "rlpt_mlp_harvest", "rlpt_mlp_train",
     "rlpt_mlp_forward", "rlpt_mlp_loss_grad", "rlpt_mlp_enable", "rlpt_mlp_move", "rlpt_mlp_stats",
     "rlpt_mlp_last_move", "rlpt_summarize", "rlpt_adaptive_ladder", "rlpt_window_means",
-]
+    "rlpt_checkpoint_save", "rlpt_checkpoint_load"]
 
 
 class RlptError(RuntimeError):
@@ -98,6 +98,8 @@ def lib() -> C.CDLL:
     P, i32, i64, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     sig = {
         "rlpt_abi_version": ([], C.c_int),
+        "rlpt_checkpoint_save": ([P, C.c_char_p], C.c_int),
+        "rlpt_checkpoint_load": ([P, C.c_char_p], C.c_int),
         "rlpt_last_error": ([], C.c_char_p),
         "rlpt_graph_build": ([P, P], C.c_int),
         "rlpt_graph_free": ([P], None),
@@ -391,6 +393,12 @@ class Context:
         E = np.zeros(self.n_copies)
         _check(lib().rlpt_energy_fp64(self._h, _ptr(E)))
         return E
+
+    def checkpoint_save(self, path: str):
+        _check(lib().rlpt_checkpoint_save(self._h, str(path).encode()))
+
+    def checkpoint_load(self, path: str):
+        _check(lib().rlpt_checkpoint_load(self._h, str(path).encode()))
 
     def local_fields(self, copy: int) -> np.ndarray:
         F = np.zeros(self.Ns[copy // self.R], dtype=np.complex128)
