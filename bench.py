@@ -262,6 +262,36 @@ def sparse_graphs(args, rlpt, torch, temps, out, N=1024, z=32):
     log(f"sparse N={N} z={z}: {out['sparse_graph']['mode_updates_per_s']:.4g} mode-updates/s")
 
 
+def ipr_comparison(args, rlpt, torch, out, Ns=(32, 64, 128), S=4, T=16, sweeps=1500):
+    """The constraint comparison of sec. IV (inverse participation ratios):
+    Y_2 = sum |a|^4 / (sum |a|^2)^2 at the coldest bath of a [0.25, 1.5] ladder,
+    for the smoothed-cubic constraint (rho = 4) and the spherical one (rho = 2),
+    on complete mode-locked graphs of growing N.  N Y_2 stays O(1) when the
+    intensity is spread over all modes and grows with N when a few modes hold
+    a finite fraction of it."""
+    temps = 0.25 * (1.5 / 0.25) ** (np.arange(T) / (T - 1))
+    res = {}
+    for rho in (4, 2):
+        row = {}
+        for N in Ns:
+            graphs = [rlpt.Graph(N, SEED_BASE + 800 + 10 * N + mu) for mu in range(S)]
+            ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=2, precision=rlpt.FP32, swap_interval=1,
+                               resync_interval=100, measure_start=sweeps // 2, measure_interval=1, n_bins=50,
+                               rho=rho)
+            ctx.init(3)
+            ctx.sweep(sweeps)
+            ctx.check()
+            o = ctx.observables()
+            y2 = o["y2_sum"][:, 0] / o["e_n"][:, 0]
+            row[str(N)] = {"Y2": float(y2.mean()), "N_Y2": float(N * y2.mean()),
+                           "N_Y2_err": float(N * y2.std(ddof=1) / np.sqrt(S))}
+            ctx.close()
+        res[f"rho{rho}"] = row
+    out["ipr_rho4_vs_rho2"] = {"temperature": float(temps[0]), "samples": S, "sweeps": sweeps, **res}
+    log("IPR comparison: " + ", ".join(f"rho{r} N={N}: N*Y2={res[f'rho{r}'][str(N)]['N_Y2']:.2f}"
+                                       for r in (4, 2) for N in Ns))
+
+
 def per_N_copies(per_N_count, T, reps):
     return per_N_count * T * reps
 
@@ -420,6 +450,7 @@ def main():
     if not args.no_cached:
         cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out)
         sparse_graphs(args, rlpt, torch, temps, out)
+        ipr_comparison(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature)", "estimator": "Sokal window c=6",
                "plain": tau_plain}
