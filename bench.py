@@ -61,7 +61,11 @@ def traffic_for_current_kernel(launch_bytes_alg: float):
 
 PROFILE_CMDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kt -o kt -- python bench.py --steps 20 --warmup 5 "
-          "--tau-sweeps 0 --no-cpu-baseline",
+          "--tau-sweeps 0 --no-cpu-baseline --no-cached",
+    "kta": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kta -o kta -- python bench.py --steps 100 "
+           "--warmup 300 --tau-sweeps 100 --no-cpu-baseline",
+    "ktb": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/ktb -o ktb -- python bench.py --workload batched "
+           "--steps 50",
     "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d gpurun_out/pmc_{C} -o pmc -- python bench.py "
            "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
     "cal": "rocprofv3 --pmc {C} -f csv -d gpurun_out/cal_{C} -o cal -- python bench.py --copy-calibration",
@@ -82,7 +86,8 @@ def summarize_profiles(d):
         return sum(vals) / len(vals), len(vals)
 
     stats = rows(os.path.join(d, "kt", "kt_kernel_stats.csv"))
-    lines = ["# rocprofv3 kernel statistics, plain PT N=256 bench workload (8 samples x 40 T x 2 replicas)",
+    lines = ["# rocprofv3 kernel statistics, headline N=256 workload (8 samples x 40 T x 2 replicas, streaming sweep, "
+             "per-copy pairs)",
              "# command (from the repository root on the GPU box):",
              "#   " + PROFILE_CMDS["kt"], "",
              f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
@@ -115,6 +120,26 @@ def summarize_profiles(d):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", "sweep_n256_kernel_stats.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    other = (("kta", "bench_all_kernel_stats.txt",
+              "N=256 bench with every variant after 300 warm-up sweeps: streaming and cached-field sweeps, shared "
+              "pairs, learned proposal (harvest, training, moves), the sparse N=1024 run and the IPR comparison "
+              "(k_sweep<float, 256, 2> here also covers the shared-pair and small-N IPR launches)"),
+             ("ktb", "batched_kernel_stats.txt",
+              "batched uneven-N workload (N in {32,48,64,96,128} x 32 samples x 32 T x 2 replicas, 10-sweep "
+              "HIP-graph segments, built-in then tuned tiles, autotuner trials)"))
+    for tag, fname, title in other:
+        path = os.path.join(d, tag, tag + "_kernel_stats.csv")
+        if not os.path.exists(path):
+            continue
+        bl = ["# rocprofv3 kernel statistics, " + title, "# command (from the repository root on the GPU box):",
+              "#   " + PROFILE_CMDS[tag], "",
+              f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+        for r in rows(path):
+            name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
+            bl.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                      f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
+        with open(os.path.join(ROOT, "profiles", fname), "w") as f:
+            f.write("\n".join(bl) + "\n")
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(traffic, f, indent=1)
     print("\n".join(lines))

@@ -381,12 +381,14 @@ __global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, Shap
     }
 }
 
-// energy change H(a') - H(a) over the by-term list, FP32 (one block per item)
+// energy change H(a') - H(a) over the by-term list, FP32: kEnergyParts
+// workgroups per item, each over a contiguous range of terms (enough
+// workgroups to fill the chip), partial sums added in a fixed order after
 __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
     __shared__ float2 s0[kMaxModes];
     __shared__ float2 s1[kMaxModes];
     __shared__ float red[4];
-    const int net = blockIdx.y, b = blockIdx.x;
+    const int net = blockIdx.y, b = blockIdx.x / kEnergyParts, part = blockIdx.x % kEnergyParts;
     const int N = M.N;
     const int64_t item = (int64_t)net * M.Bm + b;
     const int c = M.item_copy[item];
@@ -401,8 +403,9 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
     const SampleDev sd = P.samples[mu];
     const ushort4* Q = P.quads + sd.quad_base;
     const double* Jq = P.Jq + sd.quad_base;
+    const int64_t q0 = sd.n_quads * part / kEnergyParts, q1 = sd.n_quads * (part + 1) / kEnergyParts;
     float acc = 0.0f;
-    for (int64_t q = threadIdx.x; q < sd.n_quads; q += blockDim.x) {
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const ushort4 t = Q[q];
         const float J = (float)Jq[q];
         float2 p = s0[t.x], s = s0[t.y], m = s0[t.z], n = s0[t.w];
@@ -418,7 +421,16 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
     acc = wsum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) M.dE[item] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) M.dEp[item * kEnergyParts + part] = red[0] + red[1] + red[2] + red[3];
+}
+
+// the parts of every item's energy change, added in order
+__global__ void k_energy_sum(MlpDev M, int n_items) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= n_items) return;
+    float s = 0.0f;
+    for (int p = 0; p < kEnergyParts; ++p) s += M.dEp[(int64_t)item * kEnergyParts + p];
+    M.dE[item] = s;
 }
 
 __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
@@ -575,7 +587,11 @@ hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo
 }
 
 hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_change, dim3(M.Bm, M.nets), dim3(256), 0, st, M, P, sh);
+    hipLaunchKernelGGL(k_energy_change, dim3(M.Bm * kEnergyParts, M.nets), dim3(256), 0, st, M, P, sh);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = M.Bm * M.nets;
+    hipLaunchKernelGGL(k_energy_sum, dim3((n + 63) / 64), dim3(64), 0, st, M, n);
     return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@
 
 namespace rlpt {
 
+constexpr int kEnergyParts = 32;  // workgroups sharing one learned move's energy change
+
 struct MlpDev {
     int32_t nets, N, In, H, K, D, Out;
     int32_t Bm;      // inference items per net (samples x replicas)
@@ -40,6 +42,7 @@ struct MlpDev {
     float* lqf;      // [nets][Bm] forward log density
     float* dref;     // [nets][Bm] log reference-density ratio
     float* dE;       // [nets][Bm] energy change
+    float* dEp;      // [nets][Bm][kEnergyParts] partial energy changes (term ranges)
     float* la;       // [nets][Bm] log acceptance ratio
     int32_t* item_copy;  // [nets][Bm]
     // training

@@ -68,6 +68,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.lqf = f(n * Bm);
     m.dref = f(n * Bm);
     m.dE = f(n * Bm);
+    m.dEp = f(n * Bm * kEnergyParts);
     m.la = f(n * Bm);
     m.item_copy = (int32_t*)f(n * Bm);
     m.tX = f(n * Bt * m.In);
