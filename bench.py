@@ -60,22 +60,25 @@ def traffic_for_current_kernel(launch_bytes_alg: float):
 
 
 PROFILE_CMDS = {
-    "kt": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kt -o kt -- python bench.py --steps 20 --warmup 5 "
+    "kt": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kt -o kt -- python bench.py --steps 20 --warmup 5 "
           "--tau-sweeps 0 --no-cpu-baseline --no-cached",
-    "kta": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/kta -o kta -- python bench.py --steps 100 "
+    "kta": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kta -o kta -- python bench.py --steps 100 "
            "--warmup 300 --tau-sweeps 100 --no-cpu-baseline",
-    "ktb": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/ktb -o ktb -- python bench.py --workload batched "
+    "ktb": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/ktb -o ktb -- python bench.py --workload batched "
            "--steps 50",
-    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d gpurun_out/pmc_{C} -o pmc -- python bench.py "
+    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmc_{C} -o pmc -- python bench.py "
            "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
-    "cal": "rocprofv3 --pmc {C} -f csv -d gpurun_out/cal_{C} -o cal -- python bench.py --copy-calibration",
+    "cal": "rocprofv3 --pmc {C} -f csv -d {OUT}/cal_{C} -o cal -- python bench.py --copy-calibration",
 }
 
 
 def summarize_profiles(d):
-    """Turn the rocprofv3 CSVs of the commands above (under directory d) into
-    profiles/sweep_n256_kernel_stats.txt and profiles/sweep_n256_traffic.json."""
+    """Turn the rocprofv3 CSVs of the commands above (written under directory d,
+    run from the repository root) into the summaries under profiles/."""
     import csv
+
+    def cmd(tag, counter=""):
+        return PROFILE_CMDS[tag].format(OUT=os.path.relpath(d, ROOT) if os.path.isabs(d) else d, C=counter)
 
     def rows(path):
         with open(path) as f:
@@ -88,8 +91,8 @@ def summarize_profiles(d):
     stats = rows(os.path.join(d, "kt", "kt_kernel_stats.csv"))
     lines = ["# rocprofv3 kernel statistics, headline N=256 workload (8 samples x 40 T x 2 replicas, streaming sweep, "
              "per-copy pairs)",
-             "# command (from the repository root on the GPU box):",
-             "#   " + PROFILE_CMDS["kt"], "",
+             "# command (from the repository root):",
+             "#   " + cmd("kt"), "",
              f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
     for r in stats:
         name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
@@ -110,8 +113,8 @@ def summarize_profiles(d):
                "copy_kernel_fetch_kib": cal_f, "copy_kernel_write_kib": cal_w, "copy_bytes": copy_bytes,
                "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
                "avg_duration_ns_kernel_trace": float(sweep["AverageNs"]),
-               "commands": [PROFILE_CMDS["pmc"].format(C="FETCH_SIZE"), PROFILE_CMDS["pmc"].format(C="WRITE_SIZE"),
-                            PROFILE_CMDS["cal"].format(C="FETCH_SIZE"), PROFILE_CMDS["cal"].format(C="WRITE_SIZE")]}
+               "commands": [cmd("pmc", "FETCH_SIZE"), cmd("pmc", "WRITE_SIZE"), cmd("cal", "FETCH_SIZE"),
+                            cmd("cal", "WRITE_SIZE")]}
     lines += ["", "# HBM traffic of k_sweep per dispatch (rocprofv3 --pmc, one counter per run):",
               f"#   FETCH_SIZE {fetch_kib:.0f} KiB x {f_scale:.4f} (copy-kernel scale) + WRITE_SIZE {write_kib:.0f} KiB "
               f"x {w_scale:.4f} = {hbm / 1e9:.3f} GB per launch",
@@ -131,8 +134,8 @@ def summarize_profiles(d):
         path = os.path.join(d, tag, tag + "_kernel_stats.csv")
         if not os.path.exists(path):
             continue
-        bl = ["# rocprofv3 kernel statistics, " + title, "# command (from the repository root on the GPU box):",
-              "#   " + PROFILE_CMDS[tag], "",
+        bl = ["# rocprofv3 kernel statistics, " + title, "# command (from the repository root):",
+              "#   " + cmd(tag), "",
               f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
         for r in rows(path):
             name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
@@ -354,7 +357,7 @@ def main():
         summarize_profiles(args.summarize_profiles)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (disorder samples would shard "
+        print("bench.py measures one GPU: the library has no multi-GPU path (disorder samples would shard "
               "across GPUs, see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
