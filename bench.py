@@ -320,6 +320,34 @@ def ipr_comparison(args, rlpt, torch, out, Ns=(32, 64, 128), S=4, T=16, sweeps=1
                                        for r in (4, 2) for N in Ns))
 
 
+def n64_configuration(args, rlpt, torch, out):
+    """The N = 64 configuration (8 samples x 24 temperatures geometric in
+    [0.3, 1.5] x 2 replicas, FP32, recomputation every 100 sweeps): lists of
+    about 1.3 K entries per mode stay in L2, so the sweep is bound by the
+    latency of a two-mode step, not by HBM."""
+    N, S, T = 64, 8, 24
+    temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
+    graphs = [rlpt.Graph(N, SEED_BASE + 100 + mu) for mu in range(S)]
+    ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=2, precision=rlpt.FP32, swap_interval=1,
+                       resync_interval=100, measure_start=args.warmup, measure_interval=1, n_bins=100)
+    ctx.init(1)
+    ctx.sweep(args.warmup)
+    torch.cuda.synchronize()
+    ctx.sweep_timing(True)
+    t0 = time.perf_counter()
+    ctx.sweep(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.check()
+    kms, launches = ctx.sweep_time()
+    steps = N // 2
+    out["n64_configuration"] = {"copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.steps / el,
+                                "ms_per_launch": kms / launches,
+                                "us_per_two_mode_step": kms / launches * 1e3 / steps}
+    ctx.close()
+    log(f"N=64 configuration: {out['n64_configuration']['mode_updates_per_s']:.4g} mode-updates/s")
+
+
 def per_N_copies(per_N_count, T, reps):
     return per_N_count * T * reps
 
@@ -479,6 +507,7 @@ def main():
         cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out)
         sparse_graphs(args, rlpt, torch, temps, out)
         ipr_comparison(args, rlpt, torch, out)
+        n64_configuration(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature)", "estimator": "Sokal window c=6",
                "plain": tau_plain}
