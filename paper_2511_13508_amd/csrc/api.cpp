@@ -49,6 +49,36 @@ static Tile default_tile(int N) {
     return {256, 4};
 }
 
+// Few copies for the chip: a copy's sweep is a chain of dependent two-mode
+// steps, so with fewer than two workgroups per compute unit the launch is
+// bound by a step's latency. Spread the copies first (fewer per workgroup),
+// then give each copy more waves (a step's list is cut into shorter pieces).
+static void spread_tile(const std::map<int, int>& counts, int copies_per_sample, int block_max, int* block,
+                        std::map<int, int>* copies) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    auto n_blocks = [&]() {
+        int64_t n = 0;
+        for (const auto& nc : counts) {
+            const int cpw = std::max(1, std::min((*copies)[nc.first], *block / 64));
+            n += (int64_t)nc.second * ((copies_per_sample + cpw - 1) / cpw);
+        }
+        return n;
+    };
+    while (n_blocks() < 2 * (int64_t)cus) {
+        bool halved = false;
+        for (auto& kv : *copies)
+            if (kv.second > 1) {
+                kv.second /= 2;
+                halved = true;
+            }
+        if (!halved) break;
+    }
+    if (n_blocks() < 2 * (int64_t)cus && *block < block_max) *block = block_max;
+}
+
 // cached-field sweep: one copy per workgroup, two waves per 64-target slice
 // (an accepted move streams its gather blocks with twice the loads in flight)
 static Tile default_tile_cached(int N) {
@@ -686,6 +716,9 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
             block = cfg->block_threads > 0 ? cfg->block_threads : tile(c->max_N).block;
             for (const auto& nc : counts)
                 copies[nc.first] = cfg->copies_per_block > 0 ? cfg->copies_per_block : tile(nc.first).copies;
+            // the one-wave-per-copy path of short lists packs copies by itself
+            if (cfg->block_threads <= 0 && cfg->copies_per_block <= 0 && !c->sh.cached && !c->sh.short_lists)
+                spread_tile(counts, c->Rc, 512, &block, &copies);
         }
         rc = build_items(c, block, copies);
         if (rc) {
