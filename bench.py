@@ -149,19 +149,28 @@ def summarize_profiles(d):
 
 
 def cpu_baseline(N, temps, n_reps, budget_s, n_threads):
+    """The oracle on the host: whole sweeps of sample 0 for about budget_s on
+    n_threads threads, then the same on one thread (one copy per thread, so
+    the 1-thread figure is the per-core rate)."""
     from oracle import oracle as O
     og = O.Graph(N, SEED_BASE + 0)
-    pt = O.PT(og, temps, n_reps=n_reps, run_seed=1, sample=0, swap_interval=1, resync_interval=100,
-              measure_start=0, measure_interval=1, n_bins=100, n_threads=n_threads)
-    t0 = time.perf_counter()
-    sweeps = 0
-    while time.perf_counter() - t0 < budget_s:
-        pt.run(1)
-        sweeps += 1
-    el = time.perf_counter() - t0
-    return {"value": N * pt.R * sweeps / el, "unit": "mode-updates/s", "cores": n_threads, "kind": "oracle",
-            "sample": f"sample 0 of the workload: {pt.R} copies x {sweeps} whole sweeps "
-                      f"(N={N}, {og.n_terms} terms), FP64, {el:.1f} s"}
+
+    def rate(threads, budget):
+        pt = O.PT(og, temps, n_reps=n_reps, run_seed=1, sample=0, swap_interval=1, resync_interval=100,
+                  measure_start=0, measure_interval=1, n_bins=100, n_threads=threads)
+        t0 = time.perf_counter()
+        sweeps = 0
+        while time.perf_counter() - t0 < budget:
+            pt.run(1)
+            sweeps += 1
+        el = time.perf_counter() - t0
+        return N * pt.R * sweeps / el, f"{pt.R} copies x {sweeps} whole sweeps", el
+
+    v, what, el = rate(n_threads, budget_s)
+    v1, what1, el1 = rate(1, budget_s / 2)
+    return {"value": v, "unit": "mode-updates/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"sample 0 of the workload: {what} (N={N}, {og.n_terms} terms), FP64, {el:.1f} s",
+            "value_1_core": v1, "sample_1_core": f"{what1}, {el1:.1f} s"}
 
 
 def batched(args):
@@ -433,6 +442,11 @@ def main():
         ctx.sweep_timing(False)
         return el, kms, launches
 
+    def median_tau(series, t_idx, lo, m):
+        """per temperature index: median over samples of tau_int of series[mu, t, lo:m]"""
+        return np.array([float(np.median([rlpt.tau_int(series[mu, t, lo:m])[0] for mu in range(S)]))
+                         for t in t_idx])
+
     def tau_block(ctx, sweeps_per_s, t_idx, extra_sweeps):
         """continue extra_sweeps sweeps, then tau_int of E at the temperature
         indices t_idx from the series (first quarter discarded), median over samples"""
@@ -443,11 +457,9 @@ def main():
         m = int(o["e_n"][0, 0] / reps)
         m = min(m, series_len)
         lo = m // 4
-        tau = []
-        for t in t_idx:
-            tau.append(float(np.median([rlpt.tau_int(o["series_e"][mu, t, lo:m])[0] for mu in range(S)])))
-        tau = np.array(tau)
+        tau = median_tau(o["series_e"], t_idx, lo, m)
         return {"temperatures": [float(temps[t]) for t in t_idx], "tau_int_E": tau.round(2).tolist(),
+                "tau_int_q": median_tau(o["series_q"], t_idx, lo, m).round(2).tolist(),
                 "sweeps_per_s": sweeps_per_s, "eff_sweeps_per_s": (sweeps_per_s / (2 * tau)).round(3).tolist(),
                 "series_points": m - lo}
 
@@ -509,7 +521,8 @@ def main():
         ipr_comparison(args, rlpt, torch, out)
         n64_configuration(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
-        tau = {"observable": "E (energy of ladder 0 at each temperature)", "estimator": "Sokal window c=6",
+        tau = {"observable": "E (energy of ladder 0 at each temperature); tau_int_q: overlap q of the two "
+                             "replicas, same window", "estimator": "Sokal window c=6",
                "plain": tau_plain}
         # ------------------------------------------------------------ shared pair schedule
         if not args.shared_pairs:
@@ -547,11 +560,11 @@ def main():
             o = ctx.observables()
             m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds)
             lo = max(done - args.warmup, 0) + (m - max(done - args.warmup, 0)) // 4
-            tl = np.array([float(np.median([rlpt.tau_int(o["series_e"][mu, t, lo:m])[0] for mu in range(S)]))
-                           for t in t_learn])
+            tl = median_tau(o["series_e"], t_learn, lo, m)
             acc, tries = ctx.mlp_stats()
             sps3 = args.steps / el3
             tau["learned"] = {"temperatures": [float(temps[t]) for t in t_learn], "tau_int_E": tl.round(2).tolist(),
+                              "tau_int_q": median_tau(o["series_q"], t_learn, lo, m).round(2).tolist(),
                               "sweeps_per_s": sps3, "eff_sweeps_per_s": (sps3 / (2 * tl)).round(3).tolist(),
                               "series_points": m - lo, "move_acceptance": (acc / np.maximum(tries, 1)).round(4).tolist(),
                               "step_scale": args.learn_scale, "train_loss_first_last": [loss0.round(2).tolist(),
