@@ -13,7 +13,10 @@ coordinates on the constraint surface sum |a_k|^4 = N (eq. SmoothedCubic):
   prod w).
 network: features = Re/Im of a rotated so that a_0 is real and positive;
   h1 = SiLU(x W1 + b1), h2 = SiLU(h1 W2 + b2), o = h2 W3 + b3; weights rounded
-  to bfloat16 (round to nearest even), arithmetic in FP64 here.
+  to bfloat16 (round to nearest even); the precision policy (bfloat16 network,
+  FP32 accumulation) is read as bfloat16 operands of every matrix product, so
+  the inputs of each product (activations, and output gradients in training)
+  are rounded to bfloat16 too; everything else is FP64 here.
 proposal: a K-component diagonal Gaussian mixture over the displacement
   delta = (dy, dpsi) in R^(2N-1): weights softmax(o[:K]), means o[K:K+KD],
   widths sigma = smax * sigmoid(o[K+KD:]) with smax = 2 for y and pi/2 for
@@ -22,7 +25,8 @@ proposal: a K-component diagonal Gaussian mixture over the displacement
 acceptance: min(1, exp(-beta dH) rho(y')/rho(y) q(y,psi|y',psi')/q(y',psi'|y,psi)).
 training loss: the mean negative log-likelihood of observed displacements
   under the unwrapped mixture (any parameters give an exact proposal).
-Pins (tests/test_oracle_mlp.py): finite differences of the loss, the
+Pins (tests/test_oracle_mlp.py): finite differences of the loss (exact
+arithmetic, gemm_bf16=False; the rounding is an elementwise map), the
 single-Gaussian closed form, torch's bfloat16 rounding, the proposal density
 integrating to one, and the infinite-temperature closed forms of the chain.
 """
@@ -65,14 +69,18 @@ def silu(z):
     return z / (1.0 + np.exp(-z))
 
 
-def forward(params, X):
-    """params: dict W1 [2N,H], b1, W2 [H,H], b2, W3 [H,Out], b3 (weights used as given)."""
-    p1 = X @ params["W1"] + params["b1"]
+def forward(params, X, gemm_bf16=True):
+    """params: dict W1 [2N,H], b1, W2 [H,H], b2, W3 [H,Out], b3 (weights used as given).
+    gemm_bf16: round every matrix-product input to bfloat16 as the library's
+    matrix cores take it (products and sums stay exact here); False gives the
+    network in exact arithmetic."""
+    r = bf16_round if gemm_bf16 else (lambda v: v)
+    p1 = r(X) @ params["W1"] + params["b1"]
     h1 = silu(p1)
-    p2 = h1 @ params["W2"] + params["b2"]
+    p2 = r(h1) @ params["W2"] + params["b2"]
     h2 = silu(p2)
-    o = h2 @ params["W3"] + params["b3"]
-    return o, (X, p1, h1, p2, h2)
+    o = r(h2) @ params["W3"] + params["b3"]
+    return o, (X, p1, h1, p2, h2, gemm_bf16)
 
 
 def mixture(o: np.ndarray, N: int, K: int):
@@ -105,25 +113,28 @@ def nll_and_grad(o: np.ndarray, delta: np.ndarray, N: int, K: int):
 
 
 def backward(params, cache, dO):
-    X, p1, h1, p2, h2 = cache
-    grads = {"W3": h2.T @ dO, "b3": dO.sum(0)}
-    dh2 = dO @ params["W3"].T
+    """Parameter gradients of the network for output gradients dO, with the
+    matrix-product inputs rounded as in forward (bias gradients are plain sums)."""
+    X, p1, h1, p2, h2, gemm_bf16 = cache
+    r = bf16_round if gemm_bf16 else (lambda v: v)
+    grads = {"W3": r(h2).T @ r(dO), "b3": dO.sum(0)}
+    dh2 = r(dO) @ params["W3"].T
     s2 = 1.0 / (1.0 + np.exp(-p2))
     dp2 = dh2 * s2 * (1.0 + p2 * (1.0 - s2))
-    grads["W2"] = h1.T @ dp2
+    grads["W2"] = r(h1).T @ r(dp2)
     grads["b2"] = dp2.sum(0)
-    dh1 = dp2 @ params["W2"].T
+    dh1 = r(dp2) @ params["W2"].T
     s1 = 1.0 / (1.0 + np.exp(-p1))
     dp1 = dh1 * s1 * (1.0 + p1 * (1.0 - s1))
-    grads["W1"] = X.T @ dp1
+    grads["W1"] = r(X).T @ r(dp1)
     grads["b1"] = dp1.sum(0)
     return grads
 
 
-def loss_and_grads(params, a_before, a_after, N, K):
+def loss_and_grads(params, a_before, a_after, N, K, gemm_bf16=True):
     """Training loss on pairs of configurations and its parameter gradients."""
     X = features(a_before)
-    o, cache = forward(params, X)
+    o, cache = forward(params, X, gemm_bf16)
     delta = displacement(a_before, a_after)
     L, dO = nll_and_grad(o, delta, N, K)
     return L, backward(params, cache, dO)

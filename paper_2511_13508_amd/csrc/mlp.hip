@@ -1,5 +1,5 @@
-// Kernels of the learned global proposal (see mlp.hpp): batched GEMMs with
-// bfloat16 weights and FP32 accumulation, SiLU, the Gaussian-mixture head and
+// Kernels of the learned global proposal (see mlp.hpp): batched bfloat16
+// GEMMs on the matrix cores with FP32 accumulation, SiLU, the Gaussian-mixture head and
 // its gradient, Adam, and the three stages of an exact Metropolis-Hastings
 // global move (propose, energy change, accept).  Every launch covers all
 // networks (grid z = network).
@@ -45,7 +45,11 @@ __device__ inline float wrapf(float x) { return x - 2.0f * kPiF * ceilf((x - kPi
 
 // ------------------------------------------------------------------ GEMM
 // C[i][j] = act(sum_k A(i,k) B(k,j) + bias[j]), A(i,k) = A[i*as0 + k*as1],
-// B(k,j) = B[k*bs0 + j*bs1]; 64 x 64 tile per 256-thread block, 4 x 4 per thread.
+// B(k,j) = B[k*bs0 + j*bs1], on the matrix cores: both operands are rounded
+// to bfloat16 (nearest even; the weights already are) and staged in LDS, the
+// products accumulate in FP32 through v_mfma_f32_16x16x16_bf16.  A 256-thread
+// workgroup (4 waves) computes a BM x 64 tile; K advances 64 at a time, with
+// the next stage's global loads in flight while the current one is multiplied.
 template <typename TB>
 struct Gemm {
     const float* A;
@@ -62,61 +66,121 @@ struct Gemm {
     int M, N, K;
 };
 
-template <typename TB, int ACT>
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmN = 64;             // tile columns
+constexpr int kGemmK = 64;             // K per LDS stage
+constexpr int kGemmLd = kGemmK + 4;    // LDS row stride in bfloat16 elements (8-byte aligned rows)
+
+__device__ inline uint16_t bf16_bits(float x) { return f_to_bf16(x); }
+__device__ inline uint16_t bf16_bits(uint16_t x) { return x; }
+
+template <typename TB, int ACT, int BM>
 __global__ __launch_bounds__(256) void k_gemm(Gemm<TB> g) {
-    __shared__ float As[16][65];
-    __shared__ float Bs[16][65];
+    constexpr int GM = BM >= 32 ? BM / 32 : 1;  // waves along M
+    constexpr int GN = 4 / GM;                  // waves along N
+    constexpr int WM = BM / (16 * GM);          // 16 x 16 blocks per wave along M
+    constexpr int WN = kGemmN / (16 * GN);      // and along N
+    constexpr int AE = BM * kGemmK / 256;       // A elements per thread per stage
+    constexpr int BE = kGemmN * kGemmK / 256;   // B elements per thread per stage
+    __shared__ __align__(16) uint16_t As[BM][kGemmLd];      // [m][k]
+    __shared__ __align__(16) uint16_t Bs[kGemmN][kGemmLd];  // [n][k]
     const int net = blockIdx.z;
     const float* A = g.A + net * g.sA;
     const TB* B = g.B + net * g.sB;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    float acc[4][4] = {};
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * kGemmN;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm0 = (wave / GN) * WM * 16, wn0 = (wave % GN) * WN * 16;
+    const bool a_m_fast = g.as0 == 1;  // A contiguous along M (a transposed operand)
+    const bool b_n_fast = g.bs1 == 1;  // B contiguous along N
+    // element e of a stage -> (row, k) of the A tile and (k, column) of the B tile
+    auto a_rk = [&](int e, int& r, int& kk) {
+        if (a_m_fast) { r = e % BM; kk = e / BM; } else { kk = e % kGemmK; r = e / kGemmK; }
+    };
+    auto b_kc = [&](int e, int& kk, int& c) {
+        if (b_n_fast) { c = e % kGemmN; kk = e / kGemmN; } else { kk = e % kGemmK; c = e / kGemmK; }
+    };
+    uint16_t ra[AE], rb[BE];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = threadIdx.x + 256 * e;
-            const int r = idx >> 4, kk = idx & 15;
+        for (int i = 0; i < AE; ++i) {
+            int r, kk;
+            a_rk(threadIdx.x + 256 * i, r, kk);
             const int gi = m0 + r, gk = k0 + kk;
-            As[kk][r] = (gi < g.M && gk < g.K) ? A[(int64_t)gi * g.as0 + (int64_t)gk * g.as1] : 0.0f;
-            const int kb = idx >> 6, c = idx & 63;
-            const int gkb = k0 + kb, gj = n0 + c;
-            Bs[kb][c] = (gkb < g.K && gj < g.N) ? ld(B + (int64_t)gkb * g.bs0 + (int64_t)gj * g.bs1) : 0.0f;
+            ra[i] = (gi < g.M && gk < g.K) ? bf16_bits(A[(int64_t)gi * g.as0 + (int64_t)gk * g.as1]) : (uint16_t)0;
+        }
+#pragma unroll
+        for (int i = 0; i < BE; ++i) {
+            int kk, c;
+            b_kc(threadIdx.x + 256 * i, kk, c);
+            const int gk = k0 + kk, gj = n0 + c;
+            rb[i] = (gk < g.K && gj < g.N) ? bf16_bits(B[(int64_t)gk * g.bs0 + (int64_t)gj * g.bs1]) : (uint16_t)0;
+        }
+    };
+    f32x4 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += kGemmK) {
+#pragma unroll
+        for (int i = 0; i < AE; ++i) {
+            int r, kk;
+            a_rk(threadIdx.x + 256 * i, r, kk);
+            As[r][kk] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BE; ++i) {
+            int kk, c;
+            b_kc(threadIdx.x + 256 * i, kk, c);
+            Bs[c][kk] = rb[i];
         }
         __syncthreads();
+        if (k0 + kGemmK < g.K) load(k0 + kGemmK);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], b[4];
+        for (int kk = 0; kk < kGemmK; kk += 16) {
+            // operand layout of the 16x16x16 bf16 MFMA: lane l holds A[l % 16][4 (l / 16) + 0..3]
+            // and B[4 (l / 16) + 0..3][l % 16]; the result D[4 (l / 16) + v][l % 16] in slot v
+            const int q = kk + 4 * (lane >> 4), rr = lane & 15;
+            bf16x4 af[WM], bfr[WN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+            for (int i = 0; i < WM; ++i) af[i] = *reinterpret_cast<const bf16x4*>(&As[wm0 + 16 * i + rr][q]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+            for (int j = 0; j < WN; ++j) bfr[j] = *reinterpret_cast<const bf16x4*>(&Bs[wn0 + 16 * j + rr][q]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int gi = m0 + ty * 4 + i;
-        if (gi >= g.M) continue;
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int gj = n0 + tx * 4 + j;
-            if (gj >= g.N) continue;
-            const float v = acc[i][j] + (g.bias ? g.bias[net * g.sBias + gj] : 0.0f);
-            g.Cpre[net * g.sC + (int64_t)gi * g.N + gj] = v;
-            if (ACT) g.Cact[net * g.sC + (int64_t)gi * g.N + gj] = silu(v);
-        }
-    }
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = m0 + wm0 + 16 * i + 4 * (lane >> 4) + v;
+                const int gj = n0 + wn0 + 16 * j + (lane & 15);
+                if (gi >= g.M || gj >= g.N) continue;
+                const float x = acc[i][j][v] + (g.bias ? g.bias[net * g.sBias + gj] : 0.0f);
+                g.Cpre[net * g.sC + (int64_t)gi * g.N + gj] = x;
+                if (ACT) g.Cact[net * g.sC + (int64_t)gi * g.N + gj] = silu(x);
+            }
 }
 
 template <typename TB, int ACT>
 hipError_t gemm(const Gemm<TB>& g, int nets, hipStream_t st) {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nets);
-    hipLaunchKernelGGL((k_gemm<TB, ACT>), grid, dim3(256), 0, st, g);
+    if (g.M <= 16) {
+        dim3 grid((g.N + kGemmN - 1) / kGemmN, (g.M + 15) / 16, nets);
+        hipLaunchKernelGGL((k_gemm<TB, ACT, 16>), grid, dim3(256), 0, st, g);
+    } else {
+        dim3 grid((g.N + kGemmN - 1) / kGemmN, (g.M + 63) / 64, nets);
+        hipLaunchKernelGGL((k_gemm<TB, ACT, 64>), grid, dim3(256), 0, st, g);
+    }
     return hipGetLastError();
 }
 

@@ -176,3 +176,39 @@ def test_harvest_train_and_learned_pt_are_unbiased(oracle):
         rep.append((k, np.round(z, 2)))
     assert within4 == cells, rep
     assert within2 >= 0.9 * cells, rep
+
+
+def test_learned_rounds_replay_bitwise_in_hip_graphs():
+    """Sweeps with learned rounds captured in HIP graph segments and replayed
+    give bitwise the states, energies, observables and move counts of the same
+    sweeps enqueued one by one (the learned kernels draw from a device move
+    counter, so a replay advances the chain)."""
+    N, S, T, reps = 16, 2, 4, 2
+    temps = synth.geometric_temps(0.5, 1.5, T)
+    graphs = [rlpt.Graph(N, SEED3 + 70 + i) for i in range(S)]
+    ctxs = []
+    for _ in range(2):
+        ctx = make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=2, mlp_hidden=32,
+                       mlp_components=2, mlp_capacity=256, mlp_batch=64, swap_interval=2, resync_interval=10,
+                       measure_start=20, measure_interval=1, n_bins=16, series_len=64)
+        ctx.init(3)
+        ctx.sweep(20)
+        ctx.mlp_setup([1, 2], seed=5)
+        ctx.mlp_harvest(rounds=8, lag=1)
+        ctx.mlp_train(20, 1e-3)
+        ctx.mlp_enable(1, 0.3)
+        ctx.sweep(30 - ctx.counters()[0] % 10)  # to a multiple of 10 sweeps
+        ctxs.append(ctx)
+    c1, c2 = ctxs
+    c1.sweep(40)
+    for _ in range(4):
+        c2.run_graph(10, 1)
+    assert np.array_equal(c1.get_state(), c2.get_state())
+    assert np.array_equal(c1.energies()[0], c2.energies()[0])
+    o1, o2 = c1.observables(), c2.observables()
+    for f in o1:
+        assert np.array_equal(o1[f], o2[f]), f
+    a1, t1 = c1.mlp_stats()
+    a2, t2 = c2.mlp_stats()
+    assert np.array_equal(a1, a2) and np.array_equal(t1, t2) and np.all(t1 > 0)
+    assert c1.counters() == c2.counters()

@@ -52,18 +52,49 @@ def test_parameter_gradients_finite_differences(oracle):
     params = M.init_params(N, H, K, rng, out_scale=0.5)
     a = np.array([oracle.init_copy(N, 5, c) for c in range(6)])
     b = np.array([oracle.init_copy(N, 6, c) for c in range(6)])
-    L, grads = M.loss_and_grads(params, a, b, N, K)
+    L, grads = M.loss_and_grads(params, a, b, N, K, gemm_bf16=False)
     h = 1e-6
     for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
         flat = params[name].reshape(-1)
         for i in rng.choice(flat.size, 4, replace=False):
             old = flat[i]
             flat[i] = old + h
-            Lp, _ = M.loss_and_grads(params, a, b, N, K)
+            Lp, _ = M.loss_and_grads(params, a, b, N, K, gemm_bf16=False)
             flat[i] = old - h
-            Lm, _ = M.loss_and_grads(params, a, b, N, K)
+            Lm, _ = M.loss_and_grads(params, a, b, N, K, gemm_bf16=False)
             flat[i] = old
             assert grads[name].reshape(-1)[i] == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5, abs=1e-8), name
+
+
+def test_bf16_operands_are_the_exact_network_on_rounded_inputs(oracle):
+    """With bfloat16 matrix-product operands the forward equals the exact
+    network evaluated layer by layer on rounded inputs (written out here with
+    torch's bfloat16 conversion), and stays within bfloat16 resolution of the
+    exact network; the backward's weight gradients are the exact gradient's
+    products on rounded factors."""
+    import torch
+    N, H, K = 5, 24, 2
+    rng = np.random.default_rng(8)
+    params = M.rounded(M.init_params(N, H, K, rng, out_scale=0.5))
+    a = np.array([oracle.init_copy(N, 9, c) for c in range(7)])
+    X = M.features(a)
+
+    def tb(v):
+        return torch.tensor(v, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+    h1 = M.silu(tb(X) @ params["W1"] + params["b1"])
+    h2 = M.silu(tb(h1) @ params["W2"] + params["b2"])
+    ref = tb(h2) @ params["W3"] + params["b3"]
+    o, _ = M.forward(params, X)
+    np.testing.assert_allclose(o, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    o_exact, _ = M.forward(params, X, gemm_bf16=False)
+    assert np.max(np.abs(o - o_exact)) < 2e-2 * np.sqrt(np.mean(o_exact ** 2))
+    assert np.max(np.abs(o - o_exact)) > 0.0
+    b = np.array([oracle.init_copy(N, 10, c) for c in range(7)])
+    _, g = M.loss_and_grads(params, a, b, N, K)
+    _, g_exact = M.loss_and_grads(params, a, b, N, K, gemm_bf16=False)
+    for k in g:
+        assert np.linalg.norm(g[k] - g_exact[k]) <= 3e-2 * np.linalg.norm(g_exact[k]), k
 
 
 def test_coordinates_roundtrip_and_constraint(oracle):
