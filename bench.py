@@ -63,9 +63,11 @@ PROFILE_CMDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kt -o kt -- python bench.py --steps 20 --warmup 5 "
           "--tau-sweeps 0 --no-cpu-baseline --no-cached",
     "kta": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kta -o kta -- python bench.py --steps 100 "
-           "--warmup 300 --tau-sweeps 100 --no-cpu-baseline",
+           "--warmup 300 --tau-sweeps 100 --no-cpu-baseline --no-n64",
     "ktb": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/ktb -o ktb -- python bench.py --workload batched "
            "--steps 50",
+    "ktl": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/ktl -o ktl -- python bench.py --workload learned64 "
+           "--steps 2000",
     "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmc_{C} -o pmc -- python bench.py "
            "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
     "cal": "rocprofv3 --pmc {C} -f csv -d {OUT}/cal_{C} -o cal -- python bench.py --copy-calibration",
@@ -88,48 +90,56 @@ def summarize_profiles(d):
         vals = [float(r["Counter_Value"]) for r in rows(path) if kernel_pred(r["Kernel_Name"])]
         return sum(vals) / len(vals), len(vals)
 
-    stats = rows(os.path.join(d, "kt", "kt_kernel_stats.csv"))
-    lines = ["# rocprofv3 kernel statistics, headline N=256 workload (8 samples x 40 T x 2 replicas, streaming sweep, "
-             "per-copy pairs)",
-             "# command (from the repository root):",
-             "#   " + cmd("kt"), "",
-             f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
-    for r in stats:
-        name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
-        lines.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
-                     f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
-    sweep = [r for r in stats if "k_sweep<" in r["Name"]][0]
-    is_sweep = lambda n: "k_sweep<" in n  # noqa: E731
-    is_copy = lambda n: "copyBuffer" in n  # noqa: E731
-    fetch_kib, nf = mean_counter(os.path.join(d, "pmc_FETCH_SIZE", "pmc_counter_collection.csv"), is_sweep)
-    write_kib, nw = mean_counter(os.path.join(d, "pmc_WRITE_SIZE", "pmc_counter_collection.csv"), is_sweep)
-    cal_f, _ = mean_counter(os.path.join(d, "cal_FETCH_SIZE", "cal_counter_collection.csv"), is_copy)
-    cal_w, _ = mean_counter(os.path.join(d, "cal_WRITE_SIZE", "cal_counter_collection.csv"), is_copy)
-    copy_bytes = 512 * 1024 * 1024
-    f_scale, w_scale = copy_bytes / (cal_f * 1024), copy_bytes / (cal_w * 1024)
-    hbm = fetch_kib * 1024 * f_scale + write_kib * 1024 * w_scale
-    traffic = {"kernel": "k_sweep<float, 256>", "kernel_source_sha": kernel_sha(),
-               "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib, "dispatches": [nf, nw],
-               "copy_kernel_fetch_kib": cal_f, "copy_kernel_write_kib": cal_w, "copy_bytes": copy_bytes,
-               "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
-               "avg_duration_ns_kernel_trace": float(sweep["AverageNs"]),
-               "commands": [cmd("pmc", "FETCH_SIZE"), cmd("pmc", "WRITE_SIZE"), cmd("cal", "FETCH_SIZE"),
-                            cmd("cal", "WRITE_SIZE")]}
-    lines += ["", "# HBM traffic of k_sweep per dispatch (rocprofv3 --pmc, one counter per run):",
-              f"#   FETCH_SIZE {fetch_kib:.0f} KiB x {f_scale:.4f} (copy-kernel scale) + WRITE_SIZE {write_kib:.0f} KiB "
-              f"x {w_scale:.4f} = {hbm / 1e9:.3f} GB per launch",
-              f"#   over the kernel-trace average {float(sweep['AverageNs']) / 1e6:.3f} ms: "
-              f"{hbm / float(sweep['AverageNs']):.0f} GB/s"]
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", "sweep_n256_kernel_stats.txt"), "w") as f:
-        f.write("\n".join(lines) + "\n")
+    lines = []
+    have_headline = all(os.path.exists(os.path.join(d, x)) for x in ("kt", "pmc_FETCH_SIZE", "pmc_WRITE_SIZE",
+                                                                    "cal_FETCH_SIZE", "cal_WRITE_SIZE"))
+    if have_headline:
+        stats = rows(os.path.join(d, "kt", "kt_kernel_stats.csv"))
+        lines = ["# rocprofv3 kernel statistics, headline N=256 workload (8 samples x 40 T x 2 replicas, streaming sweep, "
+                 "per-copy pairs)",
+                 "# command (from the repository root):",
+                 "#   " + cmd("kt"), "",
+                 f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+        for r in stats:
+            name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
+            lines.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                         f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
+        sweep = [r for r in stats if "k_sweep<" in r["Name"]][0]
+        is_sweep = lambda n: "k_sweep<" in n  # noqa: E731
+        is_copy = lambda n: "copyBuffer" in n  # noqa: E731
+        fetch_kib, nf = mean_counter(os.path.join(d, "pmc_FETCH_SIZE", "pmc_counter_collection.csv"), is_sweep)
+        write_kib, nw = mean_counter(os.path.join(d, "pmc_WRITE_SIZE", "pmc_counter_collection.csv"), is_sweep)
+        cal_f, _ = mean_counter(os.path.join(d, "cal_FETCH_SIZE", "cal_counter_collection.csv"), is_copy)
+        cal_w, _ = mean_counter(os.path.join(d, "cal_WRITE_SIZE", "cal_counter_collection.csv"), is_copy)
+        copy_bytes = 512 * 1024 * 1024
+        f_scale, w_scale = copy_bytes / (cal_f * 1024), copy_bytes / (cal_w * 1024)
+        hbm = fetch_kib * 1024 * f_scale + write_kib * 1024 * w_scale
+        traffic = {"kernel": "k_sweep<float, 256>", "kernel_source_sha": kernel_sha(),
+                   "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib, "dispatches": [nf, nw],
+                   "copy_kernel_fetch_kib": cal_f, "copy_kernel_write_kib": cal_w, "copy_bytes": copy_bytes,
+                   "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
+                   "avg_duration_ns_kernel_trace": float(sweep["AverageNs"]),
+                   "commands": [cmd("pmc", "FETCH_SIZE"), cmd("pmc", "WRITE_SIZE"), cmd("cal", "FETCH_SIZE"),
+                                cmd("cal", "WRITE_SIZE")]}
+        lines += ["", "# HBM traffic of k_sweep per dispatch (rocprofv3 --pmc, one counter per run):",
+                  f"#   FETCH_SIZE {fetch_kib:.0f} KiB x {f_scale:.4f} (copy-kernel scale) + WRITE_SIZE {write_kib:.0f} KiB "
+                  f"x {w_scale:.4f} = {hbm / 1e9:.3f} GB per launch",
+                  f"#   over the kernel-trace average {float(sweep['AverageNs']) / 1e6:.3f} ms: "
+                  f"{hbm / float(sweep['AverageNs']):.0f} GB/s"]
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        with open(os.path.join(ROOT, "profiles", "sweep_n256_kernel_stats.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
     other = (("kta", "bench_all_kernel_stats.txt",
               "N=256 bench with every variant after 300 warm-up sweeps: streaming and cached-field sweeps, shared "
               "pairs, learned proposal (harvest, training, moves), the sparse N=1024 run and the IPR comparison "
               "(k_sweep<float, 256, 2> here also covers the shared-pair and small-N IPR launches)"),
              ("ktb", "batched_kernel_stats.txt",
               "batched uneven-N workload (N in {32,48,64,96,128} x 32 samples x 32 T x 2 replicas, 10-sweep "
-              "HIP-graph segments, built-in then tuned tiles, autotuner trials)"))
+              "HIP-graph segments, built-in then tuned tiles, autotuner trials)"),
+             ("ktl", "learned_n64_kernel_stats.txt",
+              "learned-proposal comparison at N=64 (8 samples x 24 T x 2 replicas): plain run, harvest of 10^5 "
+              "pairs per network, training (MFMA bfloat16 GEMMs), learned run with one round per sweep, "
+              "100-sweep HIP-graph segments"))
     for tag, fname, title in other:
         path = os.path.join(d, tag, tag + "_kernel_stats.csv")
         if not os.path.exists(path):
@@ -143,9 +153,10 @@ def summarize_profiles(d):
                       f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
         with open(os.path.join(ROOT, "profiles", fname), "w") as f:
             f.write("\n".join(bl) + "\n")
-    with open(TRAFFIC_FILE, "w") as f:
-        json.dump(traffic, f, indent=1)
-    print("\n".join(lines))
+    if have_headline:
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(traffic, f, indent=1)
+        print("\n".join(lines))
 
 
 def cpu_baseline(N, temps, n_reps, budget_s, n_threads):
@@ -357,6 +368,158 @@ def n64_configuration(args, rlpt, torch, out):
     log(f"N=64 configuration: {out['n64_configuration']['mode_updates_per_s']:.4g} mode-updates/s")
 
 
+def n64_physics(args, rlpt, torch, out, sweeps=100000):
+    """The N = 64 configuration run to its length: 10^5 sweeps in 100-sweep
+    HIP-graph segments, measurements over the second half (equilibration =
+    half the run, sec. III.B), FP64 recomputation every 100 sweeps.  Reports
+    per temperature the disorder averages with jackknife errors of the energy
+    per mode, the specific heat per mode, <q^2>, the overlap kurtosis, the
+    IPRs Y_2 and Y_4, the acceptance and swap rates, and the 100-bin P(q) at
+    the coldest bath, the specific-heat peak and the hottest bath."""
+    N, S, T = 64, 8, 24
+    temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
+    graphs = [rlpt.Graph(N, SEED_BASE + 100 + mu) for mu in range(S)]
+    half = sweeps // 2 // 100 * 100
+    ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=2, precision=rlpt.FP32, swap_interval=1,
+                       resync_interval=100, measure_start=half, measure_interval=1, n_bins=100)
+    ctx.init(2)
+    t0 = time.perf_counter()
+    ctx.run_graph(100, half // 100)
+    ctx.run_graph(100, (sweeps - half) // 100)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.check()
+    o = ctx.observables()
+    ctx.close()
+    sm = rlpt.summarize(o, N, temps)
+    h = o["hist"] / np.maximum(o["hist"].sum(axis=2, keepdims=True), 1)
+    pq = h.mean(axis=0)
+    pk = 2 + int(np.argmax(sm["cv"][2:T - 2]))
+    r = lambda v, d=4: np.round(np.asarray(v, dtype=float), d).tolist()  # noqa: E731
+    out["n64_physics"] = {
+        "sweeps": sweeps, "measured_sweeps": sweeps - half, "seconds": el, "sweeps_per_s": sweeps / el,
+        "temperatures": r(temps), "E_per_mode": r(sm["E"] / N), "E_per_mode_err": r(sm["E_err"] / N, 5),
+        "cv_per_mode": r(sm["cv"]), "cv_per_mode_err": r(sm["cv_err"]), "q2": r(sm["q2"]),
+        "kurtosis": r(sm["kurtosis"]), "Y2": r(sm["y2"], 5), "Y4": r(sm["y4"], 6), "acceptance": r(sm["acc_rate"]),
+        "swap_rate": r(sm["swap_rate"]),
+        "P_q": {"bins": 100, "range": [-1, 1], "at_T": {f"{temps[t]:.4f}": r(pq[t], 5) for t in (0, pk, T - 1)}},
+    }
+    log(f"N=64 physics: {sweeps} sweeps in {el:.1f} s, C_V peak at T={temps[pk]:.3f}")
+
+
+def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweeps=20000, warm=2000,
+                harvest_rounds=6250, train_steps=1000, reeq=5000):
+    """The learned-proposal configuration: N = 64, 8 samples x 24 temperatures
+    geometric in [0.3, 1.5] x 2 replicas.  A first plain run finds the peak of
+    the specific heat; networks (2N -> 256 -> 256 SiLU -> 4-component mixture)
+    at the n_nets temperatures around it are trained on 10^5 harvested pairs
+    each.  The comparison is two runs with one history: warm-up, harvest (its
+    sweeps run without swaps), reeq sweeps with swaps, then the measured
+    sweeps in 100-sweep HIP-graph segments; the learned run trains after the
+    harvest and makes one learned round per sweep from then on, the plain run
+    does not.  Reports tau_int of E and q at the learned temperatures,
+    effective sweeps/s learned / plain, and whether the energy and the overlap
+    histogram agree (paired jackknife over samples)."""
+    temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
+    graphs = [rlpt.Graph(N, 2511135080 + 300 + mu) for mu in range(S)]
+    start = warm + harvest_rounds * 2 + reeq
+
+    def run(learn_t, train):
+        cfg = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=100,
+                   measure_start=start, measure_interval=1, n_bins=100, series_len=sweeps,
+                   mlp_nets=len(learn_t), mlp_hidden=256, mlp_components=4,
+                   mlp_capacity=harvest_rounds * S * reps, mlp_batch=512)
+        ctx = rlpt.Context(graphs, temps, **cfg)
+        ctx.init(1)
+        ctx.sweep(warm)
+        ctx.mlp_setup(learn_t, seed=1)
+        t0 = time.perf_counter()
+        ctx.mlp_harvest(rounds=harvest_rounds, lag=2)
+        info = {}
+        if train:
+            l0 = ctx.mlp_train(1, 1e-3)
+            l1 = ctx.mlp_train(train_steps, 1e-3)
+            torch.cuda.synchronize()
+            info = {"harvest_and_train_s": time.perf_counter() - t0, "pairs_per_net": harvest_rounds * S * reps,
+                    "train_loss_first_last": [l0.round(2).tolist(), l1.round(2).tolist()]}
+            ctx.mlp_enable(1, args.learn_scale)
+        ctx.sweep(start - ctx.counters()[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run_graph(100, sweeps // 100)  # 100-sweep segments replayed as HIP graphs
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.check()
+        o = ctx.observables()
+        if train:
+            acc, tries = ctx.mlp_stats()
+            info["move_acceptance"] = (acc / np.maximum(tries, 1)).round(4).tolist()
+        ctx.close()
+        return o, sweeps / el, info
+
+    def peak_run():
+        ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1,
+                           resync_interval=100, measure_start=warm, measure_interval=1, n_bins=100)
+        ctx.init(3)
+        ctx.run_graph(100, warm // 100)
+        ctx.run_graph(100, sweeps // 100)
+        ctx.check()
+        cv = rlpt.summarize(ctx.observables(), N, temps)["cv"]
+        ctx.close()
+        return 2 + int(np.argmax(cv[2:T - 2]))  # interior maximum (the ladder's ends are not a peak)
+
+    def taus(o, t_idx):
+        m = min(int(o["e_n"][0, 0] / reps), sweeps)
+        lo = m // 10
+        return [np.array([float(np.median([rlpt.tau_int(o[k][mu, t, lo:m])[0] for mu in range(S)]))
+                          for t in t_idx]) for k in ("series_e", "series_q")]
+
+    def jk(v):
+        n = v.shape[0]
+        loo = (v.sum(axis=0) - v) / (n - 1)
+        return v.mean(axis=0), np.sqrt((n - 1) / n * ((loo - loo.mean(axis=0)) ** 2).sum(axis=0))
+
+    log("learned N=64: locating the C_V peak")
+    pk = peak_run()
+    t_learn = [t for t in range(pk - n_nets // 2, pk - n_nets // 2 + n_nets) if 0 <= t < T]
+    log(f"learned N=64: C_V peak at T={temps[pk]:.3f}; plain run with the harvest history")
+    op, sps_p, _ = run(t_learn, False)
+    log("learned N=64: learned run")
+    ol, sps_l, info = run(t_learn, True)
+    tEp, tqp = taus(op, t_learn)
+    tEl, tql = taus(ol, t_learn)
+    # the two runs share disorder, seed and history up to the first learned round: paired differences over samples
+    Ep, El = op["e_sum"] / op["e_n"], ol["e_sum"] / ol["e_n"]
+    dE, sE = jk(El - Ep)
+    zE = np.abs(dE) / np.maximum(sE, 1e-12)
+    hp = op["hist"] / np.maximum(op["hist"].sum(axis=2, keepdims=True), 1)
+    hl = ol["hist"] / np.maximum(ol["hist"].sum(axis=2, keepdims=True), 1)
+    dh, sh_ = jk(hl - hp)
+    mass = (hp.mean(axis=0) + hl.mean(axis=0)) > 1e-3
+    zq = np.abs(dh) / np.maximum(sh_, 1e-12)
+    effp_E, effl_E = sps_p / (2 * tEp), sps_l / (2 * tEl)
+    effp_q, effl_q = sps_p / (2 * tqp), sps_l / (2 * tql)
+    out["learned_n64"] = {
+        "config": f"N={N}, {S} samples x {T} temperatures [0.3, 1.5] x {reps} replicas, FP32; learned rounds "
+                  f"(1 per sweep, step scale {args.learn_scale}) at the {len(t_learn)} temperatures around the "
+                  f"C_V peak; both runs: {warm} warm-up, {harvest_rounds * 2} harvest (no swaps), {reeq} more sweeps, "
+                  f"then {sweeps} measured sweeps",
+        "temperatures": [float(temps[t]) for t in t_learn], "cv_peak_T": float(temps[pk]),
+        "plain": {"sweeps_per_s": sps_p, "tau_int_E": tEp.round(2).tolist(), "tau_int_q": tqp.round(2).tolist()},
+        "learned": {"sweeps_per_s": sps_l, "tau_int_E": tEl.round(2).tolist(), "tau_int_q": tql.round(2).tolist(),
+                    **info},
+        "learned_vs_plain_eff_E": (effl_E / effp_E).round(3).tolist(),
+        "learned_vs_plain_eff_q": (effl_q / effp_q).round(3).tolist(),
+        "agreement": {"E_diff_learned_minus_plain": dE.round(3).tolist(), "E_diff_err": sE.round(3).tolist(),
+                      "E_z_all_T": zE.round(2).tolist(), "E_within_2sigma": float(np.mean(zE <= 2)),
+                      "Pq_cells": int(mass.sum()), "Pq_within_2sigma": float(np.mean(zq[mass] <= 2)),
+                      "test": "paired jackknife over the 8 samples of (learned - plain)"},
+    }
+    log(f"learned N=64: eff ratio E {out['learned_n64']['learned_vs_plain_eff_E']}, "
+        f"E within 2 sigma {out['learned_n64']['agreement']['E_within_2sigma']:.2f}, "
+        f"P(q) within 2 sigma {out['learned_n64']['agreement']['Pq_within_2sigma']:.2f}")
+
+
 def per_N_copies(per_N_count, T, reps):
     return per_N_count * T * reps
 
@@ -381,12 +544,15 @@ def main():
     ap.add_argument("--learn-scale", type=float, default=0.05)
     ap.add_argument("--harvest-rounds", type=int, default=400)
     ap.add_argument("--train-steps", type=int, default=600)
+    ap.add_argument("--reeq", type=int, default=500, help="sweeps with swaps between harvest and the learned window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cached", action="store_true", help="skip the cached-field run")
+    ap.add_argument("--no-n64", action="store_true", help="skip the N=64 physics run and learned comparison")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
-    ap.add_argument("--workload", choices=["n256", "batched"], default="n256",
-                    help="n256: the headline configuration; batched: the uneven-N configuration with autotuning")
+    ap.add_argument("--workload", choices=["n256", "batched", "learned64"], default="n256",
+                    help="n256: the headline configuration; batched: the uneven-N configuration with autotuning; "
+                         "learned64: only the N=64 learned-proposal comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -404,6 +570,11 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         batched(args)
+        return
+    if args.workload == "learned64":
+        res = {}
+        learned_n64(args, rlpt, torch, res, sweeps=args.steps // 100 * 100 or 100)
+        print(json.dumps(res["learned_n64"]), flush=True)
         return
     if args.copy_calibration:
         n = 128 * 1024 * 1024  # 512 MiB of float32 read and 512 MiB written per copy
@@ -520,6 +691,10 @@ def main():
         sparse_graphs(args, rlpt, torch, temps, out)
         ipr_comparison(args, rlpt, torch, out)
         n64_configuration(args, rlpt, torch, out)
+        if not args.no_n64:
+            n64_physics(args, rlpt, torch, out)
+    if args.tau_sweeps > 0 and args.learn_temps and not args.no_n64:
+        learned_n64(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature); tau_int_q: overlap q of the two "
                              "replicas, same window", "estimator": "Sokal window c=6",
@@ -533,7 +708,7 @@ def main():
             ctx.close()
         # ------------------------------------------------------------ learned global moves
         if t_learn:
-            lcommon = dict(common, series_len=series_len + 2 * args.harvest_rounds)
+            lcommon = dict(common, series_len=series_len + 2 * args.harvest_rounds + args.reeq)
             ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, mlp_nets=len(t_learn),
                                mlp_hidden=256, mlp_components=4, mlp_capacity=8192, mlp_batch=512, **lcommon)
             ctx.init(1)
@@ -546,6 +721,8 @@ def main():
             loss = ctx.mlp_train(args.train_steps, 1e-3)
             t_train = time.perf_counter() - t0
             ctx.mlp_enable(1, args.learn_scale)
+            # the harvest ran without swaps: re-equilibrate with swaps and learned rounds before the window
+            ctx.sweep(args.reeq)
             done = ctx.counters()[0]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -558,7 +735,7 @@ def main():
             ctx.sweep(args.tau_sweeps)
             ctx.check()
             o = ctx.observables()
-            m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds)
+            m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds + args.reeq)
             lo = max(done - args.warmup, 0) + (m - max(done - args.warmup, 0)) // 4
             tl = median_tau(o["series_e"], t_learn, lo, m)
             acc, tries = ctx.mlp_stats()

@@ -351,9 +351,12 @@ int rlpt_observables(rlpt_ctx* ctx, rlpt_obs* out);
 /* two SiLU layers to a K-component diagonal Gaussian mixture over (dy, dpsi); */
 /* widths 2*sigmoid (y) and (pi/2)*sigmoid (psi), all scaled by step_scale;    */
 /* phases wrap.  Exact Metropolis-Hastings with the reference density          */
-/* prod w^(1/2) in (y, psi) (the flat measure of eq. ProbDistr).  Weights are  */
-/* bfloat16 in the GEMMs with FP32 accumulation and FP32 masters; training is */
-/* Adam on the mean negative log-likelihood of harvested displacements.       */
+/* prod w^(1/2) in (y, psi) (the flat measure of eq. ProbDistr).  Every matrix */
+/* product runs on the matrix cores with bfloat16 operands (weights; inputs   */
+/* rounded to nearest even) and FP32 accumulation; FP32 master weights;       */
+/* training is Adam on the mean negative log-likelihood of harvested          */
+/* displacements.  The harvest runs without swaps: sweep with swaps on again  */
+/* before measuring.                                                          */
 /* Random numbers: Philox keyed (run_seed, "LEARN") at (i, round, copy, 0).   */
 /* ------------------------------------------------------------------------ */
 

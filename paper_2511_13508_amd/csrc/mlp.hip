@@ -208,12 +208,8 @@ __global__ __launch_bounds__(64) void k_feat_current(MlpDev M, DevPtrs<float> P,
     const int c = P.copy_at[((int64_t)mu * sh.n_reps + r) * sh.n_temps + t];
     if (lane == 0) M.item_copy[net * M.Bm + b] = c;
     write_features(copy_amp(P, sh, M.N, c), M.N, M.X + ((int64_t)net * M.Bm + b) * M.In, lane);
-}
-
-__global__ __launch_bounds__(64) void k_feat_proposed(MlpDev M) {
-    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
-    const int64_t item = (int64_t)net * M.Bm + b;
-    write_features(M.ap + item * 2 * M.N, M.N, M.X + item * M.In, lane);
+    // the round's index for the move draws: the later kernels of the round read it minus one
+    if (net == 0 && b == 0 && lane == 0) *M.moves_done += 1;
 }
 
 // log w_k and phases of one configuration held in global memory
@@ -343,13 +339,23 @@ __global__ void k_silu_back(const float* dH, const float* P, float* dP, int64_t 
     }
 }
 
-__global__ void k_colsum(const float* Y, int rows, int cols, int64_t sY, float* out, int64_t sOut) {
+// column sums of Y [rows][cols] (bias gradients): 64 columns per 256-thread
+// block, four row slices per column summed in a fixed order
+__global__ __launch_bounds__(256) void k_colsum(const float* Y, int rows, int cols, int64_t sY, float* out,
+                                                int64_t sOut) {
+    __shared__ float part[4][64];
     const int net = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+    const int c = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += Y[net * sY + (int64_t)r * cols + j];
-    out[net * sOut + j] = s;
+    if (j < cols) {
+        const float* y = Y + net * sY + j;
+#pragma unroll 8
+        for (int r = slice; r < rows; r += 4) s += y[(int64_t)r * cols];
+    }
+    part[slice][c] = s;
+    __syncthreads();
+    if (slice == 0 && j < cols) out[net * sOut + j] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
 }
 
 __global__ void k_adam(MlpDev M, float lr, float c1, float c2) {
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, Shap
     const int N = M.N, K = M.K, D = M.D;
     const int64_t item = (int64_t)net * M.Bm + b;
     const int c = M.item_copy[item];
-    const int64_t move = *M.moves_done;
+    const int64_t move = *M.moves_done - 1;
     const float* O = M.Of + item * M.Out;
     const float* a = copy_amp(P, sh, N, c);
     // component
@@ -438,6 +444,8 @@ __global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, Shap
         ap[2 * k + 1] = A * sn;
     }
     dref = wsum(dref);
+    __syncthreads();  // ap complete: the network's input at the proposal (the current one's forward is done)
+    write_features(ap, N, M.X + item * M.In, lane);
     const float lq = log_mix(O, sdel, 1.0f, scale, N, K, D, lane);
     if (lane == 0) {
         M.lqf[item] = lq;
@@ -445,56 +453,78 @@ __global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, Shap
     }
 }
 
-// energy change H(a') - H(a) over the by-term list, FP32: kEnergyParts
-// workgroups per item, each over a contiguous range of terms (enough
-// workgroups to fill the chip), partial sums added in a fixed order after
-__global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
-    __shared__ float2 s0[kMaxModes];
-    __shared__ float2 s1[kMaxModes];
-    __shared__ float red[4];
-    const int net = blockIdx.y, b = blockIdx.x / kEnergyParts, part = blockIdx.x % kEnergyParts;
+// energy change H(a') - H(a) over the by-term list, FP32.  The learned items of
+// one sample (every network's temperature x replicas) share that sample's
+// list: a workgroup holds up to kEnergyItems of them (current and proposed
+// amplitudes in LDS) and streams a contiguous range of terms once for all of
+// them; kEnergyParts workgroups per item group fill the chip, and the parts
+// are added in a fixed order by the accept stage.
+constexpr int kEnergyItems = 8;
+
+__global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> P, ShapeInfo sh, int groups,
+                                                       int gsize) {
+    extern __shared__ float2 samp[];  // [ni][2][N]: current, proposed
+    __shared__ float red[4][kEnergyItems];
     const int N = M.N;
-    const int64_t item = (int64_t)net * M.Bm + b;
-    const int c = M.item_copy[item];
-    const int mu = c / sh.copies_per_sample;
-    const float* a = copy_amp(P, sh, N, c);
-    const float* ap = M.ap + item * 2 * N;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        s0[k] = make_float2(a[2 * k], a[2 * k + 1]);
-        s1[k] = make_float2(ap[2 * k], ap[2 * k + 1]);
+    const int part = blockIdx.x % kEnergyParts;
+    const int grp = (blockIdx.x / kEnergyParts) % groups;
+    const int mu = blockIdx.x / (kEnergyParts * groups);
+    const int per_sample = M.nets * sh.n_reps;
+    const int j0 = grp * gsize;
+    const int ni = per_sample - j0 < gsize ? per_sample - j0 : gsize;
+    auto item_of = [&](int i) -> int64_t {
+        const int j = j0 + i, net = j / sh.n_reps, r = j % sh.n_reps;
+        return (int64_t)net * M.Bm + (int64_t)mu * sh.n_reps + r;
+    };
+    for (int i = 0; i < ni; ++i) {
+        const int64_t item = item_of(i);
+        const float* a = copy_amp(P, sh, N, M.item_copy[item]);
+        const float* ap = M.ap + item * 2 * N;
+        float2* s0 = samp + (size_t)(2 * i) * N;
+        float2* s1 = s0 + N;
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            s0[k] = make_float2(a[2 * k], a[2 * k + 1]);
+            s1[k] = make_float2(ap[2 * k], ap[2 * k + 1]);
+        }
     }
     __syncthreads();
     const SampleDev sd = P.samples[mu];
     const ushort4* Q = P.quads + sd.quad_base;
     const double* Jq = P.Jq + sd.quad_base;
     const int64_t q0 = sd.n_quads * part / kEnergyParts, q1 = sd.n_quads * (part + 1) / kEnergyParts;
-    float acc = 0.0f;
+    float acc[kEnergyItems];
+#pragma unroll
+    for (int i = 0; i < kEnergyItems; ++i) acc[i] = 0.0f;
     for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const ushort4 t = Q[q];
         const float J = (float)Jq[q];
-        float2 p = s0[t.x], s = s0[t.y], m = s0[t.z], n = s0[t.w];
-        float cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
-        float dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
-        const float x0 = cr * dr - ci * di;
-        p = s1[t.x], s = s1[t.y], m = s1[t.z], n = s1[t.w];
-        cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
-        dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
-        const float x1 = cr * dr - ci * di;
-        acc += -2.0f * J * (x1 - x0);
+#pragma unroll
+        for (int i = 0; i < kEnergyItems; ++i) {
+            if (i >= ni) break;
+            const float2* s0 = samp + (size_t)(2 * i) * N;
+            const float2* s1 = s0 + N;
+            float2 p = s0[t.x], s = s0[t.y], m = s0[t.z], n = s0[t.w];
+            float cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
+            float dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
+            const float x0 = cr * dr - ci * di;
+            p = s1[t.x], s = s1[t.y], m = s1[t.z], n = s1[t.w];
+            cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
+            dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
+            const float x1 = cr * dr - ci * di;
+            acc[i] += -2.0f * J * (x1 - x0);
+        }
     }
-    acc = wsum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+#pragma unroll
+    for (int i = 0; i < kEnergyItems; ++i) {
+        if (i >= ni) break;
+        const float v = wsum(acc[i]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) M.dEp[item * kEnergyParts + part] = red[0] + red[1] + red[2] + red[3];
-}
-
-// the parts of every item's energy change, added in order
-__global__ void k_energy_sum(MlpDev M, int n_items) {
-    const int item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= n_items) return;
-    float s = 0.0f;
-    for (int p = 0; p < kEnergyParts; ++p) s += M.dEp[(int64_t)item * kEnergyParts + p];
-    M.dE[item] = s;
+    if (threadIdx.x < ni) {
+        const int i = threadIdx.x;
+        M.dEp[item_of(i) * kEnergyParts + part] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    }
 }
 
 __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
@@ -503,12 +533,14 @@ __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, Shape
     const int N = M.N, K = M.K, D = M.D;
     const int64_t item = (int64_t)net * M.Bm + b;
     const int c = M.item_copy[item];
-    const int64_t move = *M.moves_done;
+    const int64_t move = *M.moves_done - 1;
     for (int d = lane; d < D; d += 64) sdel[d] = M.delta[item * D + d];
     __syncthreads();
     const float lqr = log_mix(M.Or + item * M.Out, sdel, -1.0f, scale, N, K, D, lane);
+    float dE = 0.0f;  // the energy change's parts, added in order
+    for (int p = 0; p < kEnergyParts; ++p) dE += M.dEp[item * kEnergyParts + p];
     const float beta = P.beta[M.temp_index[net]];
-    const float la = -beta * M.dE[item] + M.dref[item] + lqr - M.lqf[item];
+    const float la = -beta * dE + M.dref[item] + lqr - M.lqf[item];
     const int nb = (D + 1) / 2;
     const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
     const double ua = uniform01<double>(wu.v[1]);
@@ -520,17 +552,15 @@ __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, Shape
     }
     if (lane == 0) {
         M.la[item] = la;
+        M.dE[item] = dE;
         if (accept) {
-            P.E[c] += M.dE[item];
+            P.E[c] += dE;
             atomicAdd(&M.acc[net], 1ull);
         }
         atomicAdd(&M.tries[net], 1ull);
     }
 }
 
-__global__ void k_moves_tick(int64_t* moves) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *moves += 1;
-}
 
 __global__ __launch_bounds__(64) void k_harvest(MlpDev M, DevPtrs<float> P, ShapeInfo sh, int which, int slot0) {
     const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
@@ -553,11 +583,6 @@ __global__ __launch_bounds__(64) void k_harvest(MlpDev M, DevPtrs<float> P, Shap
 
 hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
     hipLaunchKernelGGL(k_feat_current, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh);
-    return hipGetLastError();
-}
-
-hipError_t mlp_features_proposed(const MlpDev& M, hipStream_t st) {
-    hipLaunchKernelGGL(k_feat_proposed, dim3(M.Bm, M.nets), dim3(64), 0, st, M);
     return hipGetLastError();
 }
 
@@ -606,7 +631,7 @@ hipError_t mlp_backward(const MlpDev& M, hipStream_t st) {
         return gemm<float, 0>(g, M.nets, st);
     };
     auto bgrad = [&](const float* dY, int out, int64_t off) {
-        hipLaunchKernelGGL(k_colsum, dim3((out + 255) / 256, M.nets), dim3(256), 0, st, dY, B, out, (int64_t)B * out,
+        hipLaunchKernelGGL(k_colsum, dim3((out + 63) / 64, M.nets), dim3(256), 0, st, dY, B, out, (int64_t)B * out,
                            M.grad + off, M.NP);
         return hipGetLastError();
     };
@@ -651,19 +676,21 @@ hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo
 }
 
 hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_change, dim3(M.Bm * kEnergyParts, M.nets), dim3(256), 0, st, M, P, sh);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int n = M.Bm * M.nets;
-    hipLaunchKernelGGL(k_energy_sum, dim3((n + 63) / 64), dim3(64), 0, st, M, n);
+    // one N for every sample (checked at creation); Bm = samples x replicas
+    const int per_sample = M.nets * sh.n_reps;
+    const int fit = (int)(61440 / (2 * M.N * sizeof(float2)));  // items whose amplitudes fit 60 KiB of LDS
+    int gsize = kEnergyItems < fit ? kEnergyItems : fit;
+    gsize = gsize < per_sample ? gsize : per_sample;
+    const int groups = (per_sample + gsize - 1) / gsize;
+    const int samples = M.Bm / sh.n_reps;
+    const size_t lds = (size_t)gsize * 2 * M.N * sizeof(float2);
+    hipLaunchKernelGGL(k_energy_change, dim3((unsigned)(samples * groups * kEnergyParts)), dim3(256), lds, st, M, P,
+                       sh, groups, gsize);
     return hipGetLastError();
 }
 
 hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st) {
     hipLaunchKernelGGL(k_accept, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_moves_tick, dim3(1), dim3(64), 0, st, M.moves_done);
     return hipGetLastError();
 }
 

@@ -6,7 +6,7 @@
 // the alr intensity coordinates y_k = log(w_k / w_{N-1}), w = |a|^4 / N, and of
 // the phases; exact Metropolis-Hastings with the reference density
 // prod w^(1/2) in (y, psi).  Weights: FP32 master + bfloat16 copies used by
-// the GEMMs (FP32 accumulation).
+// the matrix-core GEMMs (bfloat16 operands, FP32 accumulation).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -62,7 +62,7 @@ struct MlpDev {
     int32_t* count;  // [nets] stored pairs
     unsigned long long* acc;    // [nets]
     unsigned long long* tries;  // [nets]
-    int64_t* moves_done;        // learned-move rounds (RNG counter)
+    int64_t* moves_done;        // learned-move rounds started (RNG counter; advanced by the round's first kernel)
 };
 
 struct MlpRun {
@@ -72,7 +72,6 @@ struct MlpRun {
 
 // all launchers enqueue on st and cover every net in one launch (grid z = net)
 hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
-hipError_t mlp_features_proposed(const MlpDev& M, hipStream_t st);
 hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int use_first, hipStream_t st);
 // forward of every net: inference (train = 0, from M.X into Of or Or) or training (from tX into tO)
 hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st);

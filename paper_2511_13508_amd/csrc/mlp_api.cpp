@@ -135,7 +135,6 @@ int mlp_enqueue_round(rlpt_ctx* c) {
     HIP_TRY2(mlp_forward(M, 0, 0, c->stream), "learned forward");
     HIP_TRY2(mlp_propose(M, c->pf, c->sh, s, c->stream), "learned propose");
     HIP_TRY2(mlp_energy_change(M, c->pf, c->sh, c->stream), "learned energy");
-    HIP_TRY2(mlp_features_proposed(M, c->stream), "learned features");
     HIP_TRY2(mlp_forward(M, 0, 1, c->stream), "learned forward");
     HIP_TRY2(mlp_accept(M, c->pf, c->sh, s, c->stream), "learned accept");
     if (c->sh.cached) HIP_TRY2(launch_fields_all(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, c->stream), "fields");
