@@ -374,8 +374,10 @@ def n64_physics(args, rlpt, torch, out, sweeps=100000):
     half the run, sec. III.B), FP64 recomputation every 100 sweeps.  Reports
     per temperature the disorder averages with jackknife errors of the energy
     per mode, the specific heat per mode, <q^2>, the overlap kurtosis, the
-    IPRs Y_2 and Y_4, the acceptance and swap rates, and the 100-bin P(q) at
-    the coldest bath, the specific-heat peak and the hottest bath."""
+    IPRs Y_2 and Y_4, the acceptance and swap rates, the 100-bin P(q) at
+    the coldest bath, the specific-heat peak and the hottest bath, and the
+    intensity spectrum (its spread over the frequency band per temperature and
+    its profile in 8 bands at those three baths)."""
     N, S, T = 64, 8, 24
     temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
     graphs = [rlpt.Graph(N, SEED_BASE + 100 + mu) for mu in range(S)]
@@ -395,6 +397,13 @@ def n64_physics(args, rlpt, torch, out, sweeps=100000):
     h = o["hist"] / np.maximum(o["hist"].sum(axis=2, keepdims=True), 1)
     pq = h.mean(axis=0)
     pk = 2 + int(np.argmax(sm["cv"][2:T - 2]))
+    # intensity spectrum I(omega_k) = <|a_k|^2> (modes in frequency order), normalised per sample and
+    # temperature to unit mean; its intensity-weighted spread in frequency rank measures the narrowing
+    spec = o["spectrum"] / o["e_n"][:, :, None]
+    spec = spec / spec.mean(axis=2, keepdims=True)
+    rank = (np.arange(N) + 0.5) / N
+    width = np.sqrt(np.sum(spec * (rank - 0.5) ** 2, axis=2) / np.sum(spec, axis=2))  # [S][T]
+    bands = spec.reshape(S, T, 8, N // 8).mean(axis=3).mean(axis=0)  # 8 frequency bands, sample mean
     r = lambda v, d=4: np.round(np.asarray(v, dtype=float), d).tolist()  # noqa: E731
     out["n64_physics"] = {
         "sweeps": sweeps, "measured_sweeps": sweeps - half, "seconds": el, "sweeps_per_s": sweeps / el,
@@ -403,6 +412,11 @@ def n64_physics(args, rlpt, torch, out, sweeps=100000):
         "kurtosis": r(sm["kurtosis"]), "Y2": r(sm["y2"], 5), "Y4": r(sm["y4"], 6), "acceptance": r(sm["acc_rate"]),
         "swap_rate": r(sm["swap_rate"]),
         "P_q": {"bins": 100, "range": [-1, 1], "at_T": {f"{temps[t]:.4f}": r(pq[t], 5) for t in (0, pk, T - 1)}},
+        "spectrum": {"width_in_frequency_rank": r(width.mean(axis=0)), "width_err": r(width.std(axis=0, ddof=1)
+                                                                                      / np.sqrt(S)),
+                     "flat_width": float(np.sqrt(1.0 / 12.0)),
+                     "bands_at_T": {f"{temps[t]:.4f}": r(bands[t]) for t in (0, pk, T - 1)},
+                     "note": "8 equal bands of frequency rank, intensity relative to the mode average"},
     }
     log(f"N=64 physics: {sweeps} sweeps in {el:.1f} s, C_V peak at T={temps[pk]:.3f}")
 

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define RLPT_ABI_VERSION 2
+#define RLPT_ABI_VERSION 3
 
 enum {
     RLPT_OK = 0,
@@ -337,6 +337,10 @@ typedef struct rlpt_obs {
     double* series_e;   /* [S][T][L] energy of ladder 0's copy at bath t, per measurement */
     double* series_q;   /* [S][T][L] overlap of ladders 0 and 1 at bath t, per measurement */
     double* hist_I;     /* [S][T][B] total intensity I/N = sum|a|^2 / N on [0, 1] (P(I), sec. II.B) */
+    double* spectrum;   /* [S][T][max N] sum over measurements and replicas of |a_k|^2, modes in   */
+                        /* frequency order: divide by e_n for the intensity spectrum I(omega_k)  */
+                        /* of sec. II.C (Fig. spectrum); rows of samples with smaller N are      */
+                        /* zero beyond their N                                                   */
 } rlpt_obs;
 
 /* Copy the accumulators to host (synchronises).  Returns RLPT_E_STATE if a

@@ -326,6 +326,7 @@ typedef struct {
     double* swap_acc; double* swap_tries;          /* [T-1] exchange acceptance */
     double* series_e; double* series_q;            /* [T][series_len] */
     double* hist_I;                                /* [T][n_bins] total intensity I/N on [0, 1] */
+    double* spectrum;                              /* [T][N] sum of |a_k|^2 over measurements and replicas */
     int64_t n_meas;
 } or_pt_accum;
 
@@ -584,6 +585,8 @@ static void measure(const or_pt_params* P, const or_pt_state* S, or_pt_accum* A)
                 s1 += I;
                 s2 += I * I;
                 s4 += I * I * I * I;
+                /* intensity spectrum I(omega_k) = <|a_k|^2> (sec. II.C), modes in frequency order */
+                A->spectrum[(size_t)t * N + k] += I;
             }
             A->e_n[t] += 1.0;
             A->e_sum[t] += S->E[c];

@@ -67,7 +67,7 @@ class PTState(C.Structure):
 
 
 _ACC_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist",
-               "acc", "tries", "swap_acc", "swap_tries", "series_e", "series_q", "hist_I"]
+               "acc", "tries", "swap_acc", "swap_tries", "series_e", "series_q", "hist_I", "spectrum"]
 
 
 class PTAccum(C.Structure):
@@ -213,7 +213,8 @@ class PT:
         self.temp_of = np.zeros(self.R, dtype=np.int32)
         self.S = PTState(a=_p(self.a).value, E=_p(self.E).value, temp_of=_p(self.temp_of).value)
         self.acc = {}
-        shapes = {"hist": (T, n_bins), "hist_I": (T, n_bins), "swap_acc": (max(T - 1, 1),), "swap_tries": (max(T - 1, 1),),
+        shapes = {"hist": (T, n_bins), "hist_I": (T, n_bins), "spectrum": (T, g.N),
+                  "swap_acc": (max(T - 1, 1),), "swap_tries": (max(T - 1, 1),),
                   "series_e": (T, max(series_len, 1)), "series_q": (T, max(series_len, 1))}
         for f in _ACC_FIELDS:
             self.acc[f] = np.zeros(shapes.get(f, (T,)), dtype=np.float64)

@@ -105,7 +105,7 @@ struct Layout {
 
 struct Regions {
     size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, pair_start, pidx, pJ, fields, ell_start, gidx16, gidx32, gJ, c0, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
-    size_t acc_begin, acc, swap_acc, obs, hist, hist_I, series_e, series_q, meas_cnt, counters, acc_end;
+    size_t acc_begin, acc, swap_acc, obs, hist, hist_I, spec, series_e, series_q, meas_cnt, counters, acc_end;
     size_t scratch, scratch_doubles, mlp, total;
 };
 
@@ -317,6 +317,7 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     r.obs = L.take(kNumObs * S * T * 8);
     r.hist = L.take(S * T * cfg.n_bins * 8);
     r.hist_I = L.take(S * T * cfg.n_bins * 8);
+    r.spec = L.take(S * T * (size_t)max_N * 8);
     r.series_e = L.take(S * T * std::max(cfg.series_len, 1) * 8);
     r.series_q = L.take(S * T * std::max(cfg.series_len, 1) * 8);
     r.meas_cnt = L.take(S * T * 4);
@@ -365,6 +366,7 @@ void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
     P.obs = reinterpret_cast<double*>(b + r.obs);
     P.hist = reinterpret_cast<double*>(b + r.hist);
     P.hist_I = reinterpret_cast<double*>(b + r.hist_I);
+    P.spec = reinterpret_cast<double*>(b + r.spec);
     P.series_e = reinterpret_cast<double*>(b + r.series_e);
     P.series_q = reinterpret_cast<double*>(b + r.series_q);
     P.meas_cnt = reinterpret_cast<int32_t*>(b + r.meas_cnt);
@@ -731,6 +733,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->sh.n_reps = c->reps;
     c->sh.copies_per_sample = c->Rc;
     c->sh.n_bins = cfg->n_bins;
+    c->sh.spec_stride = c->max_N;
     c->sh.series_len = cfg->series_len;
     c->sh.shared_pairs = cfg->shared_pairs;
     c->sh.layout = layout;
@@ -1075,6 +1078,9 @@ int rlpt_observables(rlpt_ctx* c, rlpt_obs* o) {
     if (o->hist_I)
         HIP_TRY(hipMemcpy(o->hist_I, f64 ? c->pd.hist_I : c->pf.hist_I, (size_t)ST * c->cfg.n_bins * 8,
                           hipMemcpyDeviceToHost), "read intensity hist");
+    if (o->spectrum)
+        HIP_TRY(hipMemcpy(o->spectrum, f64 ? c->pd.spec : c->pf.spec, (size_t)ST * c->max_N * 8,
+                          hipMemcpyDeviceToHost), "read spectrum");
     if (c->cfg.series_len > 0) {
         if (o->series_e)
             HIP_TRY(hipMemcpy(o->series_e, f64 ? c->pd.series_e : c->pf.series_e, (size_t)ST * c->cfg.series_len * 8,

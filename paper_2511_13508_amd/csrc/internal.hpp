@@ -128,6 +128,7 @@ struct DevPtrs {
     double* series_q;
     double* hist;
     double* hist_I;           // [S][T][bins] total intensity I/N on [0, 1]
+    double* spec;             // [S][T][spec_stride] per-mode intensity |a_k|^2 summed over measurements, replicas
     int32_t* meas_cnt;        // [S][T]
     Counters* counters;
 };
@@ -148,7 +149,7 @@ struct ShapeInfo {
     int32_t by_slot;            // items name temperature slots (hottest first), copies found via copy_at
     int32_t rho;                // constraint sum |a|^rho = N: 4 (smoothed cubic) or 2 (spherical)
     int32_t short_lists;        // every list fits one wave's registers: the one-wave-per-copy sweep
-    int32_t pad3;
+    int32_t spec_stride;        // row length of the intensity spectrum accumulator (largest N)
     uint64_t run_seed;
     double renorm_tol;
     double drift_tol;

@@ -1085,12 +1085,14 @@ __global__ __launch_bounds__(64) void k_measure(DevPtrs<R> P, ShapeInfo sh) {
         const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
         const R* a = P.amp + 2 * (sd.amp_base + local * N);
         double s1 = 0, s2 = 0, s4 = 0;
+        double* spec = P.spec + (size_t)st * sh.spec_stride;  // each lane owns its modes
         for (int k = lane; k < N; k += 64) {
             const double x = a[2 * k], y = a[2 * k + 1];
             const double I = x * x + y * y;
             s1 += I;
             s2 += I * I;
             s4 += (I * I) * (I * I);
+            spec[k] += I;
         }
         s1 = wave_sum(s1);
         s2 = wave_sum(s2);

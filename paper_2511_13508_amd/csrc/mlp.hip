@@ -20,14 +20,11 @@ constexpr float kLog2Pi = 1.83787706640934548f;
 constexpr float kPiF = 3.14159265358979324f;
 constexpr int kMaxK = 8;
 
-__device__ inline float bf16_to_f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 __device__ inline uint16_t f_to_bf16(float x) {
     uint32_t b = __float_as_uint(x);
     b += 0x7FFFu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
 }
-__device__ inline float ld(const float* p) { return *p; }
-__device__ inline float ld(const uint16_t* p) { return bf16_to_f(*p); }
 __device__ inline float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 __device__ inline float silu(float x) { return x * sigm(x); }
 

@@ -65,11 +65,6 @@ struct MlpDev {
     int64_t* moves_done;        // learned-move rounds started (RNG counter; advanced by the round's first kernel)
 };
 
-struct MlpRun {
-    float scale;     // step scale of the proposal
-    int32_t pad;
-};
-
 // all launchers enqueue on st and cover every net in one launch (grid z = net)
 hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
 hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int use_first, hipStream_t st);

@@ -21,7 +21,7 @@ SPLIT_A, SPLIT_B, SPLIT_C, SPLIT_ALL = 1, 2, 4, 7
 FP32, FP64 = 0, 1
 LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_CHUNKED = 0, 1, 2
 FIELDS_STREAM, FIELDS_CACHED = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 # every symbol declared in include/rlpt.h
 EXPORTS = [
@@ -74,7 +74,7 @@ class Config(C.Structure):
 
 
 OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",
-              "swap_acc", "swap_tries", "series_e", "series_q", "hist_I"]
+              "swap_acc", "swap_tries", "series_e", "series_q", "hist_I", "spectrum"]
 
 
 class Obs(C.Structure):
@@ -416,7 +416,8 @@ class Context:
 
     def observables(self) -> dict:
         S, T, B, Lh = self.S, self.T, self.cfg.n_bins, max(self.cfg.series_len, 1)
-        shapes = {"hist": (S, T, B), "hist_I": (S, T, B), "swap_acc": (S, max(T - 1, 1)), "swap_tries": (S, max(T - 1, 1)),
+        shapes = {"hist": (S, T, B), "hist_I": (S, T, B), "spectrum": (S, T, max(self.Ns)),
+                  "swap_acc": (S, max(T - 1, 1)), "swap_tries": (S, max(T - 1, 1)),
                   "series_e": (S, T, Lh), "series_q": (S, T, Lh)}
         out = {f: np.zeros(shapes.get(f, (S, T))) for f in OBS_FIELDS}
         o = Obs(**{f: _ptr(out[f]).value for f in OBS_FIELDS})

@@ -76,3 +76,4 @@ def test_n64_configuration_fp64_sampled(oracle):
         assert np.array_equal(temp_of[mu * ctx.R:(mu + 1) * ctx.R], pt.temp_of)
         for f in ("acc", "tries", "swap_acc", "swap_tries", "e_n", "hist", "hist_I"):
             assert np.array_equal(obs[f][mu], pt.acc[f]), f
+        np.testing.assert_allclose(obs["spectrum"][mu], pt.acc["spectrum"], rtol=1e-9, atol=1e-9)

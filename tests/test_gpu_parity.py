@@ -153,6 +153,8 @@ def compare_fp64(ctx, ors, state_tol=1e-9):
             np.testing.assert_allclose(obs[f][mu], A[f], rtol=1e-9, atol=1e-9)
         assert np.array_equal(obs["hist"][mu], A["hist"])
         assert np.array_equal(obs["hist_I"][mu], A["hist_I"])
+        np.testing.assert_allclose(obs["spectrum"][mu][:, :N], A["spectrum"], rtol=1e-9, atol=1e-9)
+        assert not np.any(obs["spectrum"][mu][:, N:])
 
 
 @pytest.mark.parametrize("layout", [PK, CH])

@@ -178,6 +178,31 @@ def test_init_is_on_constraint_and_beta0_law(oracle):
     assert abs(np.mean(a / np.abs(a))) < 5.0 / math.sqrt(a.size)
 
 
+def test_spectrum_is_flat_at_infinite_temperature(oracle):
+    """The intensity spectrum accumulator I(omega_k) = <|a_k|^2> (sec. II.C):
+    at infinite temperature every mode has the closed-form mean E|a|^2 of the
+    flat constrained law, whatever its frequency, and at a finite temperature
+    its sum over modes per measurement stays between the bounds of the
+    constraint: 1 <= sum |a|^2 <= N (Cauchy-Schwarz with sum |a|^4 = N) times
+    the measurement count."""
+    N, reps = 6, 48
+    g = oracle.Graph(N, 11)
+    pt = oracle.PT(g, [1e11, 1e12], n_reps=reps, run_seed=5, swap_interval=1, resync_interval=0,
+                   measure_start=0, measure_interval=1)
+    pt.run(3000)
+    ref = brute.beta0_moments(N)["E|a|^2"]
+    spec = pt.acc["spectrum"] / pt.acc["e_n"][:, None]
+    assert spec.shape == (2, N)
+    # copies are independent: the error of a mode's mean from the per-copy spread over a long run
+    tol = 5 * np.sqrt((ref * ref * 0.6) / (reps * 3000 / 3.0))
+    np.testing.assert_allclose(spec, ref, rtol=0, atol=tol)
+    cold = oracle.PT(g, [0.3, 0.6], n_reps=2, run_seed=6, swap_interval=1, resync_interval=0, measure_start=0,
+                     measure_interval=1)
+    cold.run(300)
+    tot = cold.acc["spectrum"].sum(axis=1)
+    assert np.all(tot >= cold.acc["e_n"] * 1.0 - 1e-9) and np.all(tot <= cold.acc["e_n"] * N + 1e-9)
+
+
 def test_beta0_chain_preserves_law_and_constraint(oracle):
     """At infinite temperature every move is accepted; starting from the exact
     beta = 0 law the chain must stay on it (the two-mode proposal is exactly
