@@ -486,12 +486,24 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
         });
     const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached, c->sh.short_lists);
     if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
+    // streaming sweep over chunked lists: hold a step's chunks in registers a step
+    // ahead when every list of the launch fits 1, 2 or 4 chunks per thread
+    int prefetch = 0;
+    if (c->sh.layout == kLayoutChunked && !c->sh.cached && !c->sh.short_lists && (block == 256 || block == 512)) {
+        uint32_t need = 0;
+        for (const ItemDev& it : items) {
+            const uint32_t nt = (uint32_t)(block / 64 / it.n_copies) * 64;
+            need = std::max(need, (c->max_chunks[it.sample] + nt - 1) / nt);
+        }
+        prefetch = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0;
+    }
     c->items = items;
     c->tile_copies = copies;
     c->launch.block_threads = block;
     c->launch.n_items = (int)items.size();
     c->launch.max_copies_per_item = max_cpi;
     c->launch.max_N = c->max_N;
+    c->launch.prefetch = prefetch;
     c->launch.lds_bytes = lds;
     c->sh.by_slot = c->sh.cached;
     return RLPT_OK;
@@ -598,6 +610,7 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     c->ws = d_workspace;
     c->ws_bytes = workspace_bytes;
     c->sh.cached = cfg->field_mode == RLPT_FIELDS_CACHED ? 1 : 0;
+    c->sh.layout = layout;
     c->layout = layout;
     // everything a run changes, for checkpoints: amplitudes, energies, drift,
     // temperature permutation, cached fields, accumulators and counters
@@ -702,6 +715,12 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
         quad_base += g->n_terms();
         c->samples.push_back(sd);
         c->N.push_back(g->N);
+        {
+            uint32_t mc = 0;
+            if (layout == kLayoutChunked)
+                for (int l = 0; l < g->N; ++l) mc = std::max(mc, g->chunk_start[l + 1] - g->chunk_start[l]);
+            c->max_chunks.push_back(mc);
+        }
         c->max_N = std::max(c->max_N, g->N);
     }
     c->amp_complex = amp_base;

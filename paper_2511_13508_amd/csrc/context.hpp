@@ -20,6 +20,7 @@ struct rlpt_ctx {
     hipStream_t stream = nullptr;
     int S = 0, T = 0, reps = 0, Rc = 0, n_copies = 0, max_N = 0;
     std::vector<int> N;
+    std::vector<uint32_t> max_chunks;  // longest chunked list of each sample (0 in the packed layout)
     std::vector<double> temps;
     std::vector<SampleDev> samples;
     std::vector<ItemDev> items;

@@ -161,6 +161,7 @@ struct SweepLaunch {
     int n_items;
     int max_copies_per_item;
     int max_N;
+    int prefetch;  // chunks per thread held a step ahead (0: streamed in the step; 1, 2 or 4)
     size_t lds_bytes;
 };
 

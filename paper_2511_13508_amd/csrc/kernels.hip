@@ -207,6 +207,55 @@ __device__ inline void mode_field(const DevPtrs<R>& P, const SampleDev& sd, int 
     }
 }
 
+// workgroup barrier that waits for LDS operations only (s_waitcnt lgkmcnt(0)
+// with vmcnt and expcnt at their maxima, 0xC07F): global loads issued before
+// it stay in flight.  Only for loops whose global memory traffic is loads.
+__device__ inline void block_sync_lds() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// list chunks of one mode held in registers, a step ahead: thread t of a
+// group of nt owns chunks beg + t + m * nt, m < PF (the host picks PF so that
+// every list of the launch fits); consumed in the order the streaming loop
+// of field_partial_chunk would take them
+template <typename R, int PF>
+struct ChunkRegs {
+    uint32_t x[PF];
+    uint2 yz[PF];
+    typename J4<R>::T J[PF];
+    uint32_t n;  // chunks of this thread
+};
+
+template <typename R, int PF>
+__device__ inline void chunk_prefetch(const DevPtrs<R>& P, const SampleDev& sd, int l, int t, int nt,
+                                      ChunkRegs<R, PF>& rg) {
+    using JT = typename J4<R>::T;
+    const uint32_t* cs = P.chunk_start + sd.mode_base;
+    const uint32_t beg = cs[l], end = cs[l + 1];
+    const JT* __restrict__ Jv = reinterpret_cast<const JT*>(P.cJ);
+    rg.n = 0;
+#pragma unroll
+    for (int m = 0; m < PF; ++m) {
+        const uint32_t c = beg + t + (uint32_t)m * nt;
+        if (c < end) {
+            rg.x[m] = P.cx[c];
+            rg.yz[m] = P.cyz[c];
+            rg.J[m] = Jv[c];
+            rg.n = m + 1;
+        }
+    }
+}
+
+template <typename R, int PF>
+__device__ inline void chunk_consume(const ChunkRegs<R, PF>& rg, const R2<R>* __restrict__ a, R& fr, R& fi) {
+#pragma unroll
+    for (int m = 0; m < PF; ++m)
+        if ((uint32_t)m < rg.n) chunk_term<R>(rg.x[m], rg.yz[m], rg.J[m], a, fr, fi);
+}
+
 // energy change of the two-mode update from the two fields of one snapshot:
 // dE = -2 Re(conj(aj_new - aj_old) F_j) - 2 Re(conj(ak_new - ak_old) F_k)
 template <typename R>
@@ -265,7 +314,11 @@ __host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
     return (amp + tab + red + 15) & ~(size_t)15;
 }
 
-template <typename R, int BLOCK, int LAYOUT>
+// PF > 0 (chunked lists short enough for PF chunks per thread): a step's list
+// chunks are loaded into registers during the previous step, and the step
+// loop's barriers wait for LDS only, so the loads stay in flight across the
+// reduction, the decision and both barriers.  Same chain, same arithmetic.
+template <typename R, int BLOCK, int LAYOUT, int PF>
 __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kWaves = BLOCK / 64;
@@ -299,11 +352,18 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     const int64_t sweep0 = P.counters->sweeps_done;
 
     R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
+    ChunkRegs<R, (PF > 0 ? PF : 1)> pj, pk;  // next step's chunks (PF > 0)
     for (int sw = 0; sw < n_sweeps; ++sw) {
         __syncthreads();
         if (active)
             for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N, sh.rho);
         __syncthreads();
+        if constexpr (PF > 0) {
+            if (active) {
+                chunk_prefetch<R, PF>(P, sd, tab[0].jk & 0xffff, gt, nt, pj);
+                chunk_prefetch<R, PF>(P, sd, tab[0].jk >> 16, gt, nt, pk);
+            }
+        }
         if (active && gt == 0) {  // snapshot of step 0
             const int j = tab[0].jk & 0xffff, k = tab[0].jk >> 16;
             ajo = a[j];
@@ -315,12 +375,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
             a[j] = ajn;
         }
         for (int s = 0; s < steps; ++s) {
-            __syncthreads();
+            if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
             R fjr = 0, fji = 0, fkr = 0, fki = 0;
             if (active) {
-                const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
-                mode_field<R, LAYOUT>(P, sd, j, a, gt, nt, fjr, fji);
-                mode_field<R, LAYOUT>(P, sd, k, a, gt, nt, fkr, fki);
+                if constexpr (PF > 0) {
+                    chunk_consume<R, PF>(pj, a, fjr, fji);
+                    chunk_consume<R, PF>(pk, a, fkr, fki);
+                    if (s + 1 < steps) {
+                        chunk_prefetch<R, PF>(P, sd, tab[s + 1].jk & 0xffff, gt, nt, pj);
+                        chunk_prefetch<R, PF>(P, sd, tab[s + 1].jk >> 16, gt, nt, pk);
+                    }
+                } else {
+                    const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
+                    mode_field<R, LAYOUT>(P, sd, j, a, gt, nt, fjr, fji);
+                    mode_field<R, LAYOUT>(P, sd, k, a, gt, nt, fkr, fki);
+                }
             }
             fjr = wave_sum(fjr);
             fji = wave_sum(fji);
@@ -332,7 +401,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
                 red[4 * gw + 2] = fkr;
                 red[4 * gw + 3] = fki;
             }
-            __syncthreads();
+            if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
             if (active && gt == 0) {
                 R2<R> Fj = mk2<R>(0, 0), Fk = mk2<R>(0, 0);
                 for (int w = 0; w < wpc; ++w) {
@@ -387,16 +456,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
 // streaming sweep.  The host takes this path only when no padded list is
 // longer than 32 * kShortSlots entries.
 constexpr int kShortSlots = 4;
-
-// workgroup barrier that waits for LDS operations only (s_waitcnt lgkmcnt(0)
-// with vmcnt and expcnt at their maxima, 0xC07F): global loads issued before
-// it stay in flight.  Only for loops whose global memory traffic is loads.
-__device__ inline void block_sync_lds() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_s_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 // keep the compiler from moving LDS accesses across a write by one lane that
 // all lanes then read (the hardware runs one wave's LDS accesses in order);
@@ -1257,12 +1316,31 @@ hipError_t launch_sweep_t(const void* ptrs, const ShapeInfo& sh, const SweepLaun
                                st, P, sh, L.max_N, n_sweeps);
         return hipGetLastError();
     }
-    if (sh.layout == kLayoutChunked)
-        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
+    if (sh.layout == kLayoutChunked) {
+        if constexpr (BLOCK == 256 || BLOCK == 512) {
+            switch (L.prefetch) {
+                case 0: break;
+                case 1:
+                    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 1>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
+                                       st, P, sh, L.max_N, n_sweeps);
+                    return hipGetLastError();
+                case 2:
+                    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 2>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
+                                       st, P, sh, L.max_N, n_sweeps);
+                    return hipGetLastError();
+                case 4:
+                    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 4>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
+                                       st, P, sh, L.max_N, n_sweeps);
+                    return hipGetLastError();
+                default: return hipErrorInvalidValue;
+            }
+        }
+        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 0>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
                            L.max_N, n_sweeps);
-    else
-        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutPacked>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
+    } else {
+        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutPacked, 0>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
                            L.max_N, n_sweeps);
+    }
     return hipGetLastError();
 }
 
