@@ -253,10 +253,13 @@ int rlpt_tune_get(rlpt_tile* out, int32_t capacity, int32_t* count);
 int rlpt_tune_save(const char* path);
 int rlpt_tune_load(const char* path);
 
-/* Measure every tile for each distinct N among graphs: one temporary context
- * per N (the samples of that N, cfg's ladder and precision) in the caller's
- * workspace (>= rlpt_workspace_size for all graphs), sweeps_per_trial timed
- * sweeps per tile after one warm-up sweep, recorded in the registry.
+/* Measure tiles on one temporary context holding all graphs (cfg's ladder and
+ * precision) in the caller's workspace (>= rlpt_workspace_size for all
+ * graphs).  For each workgroup size the N classes are tuned in turn: every
+ * copies-per-workgroup value of one N is timed on the whole launch (all N
+ * together) with the other N at their current choice (built-in at first), and
+ * the best is kept; sweeps_per_trial timed sweeps per tile after one warm-up
+ * sweep; each trial is recorded in the registry under its N.
  * *n_trials (may be NULL) receives the number of tiles timed.  Synchronous. */
 int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t n_graphs,
                   const double* temps, void* d_workspace, size_t workspace_bytes, void* hip_stream,

@@ -1240,24 +1240,32 @@ int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32
         return fail(RLPT_E_UNSUPPORTED, "the autotuner times the streaming sweep; use field_mode = RLPT_FIELDS_STREAM");
     if ((rc = check_graphs(graphs, n_graphs))) return rc;
     if (sweeps_per_trial < 1) return fail(RLPT_E_ARG, "sweeps_per_trial must be >= 1");
-    std::map<int, std::vector<const rlpt_graph*>> byN;
-    for (int i = 0; i < n_graphs; ++i) byN[graphs[i]->N].push_back(graphs[i]);
+    std::map<int, int> counts;
+    for (int i = 0; i < n_graphs; ++i) counts[graphs[i]->N] += 1;
     rlpt_config c2 = *cfg;
     c2.swap_interval = 1 << 30;  // timing covers sweeps only: one launch per trial
     c2.resync_interval = 0;
     c2.measure_interval = 0;
     c2.block_threads = 256;
     c2.copies_per_block = 1;
+    // every trial times the whole context's launch (all N together, as the
+    // context will run): per workgroup size, the N classes are tuned one after
+    // another, each over its copies per workgroup with the others at their
+    // current choice (built-in first), and each trial is recorded for its N
+    rlpt_ctx* c = nullptr;
+    rc = rlpt_create(&c2, graphs, n_graphs, temps, d_workspace, workspace_bytes, hip_stream, &c);
+    if (rc) return rc;
+    rc = rlpt_init(c, 1);
     int trials = 0;
-    for (auto& kv : byN) {
-        rlpt_ctx* c = nullptr;
-        rc = rlpt_create(&c2, kv.second.data(), (int32_t)kv.second.size(), temps, d_workspace, workspace_bytes,
-                         hip_stream, &c);
-        if (rc) return rc;
-        rc = rlpt_init(c, 1);
-        for (int b = 64; b <= 1024 && rc == RLPT_OK; b *= 2)
+    for (int b = 64; b <= 1024 && rc == RLPT_OK; b *= 2) {
+        std::map<int, int> cur;
+        for (const auto& nc : counts) cur[nc.first] = std::max(1, std::min(default_tile(nc.first).copies, b / 64));
+        for (const auto& nc : counts) {
+            double best = -1.0;
+            int best_cp = cur[nc.first];
             for (int cp = 1; cp <= b / 64 && rc == RLPT_OK; cp *= 2) {
-                std::map<int, int> copies{{kv.first, cp}};
+                std::map<int, int> copies = cur;
+                copies[nc.first] = cp;
                 if (build_items(c, b, copies) != RLPT_OK) continue;  // LDS limit
                 if ((rc = upload_items(c))) break;
                 if ((rc = rlpt_sweep(c, 1))) break;
@@ -1269,7 +1277,7 @@ int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32
                 c->timing = false;
                 if (rc) break;
                 rlpt_tile t{};
-                t.n_modes = kv.first;
+                t.n_modes = nc.first;
                 t.precision = cfg->precision;
                 t.shared_pairs = cfg->shared_pairs;
                 t.block_threads = b;
@@ -1277,11 +1285,17 @@ int rlpt_autotune(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32
                 t.ms_per_sweep = ms / sweeps_per_trial;
                 tune_record(t);
                 ++trials;
+                if (best < 0 || t.ms_per_sweep < best) {
+                    best = t.ms_per_sweep;
+                    best_cp = cp;
+                }
             }
-        int rc2 = rlpt_destroy(c);
-        if (rc) return rc;
-        if (rc2) return rc2;
+            cur[nc.first] = best_cp;
+        }
     }
+    int rc2 = rlpt_destroy(c);
+    if (rc) return rc;
+    if (rc2) return rc2;
     if (n_trials) *n_trials = trials;
     return RLPT_OK;
 }
