@@ -34,7 +34,8 @@ SEED_BASE = 2511135080 + 400  # disorder seed of sample mu: SEED_BASE + mu
 HBM_PEAK_GBS = 8000.0
 METRIC = "mode-updates/s + τ_int-corrected sweeps/s (learned vs plain PT), N=256, 1 GPU"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_n256_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2511_13508_amd", "csrc", "kernels.hip")
+# the sweep kernel and the host code that lays out its launch (tiles, item order)
+KERNEL_SRC = [os.path.join(ROOT, "paper_2511_13508_amd", "csrc", f) for f in ("kernels.hip", "api.cpp")]
 
 
 def log(msg):
@@ -42,8 +43,11 @@ def log(msg):
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for_current_kernel(launch_bytes_alg: float):

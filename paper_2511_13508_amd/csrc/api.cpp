@@ -480,10 +480,21 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
             max_cpi = std::max(max_cpi, it.n_copies);
         }
     }
-    if (c->sh.cached)  // hottest slots first across samples (stable: sample order within a rank)
+    if (c->sh.cached) {  // hottest slots first across samples (stable: sample order within a rank)
         std::stable_sort(items.begin(), items.end(), [&](const ItemDev& x, const ItemDev& y) {
             return x.first_copy - x.sample * c->Rc < y.first_copy - y.sample * c->Rc;
         });
+    } else if (c->S > 1 && *std::min_element(c->N.begin(), c->N.end()) == c->max_N) {
+        // one N: deal the samples' items round robin.  Workgroups go to the eight
+        // XCDs in turn, so an XCD then holds the copies of few samples and its L2
+        // sees only their lists (with eight samples: one sample per XCD)
+        std::vector<ItemDev> rr;
+        rr.reserve(items.size());
+        const size_t per = items.size() / c->S;  // equal item counts: same N, same tile
+        for (size_t k = 0; k < per; ++k)
+            for (int s2 = 0; s2 < c->S; ++s2) rr.push_back(items[(size_t)s2 * per + k]);
+        items.swap(rr);
+    }
     const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached, c->sh.short_lists);
     if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
     // streaming sweep over chunked lists: hold a step's chunks in registers a step
