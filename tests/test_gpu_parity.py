@@ -188,6 +188,19 @@ def test_trajectory_fp64_tiles(oracle, block, copies):
     compare_fp64(ctx, ors)
 
 
+@pytest.mark.parametrize("N,block,copies", [(20, 256, 1), (64, 256, 1), (128, 512, 1), (128, 512, 2)])
+def test_trajectory_fp64_chunks_a_step_ahead(oracle, N, block, copies):
+    """Chunked lists held in registers a step ahead: at most 35 chunks per list
+    at N = 20 (1 per thread of 256), 357 at N = 64 (2 per thread of 256) and
+    1428 at N = 128 (3 per thread of 512, the 4-chunk variant); N = 128 with two
+    copies per 512-thread workgroup needs 6 per thread and streams instead.
+    Every one gives the oracle's trajectory."""
+    ctx, ors = run_pair(oracle, [N], temps_geo(0.5, 1.2, 3), 20, 13, n_reps=2, precision=rlpt.FP64,
+                        block_threads=block, copies_per_block=copies, resync_interval=0, n_bins=10,
+                        list_layout=CH)
+    compare_fp64(ctx, ors)
+
+
 def test_edge_cases_fp64(oracle):
     """N = 4 comb (one term), odd N = 5, a single temperature and one replica."""
     for N, omega in ((4, rlpt.OMEGA_COMB), (5, rlpt.OMEGA_COMB), (7, rlpt.OMEGA_RANDOM)):
