@@ -50,7 +50,7 @@ def test_cached_uneven_batch(oracle, shared, layout):
     compare_fp64(ctx, ors)
 
 
-@pytest.mark.parametrize("block,copies", [(64, 1), (128, 1), (256, 2), (512, 4), (256, 4)])
+@pytest.mark.parametrize("block,copies", [(64, 1), (128, 1), (256, 2), (512, 4), (256, 4), (512, 1), (1024, 1)])
 def test_cached_tiles(oracle, block, copies):
     """Every launch tile gives the same trajectory."""
     ctx, ors = run_pair(oracle, [20], temps_geo(0.5, 1.2, 3), 60, 9, n_reps=3, precision=rlpt.FP64,
