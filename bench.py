@@ -427,7 +427,7 @@ def n64_physics(args, rlpt, torch, out, sweeps=100000):
 
 
 def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweeps=20000, warm=2000,
-                harvest_rounds=6250, train_steps=1000, reeq=5000):
+                harvest_rounds=6250, train_steps=1000, reeq=5000, at="peak", train=True):
     """The learned-proposal configuration: N = 64, 8 samples x 24 temperatures
     geometric in [0.3, 1.5] x 2 replicas.  A first plain run finds the peak of
     the specific heat; networks (2N -> 256 -> 256 SiLU -> 4-component mixture)
@@ -438,12 +438,15 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
     harvest and makes one learned round per sweep from then on, the plain run
     does not.  Reports tau_int of E and q at the learned temperatures,
     effective sweeps/s learned / plain, and whether the energy and the overlap
-    histogram agree (paired jackknife over samples)."""
+    histogram agree (paired jackknife over samples).  at = "cold" puts the
+    networks on the four coldest temperatures instead; train = False runs the
+    learned rounds with the networks at their initialisation (outputs near
+    zero: an isotropic small-step mixture), the same history otherwise."""
     temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
     graphs = [rlpt.Graph(N, 2511135080 + 300 + mu) for mu in range(S)]
     start = warm + harvest_rounds * 2 + reeq
 
-    def run(learn_t, train):
+    def run(learn_t, learned):
         cfg = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=100,
                    measure_start=start, measure_interval=1, n_bins=100, series_len=sweeps,
                    mlp_nets=len(learn_t), mlp_hidden=256, mlp_components=4,
@@ -455,12 +458,13 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         t0 = time.perf_counter()
         ctx.mlp_harvest(rounds=harvest_rounds, lag=2)
         info = {}
-        if train:
+        if learned and train:
             l0 = ctx.mlp_train(1, 1e-3)
             l1 = ctx.mlp_train(train_steps, 1e-3)
             torch.cuda.synchronize()
             info = {"harvest_and_train_s": time.perf_counter() - t0, "pairs_per_net": harvest_rounds * S * reps,
                     "train_loss_first_last": [l0.round(2).tolist(), l1.round(2).tolist()]}
+        if learned:
             ctx.mlp_enable(1, args.learn_scale)
         ctx.sweep(start - ctx.counters()[0])
         torch.cuda.synchronize()
@@ -470,7 +474,7 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         el = time.perf_counter() - t0
         ctx.check()
         o = ctx.observables()
-        if train:
+        if learned:
             acc, tries = ctx.mlp_stats()
             info["move_acceptance"] = (acc / np.maximum(tries, 1)).round(4).tolist()
         ctx.close()
@@ -498,10 +502,15 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         loo = (v.sum(axis=0) - v) / (n - 1)
         return v.mean(axis=0), np.sqrt((n - 1) / n * ((loo - loo.mean(axis=0)) ** 2).sum(axis=0))
 
-    log("learned N=64: locating the C_V peak")
-    pk = peak_run()
-    t_learn = [t for t in range(pk - n_nets // 2, pk - n_nets // 2 + n_nets) if 0 <= t < T]
-    log(f"learned N=64: C_V peak at T={temps[pk]:.3f}; plain run with the harvest history")
+    if at == "cold":
+        pk = -1
+        t_learn = list(range(n_nets))
+    else:
+        log("learned N=64: locating the C_V peak")
+        pk = peak_run()
+        t_learn = [t for t in range(pk - n_nets // 2, pk - n_nets // 2 + n_nets) if 0 <= t < T]
+        log(f"learned N=64: C_V peak at T={temps[pk]:.3f}")
+    log("learned N=64: plain run with the harvest history")
     op, sps_p, _ = run(t_learn, False)
     log("learned N=64: learned run")
     ol, sps_l, info = run(t_learn, True)
@@ -520,10 +529,11 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
     effp_q, effl_q = sps_p / (2 * tqp), sps_l / (2 * tql)
     out["learned_n64"] = {
         "config": f"N={N}, {S} samples x {T} temperatures [0.3, 1.5] x {reps} replicas, FP32; learned rounds "
-                  f"(1 per sweep, step scale {args.learn_scale}) at the {len(t_learn)} temperatures around the "
-                  f"C_V peak; both runs: {warm} warm-up, {harvest_rounds * 2} harvest (no swaps), {reeq} more sweeps, "
+                  f"(1 per sweep, step scale {args.learn_scale}, {'trained' if train else 'untrained'} networks) at "
+                  f"the {len(t_learn)} {'coldest temperatures' if at == 'cold' else 'temperatures around the C_V peak'}"
+                  f"; both runs: {warm} warm-up, {harvest_rounds * 2} harvest (no swaps), {reeq} more sweeps, "
                   f"then {sweeps} measured sweeps",
-        "temperatures": [float(temps[t]) for t in t_learn], "cv_peak_T": float(temps[pk]),
+        "temperatures": [float(temps[t]) for t in t_learn], "cv_peak_T": float(temps[pk]) if pk >= 0 else None,
         "plain": {"sweeps_per_s": sps_p, "tau_int_E": tEp.round(2).tolist(), "tau_int_q": tqp.round(2).tolist()},
         "learned": {"sweeps_per_s": sps_l, "tau_int_E": tEl.round(2).tolist(), "tau_int_q": tql.round(2).tolist(),
                     **info},
@@ -568,6 +578,10 @@ def main():
     ap.add_argument("--workload", choices=["n256", "batched", "learned64"], default="n256",
                     help="n256: the headline configuration; batched: the uneven-N configuration with autotuning; "
                          "learned64: only the N=64 learned-proposal comparison")
+    ap.add_argument("--n64-learn-at", choices=["peak", "cold"], default="peak",
+                    help="learned64 workload: networks around the C_V peak or on the four coldest temperatures")
+    ap.add_argument("--n64-untrained", action="store_true",
+                    help="learned64 workload: learned rounds with untrained networks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -588,7 +602,8 @@ def main():
         return
     if args.workload == "learned64":
         res = {}
-        learned_n64(args, rlpt, torch, res, sweeps=args.steps // 100 * 100 or 100)
+        learned_n64(args, rlpt, torch, res, sweeps=args.steps // 100 * 100 or 100, at=args.n64_learn_at,
+                    train=not args.n64_untrained)
         print(json.dumps(res["learned_n64"]), flush=True)
         return
     if args.copy_calibration:
