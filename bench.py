@@ -710,7 +710,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_sweep", "ms_per_launch": kms / launches,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None,
+                     "traffic_GBps": traffic / t_launch / 1e9 if traffic else None,
+                     "note": "algorithmic bytes: every list entry a step reads; traffic: rocprofv3 fabric bytes "
+                             "(L2 misses) of the same launch; each XCD's L2 serves its sample's repeated lists"},
         "sweeps_per_s": sweeps_per_s,
     }
     # ---------------------------------------------------------------- cached local fields
