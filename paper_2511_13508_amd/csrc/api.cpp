@@ -106,7 +106,7 @@ struct Layout {
 struct Regions {
     size_t samples, items, mode_start, idx, J, chunk_start, cx, cyz, cJ, pair_start, pidx, pJ, fields, ell_start, gidx16, gidx32, gJ, c0, quads, Jq, amp, E, E64, drift, temp_of, copy_at, beta, beta64;
     size_t acc_begin, acc, swap_acc, obs, hist, hist_I, spec, series_e, series_q, meas_cnt, counters, acc_end;
-    size_t scratch, scratch_doubles, mlp, total;
+    size_t scratch, scratch_doubles, rs_part, mlp, total;
 };
 
 int check_config(const rlpt_config* cfg) {
@@ -325,6 +325,7 @@ Regions plan(const rlpt_config& cfg, const rlpt_graph* const* g, int S, int layo
     r.acc_end = L.off;
     r.scratch_doubles = std::max<size_t>(2 * amp, 8192);
     r.scratch = L.take(r.scratch_doubles * 8);
+    r.rs_part = L.take(copies * kResyncParts * 8);
     r.mlp = L.off;
     L.off = mlp_layout(cfg, g[0]->N, S, nullptr, nullptr, L.off);
     r.total = L.off;
@@ -371,6 +372,7 @@ void fill_ptrs(DevPtrs<R>& P, unsigned char* b, const Regions& r) {
     P.series_q = reinterpret_cast<double*>(b + r.series_q);
     P.meas_cnt = reinterpret_cast<int32_t*>(b + r.meas_cnt);
     P.counters = reinterpret_cast<Counters*>(b + r.counters);
+    P.rs_part = reinterpret_cast<double*>(b + r.rs_part);
 }
 
 template <typename T>

@@ -131,7 +131,10 @@ struct DevPtrs {
     double* spec;             // [S][T][spec_stride] per-mode intensity |a_k|^2 summed over measurements, replicas
     int32_t* meas_cnt;        // [S][T]
     Counters* counters;
+    double* rs_part;          // [copies][kResyncParts] partial FP64 energies of a recomputation
 };
+
+constexpr int kResyncParts = 8;  // term ranges of one energy recomputation (workgroups per copy group)
 
 // offsets (in doubles) of the [S][T] accumulator blocks inside DevPtrs::obs
 enum ObsField { kEN = 0, kESum, kESq, kY2, kY4, kQN, kQSum, kQSq, kQ4, kNumObs };

@@ -1002,47 +1002,93 @@ __global__ __launch_bounds__(256) void k_init(DevPtrs<R> P, ShapeInfo sh) {
 // one block per copy: H = -2 sum_q J_q Re(conj a_p conj a_s a_m a_n) and
 // S = sum |a|^4 in FP64.  mode 0: drift check, renormalise when
 // |S/N - 1| > renorm_tol (H scales by N/S), store E; mode 1: E64 only.
+// FP64 energy recomputation in two stages.  Stage one: the copies of one
+// sample in groups of up to kResyncCopies (FP64 amplitudes in LDS) and the
+// sample's by-term list cut into kResyncParts ranges; a workgroup streams one
+// range once for its whole group and leaves each copy's partial energy.
+constexpr int kResyncCopies = 8;
+
+__host__ __device__ inline int resync_group(int N) {
+    const int fit = (48 * 1024) / (N * 16);  // FP64 complex amplitudes of the group within 48 KiB
+    return fit < 1 ? 1 : (fit < kResyncCopies ? fit : kResyncCopies);
+}
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_resync(DevPtrs<R> P, ShapeInfo sh, int mode) {
-    __shared__ double2 a[kMaxModes];
-    __shared__ double red[2][4];
-    __shared__ double bc[2];
-    const int c = blockIdx.x;
+__global__ __launch_bounds__(256) void k_resync_part(DevPtrs<R> P, ShapeInfo sh, int group, int groups) {
+    extern __shared__ double2 ra[];  // [group][N]
+    __shared__ double red[4][kResyncCopies];
+    const int part = blockIdx.x % kResyncParts;
+    const int grp = (blockIdx.x / kResyncParts) % groups;
+    const int mu = blockIdx.x / (kResyncParts * groups);
+    const SampleDev sd = P.samples[mu];
+    const int N = sd.N;
+    const int g0 = grp * group;
+    const int ng = sh.copies_per_sample - g0 < group ? sh.copies_per_sample - g0 : group;
+    for (int i = 0; i < ng; ++i) {
+        const R* amp = P.amp + 2 * (sd.amp_base + (int64_t)(g0 + i) * N);
+        for (int k = threadIdx.x; k < N; k += blockDim.x)
+            ra[(size_t)i * N + k] = make_double2((double)amp[2 * k], (double)amp[2 * k + 1]);
+    }
+    __syncthreads();
+    double H[kResyncCopies];
+#pragma unroll
+    for (int i = 0; i < kResyncCopies; ++i) H[i] = 0.0;
+    const ushort4* Q = P.quads + sd.quad_base;
+    const double* Jq = P.Jq + sd.quad_base;
+    const int64_t q0 = sd.n_quads * part / kResyncParts, q1 = sd.n_quads * (part + 1) / kResyncParts;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        const ushort4 t = Q[q];
+        const double J = Jq[q];
+#pragma unroll
+        for (int i = 0; i < kResyncCopies; ++i) {
+            if (i >= ng) break;
+            const double2* a = ra + (size_t)i * N;
+            const double2 p = a[t.x], s = a[t.y], m = a[t.z], n = a[t.w];
+            // conj(p) conj(s) = (p.x s.x - p.y s.y, -(p.x s.y + p.y s.x))
+            const double cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
+            const double dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
+            H[i] += -2.0 * J * (cr * dr - ci * di);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kResyncCopies; ++i) {
+        if (i >= ng) break;
+        const double h = wave_sum(H[i]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = h;
+    }
+    __syncthreads();
+    if (threadIdx.x < ng) {
+        const int i = threadIdx.x;
+        const int64_t c = (int64_t)mu * sh.copies_per_sample + g0 + i;
+        P.rs_part[c * kResyncParts + part] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    }
+}
+
+// Stage two, one wave per copy: H = the parts in order, S = sum |a|^rho; the
+// drift and finiteness checks, renormalisation by (N/S)^(1/rho) when S is off
+// N by more than renorm_tol (H scales with the fourth power), and the energies.
+// mode 0: periodic recomputation; 1: FP64 energies into E64 only; 2: E = H.
+template <typename R>
+__global__ __launch_bounds__(64) void k_resync_fin(DevPtrs<R> P, ShapeInfo sh, int mode) {
+    const int c = blockIdx.x, lane = threadIdx.x;
     const int mu = c / sh.copies_per_sample;
     const SampleDev sd = P.samples[mu];
     const int N = sd.N;
     const int64_t local = c - (int64_t)mu * sh.copies_per_sample;
     R* amp = P.amp + 2 * (sd.amp_base + local * N);
     double s4 = 0.0;  // sum |a|^rho
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    for (int k = lane; k < N; k += 64) {
         const double x = (double)amp[2 * k], y = (double)amp[2 * k + 1];
-        a[k] = make_double2(x, y);
         const double u = x * x + y * y;
         s4 += sh.rho == 2 ? u : u * u;
     }
-    __syncthreads();
-    double H = 0.0;
-    const ushort4* Q = P.quads + sd.quad_base;
-    const double* Jq = P.Jq + sd.quad_base;
-    for (int64_t q = threadIdx.x; q < sd.n_quads; q += blockDim.x) {
-        const ushort4 t = Q[q];
-        const double2 p = a[t.x], s = a[t.y], m = a[t.z], n = a[t.w];
-        // conj(p) conj(s) = (p.x s.x - p.y s.y, -(p.x s.y + p.y s.x))
-        const double cr = p.x * s.x - p.y * s.y, ci = -(p.x * s.y + p.y * s.x);
-        const double dr = m.x * n.x - m.y * n.y, di = m.x * n.y + m.y * n.x;
-        H += -2.0 * Jq[q] * (cr * dr - ci * di);
-    }
-    H = wave_sum(H);
-    s4 = wave_sum(s4);
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = H;
-        red[1][threadIdx.x >> 6] = s4;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double Ht = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        const double St = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-        double f = 1.0;
+    const double St = wave_sum(s4);
+    double Ht = 0.0;
+    for (int p = 0; p < kResyncParts; ++p) Ht += P.rs_part[(int64_t)c * kResyncParts + p];
+    double f = 1.0;
+    if (mode == 0 && fabs(St / (double)N - 1.0) > sh.renorm_tol && St > 0.0)
+        f = sh.rho == 2 ? sqrt((double)N / St) : pow((double)N / St, 0.25);
+    if (lane == 0) {
         if (mode == 2) P.E[c] = (R)Ht;
         if (mode == 0) {
             const double Er = (double)P.E[c];
@@ -1051,24 +1097,16 @@ __global__ __launch_bounds__(256) void k_resync(DevPtrs<R> P, ShapeInfo sh, int 
             P.drift[c] = d;
             if (!isfinite(Ht) || !isfinite(St) || !isfinite(Er)) atomicOr(&P.counters->error_flags, 2);
             else if (sh.drift_tol > 0.0 && d > sh.drift_tol) atomicOr(&P.counters->error_flags, 1);
-            if (fabs(St / (double)N - 1.0) > sh.renorm_tol && St > 0.0) {
-                // H is homogeneous of degree 4 in a
-                f = sh.rho == 2 ? sqrt((double)N / St) : pow((double)N / St, 0.25);
-                Ht *= f * f * f * f;
-            }
+            if (f != 1.0) Ht *= f * f * f * f;  // H is homogeneous of degree 4 in a
             P.E[c] = (R)Ht;
         }
         P.E64[c] = Ht;
-        bc[0] = f;
     }
-    __syncthreads();
-    if (mode == 0 && bc[0] != 1.0) {
-        const double f = bc[0];
-        for (int k = threadIdx.x; k < N; k += blockDim.x) {
-            amp[2 * k] = (R)(a[k].x * f);
-            amp[2 * k + 1] = (R)(a[k].y * f);
+    if (f != 1.0)
+        for (int k = lane; k < N; k += 64) {
+            amp[2 * k] = (R)((double)amp[2 * k] * f);
+            amp[2 * k + 1] = (R)((double)amp[2 * k + 1] * f);
         }
-    }
 }
 
 // ---------------------------------------------------------------- replica exchange
@@ -1420,7 +1458,17 @@ hipError_t launch_tick(const void* ptrs, int precision, int64_t d_sweeps, int64_
 
 template <typename R>
 static hipError_t resync_t(const void* ptrs, const ShapeInfo& sh, int n_copies, int mode, hipStream_t st) {
-    hipLaunchKernelGGL(k_resync<R>, dim3(n_copies), dim3(256), 0, st, *static_cast<const DevPtrs<R>*>(ptrs), sh, mode);
+    const DevPtrs<R>& P = *static_cast<const DevPtrs<R>*>(ptrs);
+    // copy groups sized for the largest N of the context (spec_stride); n_copies = samples x copies per sample
+    const int group = resync_group(sh.spec_stride);
+    const int groups = (sh.copies_per_sample + group - 1) / group;
+    const int samples = n_copies / sh.copies_per_sample;
+    const size_t lds = (size_t)group * sh.spec_stride * sizeof(double2);
+    hipLaunchKernelGGL(k_resync_part<R>, dim3(samples * groups * kResyncParts), dim3(256), lds, st, P, sh, group,
+                       groups);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resync_fin<R>, dim3(n_copies), dim3(64), 0, st, P, sh, mode);
     return hipGetLastError();
 }
 hipError_t launch_resync(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int mode, hipStream_t st) {
