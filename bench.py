@@ -226,7 +226,7 @@ def batched(args):
     v0, b0, t0_ = run("built-in tiles")
     log("autotuning")
     t_tune = time.perf_counter()
-    n_trials = rlpt.autotune(graphs, temps, sweeps_per_trial=3, **kw)
+    n_trials = rlpt.autotune(graphs, temps, sweeps_per_trial=10, **kw)
     t_tune = time.perf_counter() - t_tune
     v1, b1, t1_ = run("tuned tiles")
     # the tuner times every trial on the whole launch: per N, the trial of the chosen tile

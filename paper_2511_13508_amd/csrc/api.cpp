@@ -486,15 +486,27 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
         std::stable_sort(items.begin(), items.end(), [&](const ItemDev& x, const ItemDev& y) {
             return x.first_copy - x.sample * c->Rc < y.first_copy - y.sample * c->Rc;
         });
-    } else if (c->S > 1 && *std::min_element(c->N.begin(), c->N.end()) == c->max_N) {
-        // one N: deal the samples' items round robin.  Workgroups go to the eight
-        // XCDs in turn, so an XCD then holds the copies of few samples and its L2
-        // sees only their lists (with eight samples: one sample per XCD)
+    } else {
+        // within each N class (classes stay in decreasing N), deal the samples'
+        // items round robin.  Workgroups go to the eight XCDs in turn, so an XCD
+        // then holds the copies of few samples and its L2 sees only their lists
+        // (eight samples of one N: one sample per XCD)
         std::vector<ItemDev> rr;
         rr.reserve(items.size());
-        const size_t per = items.size() / c->S;  // equal item counts: same N, same tile
-        for (size_t k = 0; k < per; ++k)
-            for (int s2 = 0; s2 < c->S; ++s2) rr.push_back(items[(size_t)s2 * per + k]);
+        size_t b = 0;
+        while (b < items.size()) {
+            const int n_cls = c->N[items[b].sample];
+            size_t e = b;
+            while (e < items.size() && c->N[items[e].sample] == n_cls) ++e;
+            // [b, e): the class's samples in turn, each with the same item count (same N, same tile)
+            std::vector<size_t> start;
+            for (size_t i = b; i < e; ++i)
+                if (i == b || items[i].sample != items[i - 1].sample) start.push_back(i);
+            const size_t per = (e - b) / start.size();
+            for (size_t k = 0; k < per; ++k)
+                for (size_t st = 0; st < start.size(); ++st) rr.push_back(items[start[st] + k]);
+            b = e;
+        }
         items.swap(rr);
     }
     const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached, c->sh.short_lists);
