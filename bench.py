@@ -426,6 +426,61 @@ def n64_physics(args, rlpt, torch, out, sweeps=100000):
     log(f"N=64 physics: {sweeps} sweeps in {el:.1f} s, C_V peak at T={temps[pk]:.3f}")
 
 
+def n64_protocol(args, rlpt, torch, out, cv_per_mode, sweeps=32768, ladder_sweeps=20000):
+    """The paper's run protocol on the N = 64 configuration (sec. III.B, App. A):
+    the doubling-window thermalisation check (energy means over sweeps
+    [2^k, 2^(k+1)) from a random start, sample-averaged, at the coldest bath,
+    the specific-heat peak and the hottest bath), and the ladder adapted to the
+    measured specific heat (eq. PT_Ti, C = 0.6) run beside the geometric one:
+    swap acceptance across the ladder (the rule spaces temperatures so that
+    neighbouring energy distributions overlap alike)."""
+    N, S, T = 64, 8, 24
+    temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
+    graphs = [rlpt.Graph(N, SEED_BASE + 100 + mu) for mu in range(S)]
+    ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=2, precision=rlpt.FP32, swap_interval=1,
+                       resync_interval=100, measure_start=0, measure_interval=1, n_bins=100, series_len=sweeps)
+    ctx.init(4)
+    ctx.run_graph(100, sweeps // 100)
+    ctx.sweep(sweeps % 100)
+    ctx.check()
+    o = ctx.observables()
+    ctx.close()
+    pk = 2 + int(np.argmax(np.asarray(cv_per_mode)[2:T - 2]))
+    windows = {}
+    for t in (0, pk, T - 1):
+        per = [rlpt.window_means(o["series_e"][mu, t, :sweeps])[0] for mu in range(S)]
+        m = np.array(per) / N
+        windows[f"{temps[t]:.4f}"] = {"E_per_mode": np.round(m.mean(axis=0), 4).tolist()[-6:],
+                                       "err": np.round(m.std(axis=0, ddof=1) / np.sqrt(S), 4).tolist()[-6:]}
+    starts = rlpt.window_means(o["series_e"][0, 0, :sweeps])[1].tolist()[-6:]
+
+    def swap_rates(ladder):
+        Tn = len(ladder)
+        c2 = rlpt.Context(graphs, ladder, n_temps=Tn, n_reps=2, precision=rlpt.FP32, swap_interval=1,
+                          resync_interval=100, measure_start=ladder_sweeps // 2, measure_interval=1, n_bins=10)
+        c2.init(5)
+        c2.run_graph(100, ladder_sweeps // 200)
+        c2.run_graph(100, ladder_sweeps // 200)
+        c2.check()
+        r = rlpt.summarize(c2.observables(), N, ladder)["swap_rate"]
+        c2.close()
+        return r
+
+    adapt = rlpt.adaptive_ladder(temps, np.asarray(cv_per_mode) * N, 0.3, 1.5, c=0.6)
+    r_geo, r_ad = swap_rates(temps), swap_rates(adapt)
+    out["n64_protocol"] = {
+        "doubling_windows": {"window_starts": starts, "at_T": windows,
+                             "note": "energy per mode averaged over sweeps [start_k, start_{k+1}), last six windows"},
+        "adaptive_ladder": {"C": 0.6, "temperatures": np.round(adapt, 4).tolist(), "n": int(len(adapt)),
+                            "swap_rate_min_max": [float(r_ad.min()), float(r_ad.max())],
+                            "swap_rate_std": float(r_ad.std())},
+        "geometric_ladder": {"n": T, "swap_rate_min_max": [float(r_geo.min()), float(r_geo.max())],
+                             "swap_rate_std": float(r_geo.std())},
+    }
+    log(f"N=64 protocol: adaptive ladder {len(adapt)} temperatures, swap rates "
+        f"{r_ad.min():.2f}-{r_ad.max():.2f} (geometric {r_geo.min():.2f}-{r_geo.max():.2f})")
+
+
 def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweeps=20000, warm=2000,
                 harvest_rounds=6250, train_steps=1000, reeq=5000, at="peak", train=True):
     """The learned-proposal configuration: N = 64, 8 samples x 24 temperatures
@@ -727,6 +782,7 @@ def main():
         n64_configuration(args, rlpt, torch, out)
         if not args.no_n64:
             n64_physics(args, rlpt, torch, out)
+            n64_protocol(args, rlpt, torch, out, out["n64_physics"]["cv_per_mode"])
     if args.tau_sweeps > 0 and args.learn_temps and not args.no_n64:
         learned_n64(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
