@@ -41,7 +41,7 @@ enum {
     RLPT_E_NOMEM = -2,       /* host allocation failed or workspace too small */
     RLPT_E_HIP = -3,         /* a HIP runtime call failed */
     RLPT_E_STATE = -4,       /* NaN or energy / constraint drift found at a resync */
-    RLPT_E_UNSUPPORTED = -5  /* option not supported by this build */
+    RLPT_E_UNSUPPORTED = -5  /* option the library does not support (e.g. learned moves in FP64) */
 };
 
 enum { RLPT_OMEGA_RANDOM = 0, RLPT_OMEGA_COMB = 1 };
