@@ -618,7 +618,7 @@ def main():
     ap.add_argument("--copies-per-block", type=int, default=0)
     ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 packed (8 B/entry), 2 chunked (6.25 B/entry)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--tau-sweeps", type=int, default=6000, help="extra sweeps per run for tau_int (0: skip)")
+    ap.add_argument("--tau-sweeps", type=int, default=20000, help="extra sweeps per run for tau_int (0: skip)")
     ap.add_argument("--learn-temps", type=lambda v: [int(x) for x in v.split(",")] if v else [],
                     default=[25, 26, 27, 28], help="temperature indices with learned global moves")
     ap.add_argument("--learn-scale", type=float, default=0.05)
