@@ -149,9 +149,10 @@ typedef struct rlpt_config {
                                  terms holding both j and k (12 entries per term in all) and
                                  streams the two lists only when accepted, to update the fields
                                  it changes.  Same chain, same draws; results agree with the
-                                 streaming sweep up to rounding order (the field updates are
-                                 LDS atomics).  Fields are recomputed from scratch at init,
-                                 every recomputation, rlpt_set_state and learned rounds.
+                                 streaming sweep up to rounding order (each target's field
+                                 change is gathered in a fixed order).  Fields are recomputed
+                                 from scratch at init, every recomputation, rlpt_set_state and
+                                 learned rounds.
                                  Needs 12 * n_terms more list entries of 4 + 4|8 bytes and
                                  (N^2 + 1) * 4 bytes per sample. */
     int32_t rho;              /* global constraint sum_k |a_k|^rho = N (eq. SmoothedCubic): 4 (default;

@@ -5,7 +5,7 @@ The cached sweep keeps every copy's local fields in LDS / HBM and updates
 them on acceptance instead of recomputing F_j, F_k from the lists at every
 two-mode update.  It runs the same chain on the same draws as the streaming
 sweep (sec. III.A), so the oracle's trajectories are the reference; the
-field updates are LDS atomics, so agreement is up to rounding order:
+fields are updated by fixed-order gathers, so agreement is up to rounding order:
 FP64 states within 1e-9 and every discrete decision exact, as for the
 streaming path.
 """
