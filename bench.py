@@ -72,6 +72,9 @@ PROFILE_CMDS = {
            "--steps 50",
     "ktl": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/ktl -o ktl -- python bench.py --workload learned64 "
            "--steps 2000",
+    "pmc64": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_LDS SQ_INSTS_VALU SQ_WAVE_CYCLES "
+             "SQ_BUSY_CYCLES SQ_INSTS_SALU --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmc64 -o pmc -- "
+             "python bench.py --workload n64",
     "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmc_{C} -o pmc -- python bench.py "
            "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
     "cal": "rocprofv3 --pmc {C} -f csv -d {OUT}/cal_{C} -o cal -- python bench.py --copy-calibration",
@@ -156,6 +159,20 @@ def summarize_profiles(d):
             bl.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
                       f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
         with open(os.path.join(ROOT, "profiles", fname), "w") as f:
+            f.write("\n".join(bl) + "\n")
+    pmc64 = os.path.join(d, "pmc64", "pmc_counter_collection.csv")
+    if os.path.exists(pmc64):
+        acc = {}
+        kname = ""
+        for r in rows(pmc64):
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            kname = r["Kernel_Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
+        bl = ["# rocprofv3 SQ counters of the sweep kernel, N=64 configuration (8 samples x 24 T x 2 replicas, 384 "
+              "copies, 512 threads per copy), mean per dispatch", "# command (from the repository root):",
+              "#   " + cmd("pmc64"), f"# kernel: {kname}", ""]
+        for k in sorted(acc):
+            bl.append(f"{k:<24} {sum(acc[k]) / len(acc[k]):>16.1f}   ({len(acc[k])} dispatches)")
+        with open(os.path.join(ROOT, "profiles", "sweep_n64_sq_counters.txt"), "w") as f:
             f.write("\n".join(bl) + "\n")
     if have_headline:
         with open(TRAFFIC_FILE, "w") as f:
@@ -630,9 +647,10 @@ def main():
     ap.add_argument("--no-n64", action="store_true", help="skip the N=64 physics run and learned comparison")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
-    ap.add_argument("--workload", choices=["n256", "batched", "learned64"], default="n256",
+    ap.add_argument("--workload", choices=["n256", "batched", "learned64", "n64"], default="n256",
                     help="n256: the headline configuration; batched: the uneven-N configuration with autotuning; "
-                         "learned64: only the N=64 learned-proposal comparison")
+                         "learned64: only the N=64 learned-proposal comparison; n64: only the N=64 configuration's "
+                         "rate")
     ap.add_argument("--n64-learn-at", choices=["peak", "cold"], default="peak",
                     help="learned64 workload: networks around the C_V peak or on the four coldest temperatures")
     ap.add_argument("--n64-untrained", action="store_true",
@@ -654,6 +672,11 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         batched(args)
+        return
+    if args.workload == "n64":
+        res = {}
+        n64_configuration(args, rlpt, torch, res)
+        print(json.dumps(res["n64_configuration"]), flush=True)
         return
     if args.workload == "learned64":
         res = {}
