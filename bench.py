@@ -202,7 +202,19 @@ def cpu_baseline(N, temps, n_reps, budget_s, n_threads):
     v1, what1, el1 = rate(1, budget_s / 2)
     return {"value": v, "unit": "mode-updates/s", "cores": n_threads, "kind": "oracle",
             "sample": f"sample 0 of the workload: {what} (N={N}, {og.n_terms} terms), FP64, {el:.1f} s",
-            "value_1_core": v1, "sample_1_core": f"{what1}, {el1:.1f} s"}
+            "value_1_core": v1, "sample_1_core": f"{what1}, {el1:.1f} s",
+            "cpu_model": cpu_model(), "cpus_available": len(os.sched_getaffinity(0)), "nproc": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def batched(args):

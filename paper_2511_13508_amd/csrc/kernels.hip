@@ -207,6 +207,17 @@ __device__ inline void mode_field(const DevPtrs<R>& P, const SampleDev& sd, int 
     }
 }
 
+// the same from list bounds staged in LDS (lb[l], lb[l + 1] for mode l): the
+// step's first global load is then the list itself
+template <typename R, int LAYOUT>
+__device__ inline void mode_field_lds(const DevPtrs<R>& P, const uint32_t* lb, int l, const R2<R>* __restrict__ a,
+                                      int t, int nt, R& fr, R& fi) {
+    if constexpr (LAYOUT == kLayoutChunked)
+        field_partial_chunk<R>(P.cx, P.cyz, P.cJ, lb[l], lb[l + 1], a, t, nt, fr, fi);
+    else
+        field_partial<R>(P.idx, P.J, lb[l], lb[l + 1], a, t, nt, fr, fi);
+}
+
 // workgroup barrier that waits for LDS operations only (s_waitcnt lgkmcnt(0)
 // with vmcnt and expcnt at their maxima, 0xC07F): global loads issued before
 // it stay in flight.  Only for loops whose global memory traffic is loads.
@@ -217,7 +228,7 @@ __device__ inline void block_sync_lds() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// list chunks of one mode held in registers, a step ahead: thread t of a
+// list chunks of one mode held in registers ahead of their step: thread t of a
 // group of nt owns chunks beg + t + m * nt, m < PF (the host picks PF so that
 // every list of the launch fits); consumed in the order the streaming loop
 // of field_partial_chunk would take them
@@ -230,11 +241,10 @@ struct ChunkRegs {
 };
 
 template <typename R, int PF>
-__device__ inline void chunk_prefetch(const DevPtrs<R>& P, const SampleDev& sd, int l, int t, int nt,
+__device__ inline void chunk_prefetch(const DevPtrs<R>& P, const uint32_t* lb, int l, int t, int nt,
                                       ChunkRegs<R, PF>& rg) {
     using JT = typename J4<R>::T;
-    const uint32_t* cs = P.chunk_start + sd.mode_base;
-    const uint32_t beg = cs[l], end = cs[l + 1];
+    const uint32_t beg = lb[l], end = lb[l + 1];
     const JT* __restrict__ Jv = reinterpret_cast<const JT*>(P.cJ);
     rg.n = 0;
 #pragma unroll
@@ -305,6 +315,9 @@ __device__ inline StepDraw<R> draw_step(uint64_t seed, int64_t pair_stream, int6
     return d;
 }
 
+// LDS bytes of the sample's list bounds (max_N + 1 offsets), ahead of the copy groups
+__host__ __device__ inline size_t bounds_bytes(int max_N) { return ((size_t)(max_N + 1) * 4 + 15) & ~(size_t)15; }
+
 // LDS bytes of one copy group: amplitudes of max_N modes + step tables + reduction slots
 template <typename R>
 __host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
@@ -315,9 +328,9 @@ __host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
 }
 
 // PF > 0 (chunked lists short enough for PF chunks per thread): a step's list
-// chunks are loaded into registers during the previous step, and the step
-// loop's barriers wait for LDS only, so the loads stay in flight across the
-// reduction, the decision and both barriers.  Same chain, same arithmetic.
+// chunks are loaded into registers two steps earlier, and the step loop's
+// barriers wait for LDS only, so the loads stay in flight across two steps'
+// reductions, decisions and barriers.  Same chain, same arithmetic.
 template <typename R, int BLOCK, int LAYOUT, int PF>
 __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -334,10 +347,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     const int nt = wpc * 64;
     const int gsel = active ? g : 0;
 
-    unsigned char* base = smem + (size_t)gsel * group_bytes<R>(max_N, kWaves);
+    uint32_t* lb = reinterpret_cast<uint32_t*>(smem);  // list bounds of the item's sample
+    unsigned char* base = smem + bounds_bytes(max_N) + (size_t)gsel * group_bytes<R>(max_N, kWaves);
     R2<R>* a = reinterpret_cast<R2<R>*>(base);
     StepDraw<R>* tab = reinterpret_cast<StepDraw<R>*>(base + (size_t)max_N * 2 * sizeof(R));
     R* red = reinterpret_cast<R*>(base + (size_t)max_N * 2 * sizeof(R) + (size_t)(max_N / 2 + 1) * sizeof(StepDraw<R>));
+    {
+        const uint32_t* gb = (LAYOUT == kLayoutChunked ? P.chunk_start : P.mode_start) + sd.mode_base;
+        for (int i = threadIdx.x; i <= N; i += BLOCK) lb[i] = gb[i];  // visible after the sweep loop's first barrier
+    }
 
     const int c = it.first_copy + gsel;
     const int64_t local = c - (int64_t)it.sample * sh.copies_per_sample;
@@ -352,7 +370,70 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     const int64_t sweep0 = P.counters->sweeps_done;
 
     R2<R> ajo = mk2<R>(0, 0), ajn = mk2<R>(0, 0), akn = mk2<R>(0, 0);
-    ChunkRegs<R, (PF > 0 ? PF : 1)> pj, pk;  // next step's chunks (PF > 0)
+    // PF > 0: chunks of steps s (set A for even s, B for odd s) and s + 1 in
+    // registers; step s consumes its set and refills it with step s + 2
+    using Regs = ChunkRegs<R, (PF > 0 ? PF : 1)>;
+    Regs pjA, pkA, pjB, pkB;
+    auto run_step = [&](int s, Regs& rj, Regs& rk) {
+        if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
+        R fjr = 0, fji = 0, fkr = 0, fki = 0;
+        if (active) {
+            if constexpr (PF > 0) {
+                chunk_consume<R, PF>(rj, a, fjr, fji);
+                chunk_consume<R, PF>(rk, a, fkr, fki);
+                if (s + 2 < steps) {
+                    chunk_prefetch<R, PF>(P, lb, tab[s + 2].jk & 0xffff, gt, nt, rj);
+                    chunk_prefetch<R, PF>(P, lb, tab[s + 2].jk >> 16, gt, nt, rk);
+                }
+            } else {
+                const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
+                mode_field_lds<R, LAYOUT>(P, lb, j, a, gt, nt, fjr, fji);
+                mode_field_lds<R, LAYOUT>(P, lb, k, a, gt, nt, fkr, fki);
+            }
+        }
+        fjr = wave_sum(fjr);
+        fji = wave_sum(fji);
+        fkr = wave_sum(fkr);
+        fki = wave_sum(fki);
+        if (active && lane == 0) {
+            red[4 * gw + 0] = fjr;
+            red[4 * gw + 1] = fji;
+            red[4 * gw + 2] = fkr;
+            red[4 * gw + 3] = fki;
+        }
+        if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
+        if (active && gt == 0) {
+            R2<R> Fj = mk2<R>(0, 0), Fk = mk2<R>(0, 0);
+            for (int w = 0; w < wpc; ++w) {
+                Fj.x += red[4 * w + 0];
+                Fj.y += red[4 * w + 1];
+                Fk.x += red[4 * w + 2];
+                Fk.y += red[4 * w + 3];
+            }
+            const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
+            const R2<R> ako = a[k];
+            const R dE = pair_delta<R>(ajo, ajn, ako, akn, Fj, Fk);
+            const bool accept = (dE <= (R)0) || (tab[s].u < exp(-beta * dE));
+            if (accept) {
+                a[k] = akn;
+                E += dE;
+                ++n_acc;
+            } else {
+                a[j] = ajo;
+            }
+            if (s + 1 < steps) {  // snapshot of the next step
+                const StepDraw<R> d = tab[s + 1];
+                const int j2 = d.jk & 0xffff, k2 = d.jk >> 16;
+                ajo = a[j2];
+                const R2<R> ako2 = a[k2];
+                const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
+                const R K = sh.rho == 2 ? sqrt(uj + uk) : sqrt(sqrt(uj * uj + uk * uk));
+                ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
+                akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
+                a[j2] = ajn;
+            }
+        }
+    };
     for (int sw = 0; sw < n_sweeps; ++sw) {
         __syncthreads();
         if (active)
@@ -360,8 +441,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
         __syncthreads();
         if constexpr (PF > 0) {
             if (active) {
-                chunk_prefetch<R, PF>(P, sd, tab[0].jk & 0xffff, gt, nt, pj);
-                chunk_prefetch<R, PF>(P, sd, tab[0].jk >> 16, gt, nt, pk);
+                chunk_prefetch<R, PF>(P, lb, tab[0].jk & 0xffff, gt, nt, pjA);
+                chunk_prefetch<R, PF>(P, lb, tab[0].jk >> 16, gt, nt, pkA);
+                if (steps > 1) {
+                    chunk_prefetch<R, PF>(P, lb, tab[1].jk & 0xffff, gt, nt, pjB);
+                    chunk_prefetch<R, PF>(P, lb, tab[1].jk >> 16, gt, nt, pkB);
+                }
             }
         }
         if (active && gt == 0) {  // snapshot of step 0
@@ -374,66 +459,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
             akn = mk2<R>(K * tab[0].sk * tab[0].ekr, K * tab[0].sk * tab[0].eki);
             a[j] = ajn;
         }
-        for (int s = 0; s < steps; ++s) {
-            if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
-            R fjr = 0, fji = 0, fkr = 0, fki = 0;
-            if (active) {
-                if constexpr (PF > 0) {
-                    chunk_consume<R, PF>(pj, a, fjr, fji);
-                    chunk_consume<R, PF>(pk, a, fkr, fki);
-                    if (s + 1 < steps) {
-                        chunk_prefetch<R, PF>(P, sd, tab[s + 1].jk & 0xffff, gt, nt, pj);
-                        chunk_prefetch<R, PF>(P, sd, tab[s + 1].jk >> 16, gt, nt, pk);
-                    }
-                } else {
-                    const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
-                    mode_field<R, LAYOUT>(P, sd, j, a, gt, nt, fjr, fji);
-                    mode_field<R, LAYOUT>(P, sd, k, a, gt, nt, fkr, fki);
-                }
-            }
-            fjr = wave_sum(fjr);
-            fji = wave_sum(fji);
-            fkr = wave_sum(fkr);
-            fki = wave_sum(fki);
-            if (active && lane == 0) {
-                red[4 * gw + 0] = fjr;
-                red[4 * gw + 1] = fji;
-                red[4 * gw + 2] = fkr;
-                red[4 * gw + 3] = fki;
-            }
-            if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
-            if (active && gt == 0) {
-                R2<R> Fj = mk2<R>(0, 0), Fk = mk2<R>(0, 0);
-                for (int w = 0; w < wpc; ++w) {
-                    Fj.x += red[4 * w + 0];
-                    Fj.y += red[4 * w + 1];
-                    Fk.x += red[4 * w + 2];
-                    Fk.y += red[4 * w + 3];
-                }
-                const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
-                const R2<R> ako = a[k];
-                const R dE = pair_delta<R>(ajo, ajn, ako, akn, Fj, Fk);
-                const bool accept = (dE <= (R)0) || (tab[s].u < exp(-beta * dE));
-                if (accept) {
-                    a[k] = akn;
-                    E += dE;
-                    ++n_acc;
-                } else {
-                    a[j] = ajo;
-                }
-                if (s + 1 < steps) {  // snapshot of the next step
-                    const StepDraw<R> d = tab[s + 1];
-                    const int j2 = d.jk & 0xffff, k2 = d.jk >> 16;
-                    ajo = a[j2];
-                    const R2<R> ako2 = a[k2];
-                    const R uj = ajo.x * ajo.x + ajo.y * ajo.y, uk = ako2.x * ako2.x + ako2.y * ako2.y;
-                    const R K = sh.rho == 2 ? sqrt(uj + uk) : sqrt(sqrt(uj * uj + uk * uk));
-                    ajn = mk2<R>(K * d.cj * d.ejr, K * d.cj * d.eji);
-                    akn = mk2<R>(K * d.sk * d.ekr, K * d.sk * d.eki);
-                    a[j2] = ajn;
-                }
-            }
+        int s = 0;
+        for (; s + 1 < steps; s += 2) {
+            run_step(s, pjA, pkA);
+            run_step(s + 1, pjB, pkB);
         }
+        if (s < steps) run_step(s, pjA, pkA);
     }
     __syncthreads();
     if (active) {
@@ -1404,8 +1435,8 @@ size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item
     if (cached)
         return (size_t)max_copies_per_item * (precision == RLPT_FP64 ? group_bytes_cached<double>(max_N, waves)
                                                                      : group_bytes_cached<float>(max_N, waves));
-    return (size_t)max_copies_per_item *
-           (precision == RLPT_FP64 ? group_bytes<double>(max_N, waves) : group_bytes<float>(max_N, waves));
+    return bounds_bytes(max_N) + (size_t)max_copies_per_item * (precision == RLPT_FP64 ? group_bytes<double>(max_N, waves)
+                                                                                       : group_bytes<float>(max_N, waves));
 }
 
 template <typename R>
