@@ -11,9 +11,10 @@ and already resident in HBM when timing starts.
 
 Prints one JSON line.  ``value`` = mode-updates/s (N mode-updates per copy
 per sweep) over the timed steps.  ``roofline`` describes the sweep kernel:
-algorithmic bytes per launch (8 B per list entry streamed: packed indices +
-FP32 coupling) over its mean duration measured with HIP events on the
-context's stream.  ``cpu_baseline`` times the CPU FP64 oracle on a bounded
+algorithmic bytes per launch (every list entry a step streams: 6.25 B in
+the chunked layout, 25 B per chunk of 4 entries sharing their partner mode;
+8 B in the packed one) over its mean duration measured with HIP events on
+the context's stream.  ``cpu_baseline`` times the CPU FP64 oracle on a bounded
 slice of the same workload (sample 0, all 80 copies, whole sweeps for ~10 s).
 """
 from __future__ import annotations
@@ -738,12 +739,22 @@ def main():
         return np.array([float(np.median([rlpt.tau_int(series[mu, t, lo:m])[0] for mu in range(S)]))
                          for t in t_idx])
 
-    def tau_block(ctx, sweeps_per_s, t_idx, extra_sweeps):
+    def long_run(ctx, n, tag):
+        """n sweeps in pieces of 10,000, a progress line after each"""
+        done = 0
+        while done < n:
+            k = min(10000, n - done)
+            ctx.sweep(k)
+            ctx.check()
+            done += k
+            if n > 10000:
+                log(f"{tag}: {done}/{n} sweeps")
+
+    def tau_block(ctx, sweeps_per_s, t_idx, extra_sweeps, tag):
         """continue extra_sweeps sweeps, then tau_int of E at the temperature
         indices t_idx from the series (first quarter discarded), median over samples"""
         if extra_sweeps > 0:
-            ctx.sweep(extra_sweeps)
-            ctx.check()
+            long_run(ctx, extra_sweeps, tag)
         o = ctx.observables()
         m = int(o["e_n"][0, 0] / reps)
         m = min(m, series_len)
@@ -776,7 +787,7 @@ def main():
     tau_plain = None
     if args.tau_sweeps > 0:
         log(f"plain: {args.tau_sweeps} more sweeps for tau_int")
-        tau_plain = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps)
+        tau_plain = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps, "plain")
     ctx.close()
     out = {
         "metric": METRIC,
@@ -828,7 +839,7 @@ def main():
         if not args.shared_pairs:
             ctx = rlpt.Context(graphs, temps, shared_pairs=1, **common)
             el2, _, _ = timed(ctx, "shared pairs")
-            tau["shared_pairs"] = tau_block(ctx, args.steps / el2, t_learn, args.tau_sweeps)
+            tau["shared_pairs"] = tau_block(ctx, args.steps / el2, t_learn, args.tau_sweeps, "shared pairs")
             tau["shared_pairs"]["mode_updates_per_s"] = N * n_copies * args.steps / el2
             ctx.close()
         # ------------------------------------------------------------ learned global moves
@@ -857,8 +868,7 @@ def main():
             log(f"learned: {args.steps / el3:.1f} sweeps/s; tau_int run")
             # measurements started at the warm-up boundary: the series covers harvest + learned sweeps;
             # tau is taken over the learned part only
-            ctx.sweep(args.tau_sweeps)
-            ctx.check()
+            long_run(ctx, args.tau_sweeps, "learned")
             o = ctx.observables()
             m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds + args.reeq)
             lo = max(done - args.warmup, 0) + (m - max(done - args.warmup, 0)) // 4
