@@ -388,16 +388,21 @@ def n64_configuration(args, rlpt, torch, out):
     ctx.init(1)
     ctx.sweep(args.warmup)
     torch.cuda.synchronize()
-    ctx.sweep_timing(True)
+    # wall clock without events (a sweep here is ~80 us, and two event records
+    # per launch would add several); then the same number of sweeps with HIP
+    # events around each sweep launch for the kernel's own time
     t0 = time.perf_counter()
     ctx.sweep(args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ctx.sweep_timing(True)
+    ctx.sweep(args.steps)
+    torch.cuda.synchronize()
     ctx.check()
     kms, launches = ctx.sweep_time()
     steps = N // 2
     out["n64_configuration"] = {"copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.steps / el,
-                                "ms_per_launch": kms / launches,
+                                "us_per_sweep_wall": el / args.steps * 1e6, "ms_per_launch": kms / launches,
                                 "us_per_two_mode_step": kms / launches * 1e3 / steps}
     ctx.close()
     log(f"N=64 configuration: {out['n64_configuration']['mode_updates_per_s']:.4g} mode-updates/s")
