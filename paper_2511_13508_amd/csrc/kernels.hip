@@ -1142,17 +1142,21 @@ __global__ __launch_bounds__(64) void k_resync_fin(DevPtrs<R> P, ShapeInfo sh, i
 
 // ---------------------------------------------------------------- replica exchange
 // one 64-thread block per ladder (sample, replica): energies of the ladder's
-// temperatures and the pairs' uniforms are staged in LDS in parallel, then one
-// lane proposes the neighbouring baths in ascending order, each accepted with
-// min[1, exp((b_i - b_{i+1})(E_i - E_{i+1}))], and the ladder is written back
+// temperatures, the pairs' uniforms and the differences b_i - b_{i+1} are
+// staged in LDS in parallel, then one lane proposes the neighbouring baths in
+// ascending order, each accepted with min[1, exp((b_i - b_{i+1})(E_i - E_{i+1}))],
+// carrying the copy that moves up in registers (no global memory access in the
+// chain); the ladder and the acceptance counts are written back in parallel
 template <typename R>
 __global__ __launch_bounds__(64) void k_swap(DevPtrs<R> P, ShapeInfo sh) {
-    extern __shared__ double sw[];  // [T] energies, [T] uniforms, [T] copy at temperature
+    extern __shared__ double sw[];  // [T] energies, [T] uniforms, [T] b_i - b_{i+1}, [T] copies, [T] accepted
     const int L = blockIdx.x;
     const int T = sh.n_temps;
-    double* e = sw;
-    double* u = sw + T;
-    int32_t* at_s = reinterpret_cast<int32_t*>(sw + 2 * T);
+    double* __restrict__ e = sw;
+    double* __restrict__ u = sw + T;
+    double* __restrict__ db = sw + 2 * T;
+    int32_t* __restrict__ at_s = reinterpret_cast<int32_t*>(sw + 3 * T);
+    int32_t* __restrict__ took = at_s + T;
     int32_t* at = P.copy_at + (size_t)L * T;
     const int64_t round = P.counters->swaps_done;
     for (int i = threadIdx.x; i < T; i += 64) {
@@ -1161,26 +1165,35 @@ __global__ __launch_bounds__(64) void k_swap(DevPtrs<R> P, ShapeInfo sh) {
         e[i] = (double)P.E[c];
         const Philox4 w = philox4x64((uint64_t)i, (uint64_t)round, (uint64_t)L, 0, sh.run_seed, kTagSwap);
         u[i] = uniform01<double>(w.v[0]);
+        db[i] = i + 1 < T ? P.beta64[i] - P.beta64[i + 1] : 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // the chain in registers: (cc, ec) is the copy and energy now at bath i;
+        // bath i + 1 still holds its own until pair i is decided
+        int cc = at_s[0];
+        double ec = e[0];
         for (int i = 0; i + 1 < T; ++i) {
-            const double x = (P.beta64[i] - P.beta64[i + 1]) * (e[i] - e[i + 1]);
-            if ((x >= 0.0) || (u[i] < exp(x))) {
-                const int ci = at_s[i];
-                at_s[i] = at_s[i + 1];
-                at_s[i + 1] = ci;
-                const double ei = e[i];
-                e[i] = e[i + 1];
-                e[i + 1] = ei;
-                P.swap_acc[(size_t)L * (T - 1) + i] += 1ull;
+            const int cn = at_s[i + 1];
+            const double en = e[i + 1];
+            const double x = db[i] * (ec - en);
+            const bool acc = (x >= 0.0) || (u[i] < exp(x));
+            took[i] = acc ? 1 : 0;
+            if (acc) {
+                at_s[i] = cn;
+            } else {
+                at_s[i] = cc;
+                cc = cn;
+                ec = en;
             }
         }
+        at_s[T - 1] = cc;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < T; i += 64) {
         at[i] = at_s[i];
         P.temp_of[at_s[i]] = i;
+        if (i + 1 < T && took[i]) P.swap_acc[(size_t)L * (T - 1) + i] += 1ull;
     }
 }
 
@@ -1472,7 +1485,7 @@ hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int
 template <typename R>
 static hipError_t swap_t(const void* ptrs, const ShapeInfo& sh, hipStream_t st) {
     const int n = sh.n_samples * sh.n_reps;
-    const size_t lds = (size_t)sh.n_temps * (2 * sizeof(double) + sizeof(int32_t)) + 16;
+    const size_t lds = (size_t)sh.n_temps * (3 * sizeof(double) + 2 * sizeof(int32_t)) + 16;
     hipLaunchKernelGGL(k_swap<R>, dim3(n), dim3(64), lds, st, *static_cast<const DevPtrs<R>*>(ptrs), sh);
     return hipGetLastError();
 }
