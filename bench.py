@@ -235,30 +235,51 @@ def batched(args):
     kw = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=0, measure_start=0,
               measure_interval=10, n_bins=100)
 
-    def run(tag):
-        ctx = rlpt.Context(graphs, temps, **kw)
+    # algorithmic bytes of one sweep launch: every copy streams, per two-mode
+    # step, the lists of j and k (all lists chunked here: 6.25 B per entry)
+    infos = [g.info() for g in graphs]
+    bytes_per_sweep = sum(reps * T * inf["deg_sum"] * 6.25 for inf in infos)
+
+    def rate(gs, ctx_kw, segments):
+        """mode-updates/s of 10-sweep HIP-graph segments, then the sweep kernel's
+        mean launch time from HIP events over 20 eager sweeps"""
+        ctx = rlpt.Context(gs, temps, **ctx_kw)
         ctx.init(1)
         ctx.run_graph(10, 2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.run_graph(10, args.steps // 10)
+        ctx.run_graph(10, segments)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        ctx.sweep_timing(True)
+        ctx.sweep(20)
+        torch.cuda.synchronize()
         ctx.check()
-        block, cp = ctx.tile()
-        tile = {int(N): int(cp[i * per_N]) for i, N in enumerate(Ns)}
-        v = mode_updates_per_sweep * (args.steps // 10 * 10) / el
-        log(f"{tag}: {v:.4g} mode-updates/s, block {block}, copies per block {tile}")
+        kms, launches = ctx.sweep_time()
+        tile = ctx.tile()
         ctx.close()
-        return v, block, tile
+        return sum(g.N for g in gs) * T * reps * segments * 10 / el, kms / launches, tile
+
+    def run(tag):
+        v, ms, (block, cp) = rate(graphs, kw, args.steps // 10)
+        tile = {int(N): int(cp[i * per_N]) for i, N in enumerate(Ns)}
+        log(f"{tag}: {v:.4g} mode-updates/s, block {block}, copies per block {tile}")
+        return v, block, tile, ms
 
     rlpt.tune_clear()
-    v0, b0, t0_ = run("built-in tiles")
+    v0, b0, t0_, ms0 = run("built-in tiles")
+    # each N class alone (its 32 samples in a launch of their own, built-in tile)
+    alone = {}
+    for i, N in enumerate(Ns):
+        vN, msN, _ = rate(graphs[i * per_N:(i + 1) * per_N], kw, args.steps // 10)
+        alone[N] = {"mode_updates_per_s": vN, "ms_per_launch": msN,
+                    "share_of_mixed_mode_updates": N * per_N / sum(g.N for g in graphs)}
+        log(f"N={N} alone: {vN:.4g} mode-updates/s, {msN:.3f} ms per sweep launch")
     log("autotuning")
     t_tune = time.perf_counter()
     n_trials = rlpt.autotune(graphs, temps, sweeps_per_trial=10, **kw)
     t_tune = time.perf_counter() - t_tune
-    v1, b1, t1_ = run("tuned tiles")
+    v1, b1, t1_, ms1 = run("tuned tiles")
     # the tuner times every trial on the whole launch: per N, the trial of the chosen tile
     per_N = {}
     for e in rlpt.tune_entries():
@@ -270,6 +291,12 @@ def batched(args):
            "copies": copies, "steps": args.steps // 10 * 10, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched uneven N: N in {32,48,64,96,128} x 32 samples x 32 temperatures x "
                                   "2 replicas, FP32, 10-sweep HIP-graph segments"},
+           "roofline": {"bound": "hbm", "kernel": "k_sweep (one launch for every N)", "unit": "GB/s",
+                        "algorithmic_bytes_per_launch": bytes_per_sweep, "ms_per_launch": ms1,
+                        "achieved": bytes_per_sweep / ms1 / 1e6, "peak": HBM_PEAK_GBS,
+                        "frac": bytes_per_sweep / ms1 / 1e6 / HBM_PEAK_GBS,
+                        "ms_per_launch_builtin_tiles": ms0},
+           "per_N_alone": alone,
            "tile_builtin": {"block": b0, "copies_per_block": t0_}, "tile_tuned": {"block": b1, "copies_per_block": t1_},
            "autotune": {"trials": n_trials, "seconds": t_tune,
                         "method": "per workgroup size, each N's copies per workgroup timed on the whole launch "
