@@ -432,6 +432,37 @@ def n64_configuration(args, rlpt, torch, out):
                                 "us_per_sweep_wall": el / args.steps * 1e6, "ms_per_launch": kms / launches,
                                 "us_per_two_mode_step": kms / launches * 1e3 / steps}
     ctx.close()
+    # latency floor: the same kernel and tile (one copy per 512-thread workgroup)
+    # at N = 32 ... 128 with the same ladder.  Up to N = 64 a step's time does
+    # not depend on the length of its lists (the list work hides under the
+    # step's chain of reductions, barriers and decision): the smallest of those
+    # times is the floor; beyond, the time grows with the entries streamed
+    pts = []
+    for n in (32, 48, 64, 96, 128):
+        gs = [rlpt.Graph(n, SEED_BASE + 100 + 10 * n + mu) for mu in range(S)]
+        c2 = rlpt.Context(gs, temps, n_temps=T, n_reps=2, precision=rlpt.FP32, swap_interval=1,
+                          resync_interval=100, measure_start=0, measure_interval=1, n_bins=100,
+                          block_threads=512, copies_per_block=1)
+        c2.init(1)
+        c2.sweep(50)
+        torch.cuda.synchronize()
+        c2.sweep_timing(True)
+        c2.sweep(200)
+        torch.cuda.synchronize()
+        c2.check()
+        ms, nl = c2.sweep_time()
+        c2.close()
+        entries = np.mean([2 * g.info()["deg_sum"] / n for g in gs])  # both lists of a step, mean
+        pts.append((n, entries, ms / nl * 1e3 / (n // 2)))
+    floor = min(p[2] for p in pts if p[0] <= 64)
+    slope = (pts[-1][2] - pts[-2][2]) / (pts[-1][1] - pts[-2][1])
+    step64 = out["n64_configuration"]["us_per_two_mode_step"]
+    out["n64_configuration"]["latency_floor"] = {
+        "method": "k_sweep at one copy per 512-thread workgroup, 8 samples x 24 T x 2 replicas at N = 32..128; "
+                  "floor = the smallest us per two-mode step over N <= 64, where the step time does not follow "
+                  "the list length; ns per entry from the two largest N",
+        "points": [{"N": p[0], "entries_per_step": round(p[1], 1), "us_per_step": round(p[2], 4)} for p in pts],
+        "us_per_step_floor": floor, "ns_per_entry_large_N": slope * 1e3, "n64_step_over_floor": step64 / floor}
     log(f"N=64 configuration: {out['n64_configuration']['mode_updates_per_s']:.4g} mode-updates/s")
 
 
