@@ -511,16 +511,29 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
     }
     const size_t lds = sweep_lds_bytes(c->cfg.precision, block, max_cpi, c->max_N, c->sh.cached, c->sh.short_lists);
     if (lds > 64 * 1024) return fail(RLPT_E_ARG, "sweep tile needs more than 64 KiB of LDS; use fewer copies per block");
-    // streaming sweep over chunked lists: hold a step's chunks in registers a step
-    // ahead when every list of the launch fits 1, 2 or 4 chunks per thread
-    int prefetch = 0;
+    // streaming sweep over chunked lists: hold a step's chunks in registers
+    // ahead when every list of the launch fits 1, 2 or 4 chunks per thread; if
+    // they still fit with each list on half of a copy's waves, split the lists
+    // that way (a wave then reduces two values per step instead of four)
+    int prefetch = 0, split = 0;
     if (c->sh.layout == kLayoutChunked && !c->sh.cached && !c->sh.short_lists && (block == 256 || block == 512)) {
-        uint32_t need = 0;
+        auto pf = [](uint32_t need) { return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0; };
+        uint32_t need = 0, need_half = 0;
+        bool halves = true;
         for (const ItemDev& it : items) {
-            const uint32_t nt = (uint32_t)(block / 64 / it.n_copies) * 64;
+            const uint32_t wpc = (uint32_t)(block / 64 / it.n_copies), nt = wpc * 64;
             need = std::max(need, (c->max_chunks[it.sample] + nt - 1) / nt);
+            if (wpc >= 2)
+                need_half = std::max(need_half, (c->max_chunks[it.sample] + nt / 2 - 1) / (nt / 2));
+            else
+                halves = false;
         }
-        prefetch = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0;
+        if (halves && pf(need_half) > 0) {
+            prefetch = pf(need_half);
+            split = 1;
+        } else {
+            prefetch = pf(need);
+        }
     }
     c->items = items;
     c->tile_copies = copies;
@@ -529,6 +542,7 @@ int build_items(rlpt_ctx* c, int block, const std::map<int, int>& copies) {
     c->launch.max_copies_per_item = max_cpi;
     c->launch.max_N = c->max_N;
     c->launch.prefetch = prefetch;
+    c->launch.split = split;
     c->launch.lds_bytes = lds;
     c->sh.by_slot = c->sh.cached;
     return RLPT_OK;

@@ -164,7 +164,8 @@ struct SweepLaunch {
     int n_items;
     int max_copies_per_item;
     int max_N;
-    int prefetch;  // chunks per thread held a step ahead (0: streamed in the step; 1, 2 or 4)
+    int prefetch;  // chunks per thread held ahead of their step (0: streamed in the step; 1, 2 or 4)
+    int split;     // prefetch > 0: half of a copy's waves sum each mode's list
     size_t lds_bytes;
 };
 

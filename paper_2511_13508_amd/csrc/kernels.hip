@@ -88,11 +88,36 @@ __device__ inline R row_sum(R v) {
     return v;
 }
 
+// row broadcasts (DPP row_bcast:15 = 0x142 into rows 1 and 3, row_bcast:31 =
+// 0x143 into rows 2 and 3); lanes of the other rows receive 0
+template <int CTRL, int ROWS>
+__device__ inline float dpp_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ inline double dpp_bcast(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // sum over the wave, the same value in every lane (all lanes active)
 template <typename R>
 __device__ inline R wave_sum(R v) {
     v = row_sum(v);
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// the same sum, valid in lane 63 only, without lane reads: rows 1 and 3 add
+// the totals of rows 0 and 2, then row 3 adds row 1's; (r3 + r2) + (r1 + r0)
+// rounds exactly as wave_sum's (r0 + r1) + (r2 + r3)
+template <typename R>
+__device__ inline R wave_sum_last(R v) {
+    v = row_sum(v);
+    v += dpp_bcast<0x142, 0xA>(v);
+    v += dpp_bcast<0x143, 0xC>(v);
+    return v;
 }
 
 // contribution J conj(a_x) a_y a_z of one packed entry
@@ -331,7 +356,7 @@ __host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
 // chunks are loaded into registers two steps earlier, and the step loop's
 // barriers wait for LDS only, so the loads stay in flight across two steps'
 // reductions, decisions and barriers.  Same chain, same arithmetic.
-template <typename R, int BLOCK, int LAYOUT, int PF>
+template <typename R, int BLOCK, int LAYOUT, int PF, bool SPLIT>
 __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kWaves = BLOCK / 64;
@@ -346,6 +371,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     const int gt = threadIdx.x - g * wpc * 64;
     const int nt = wpc * 64;
     const int gsel = active ? g : 0;
+    // halves (SPLIT, with PF > 0; the host sets it only when every item has two
+    // or more waves per copy): the copy's first wpc/2 waves sum mode j's list
+    // and the others mode k's, so a wave holds one list's chunks and reduces two
+    // values, not four; lt of lnt is the thread's place in its half
+    constexpr bool halves = SPLIT && PF > 0;
+    const bool on_k = halves && gw >= wpc / 2;
+    const int lnt = halves ? nt / 2 : nt;
+    const int lt = on_k ? gt - lnt : gt;
 
     uint32_t* lb = reinterpret_cast<uint32_t*>(smem);  // list bounds of the item's sample
     unsigned char* base = smem + bounds_bytes(max_N) + (size_t)gsel * group_bytes<R>(max_N, kWaves);
@@ -379,11 +412,26 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
         R fjr = 0, fji = 0, fkr = 0, fki = 0;
         if (active) {
             if constexpr (PF > 0) {
-                chunk_consume<R, PF>(rj, a, fjr, fji);
-                chunk_consume<R, PF>(rk, a, fkr, fki);
-                if (s + 2 < steps) {
-                    chunk_prefetch<R, PF>(P, lb, tab[s + 2].jk & 0xffff, gt, nt, rj);
-                    chunk_prefetch<R, PF>(P, lb, tab[s + 2].jk >> 16, gt, nt, rk);
+                if (halves) {  // this half's list only, in rj
+                    R fr = 0, fi = 0;
+                    chunk_consume<R, PF>(rj, a, fr, fi);
+                    if (s + 2 < steps)
+                        chunk_prefetch<R, PF>(P, lb, on_k ? (tab[s + 2].jk >> 16) : (tab[s + 2].jk & 0xffff), lt,
+                                              lnt, rj);
+                    if (on_k) {
+                        fkr = fr;
+                        fki = fi;
+                    } else {
+                        fjr = fr;
+                        fji = fi;
+                    }
+                } else {
+                    chunk_consume<R, PF>(rj, a, fjr, fji);
+                    chunk_consume<R, PF>(rk, a, fkr, fki);
+                    if (s + 2 < steps) {
+                        chunk_prefetch<R, PF>(P, lb, tab[s + 2].jk & 0xffff, gt, nt, rj);
+                        chunk_prefetch<R, PF>(P, lb, tab[s + 2].jk >> 16, gt, nt, rk);
+                    }
                 }
             } else {
                 const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
@@ -391,24 +439,44 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
                 mode_field_lds<R, LAYOUT>(P, lb, k, a, gt, nt, fkr, fki);
             }
         }
-        fjr = wave_sum(fjr);
-        fji = wave_sum(fji);
-        fkr = wave_sum(fkr);
-        fki = wave_sum(fki);
-        if (active && lane == 0) {
-            red[4 * gw + 0] = fjr;
-            red[4 * gw + 1] = fji;
-            red[4 * gw + 2] = fkr;
-            red[4 * gw + 3] = fki;
+        if (halves) {
+            const R r0 = wave_sum_last(on_k ? fkr : fjr);
+            const R r1 = wave_sum_last(on_k ? fki : fji);
+            if (active && lane == 63) {
+                red[2 * gw + 0] = r0;
+                red[2 * gw + 1] = r1;
+            }
+        } else {
+            fjr = wave_sum_last(fjr);
+            fji = wave_sum_last(fji);
+            fkr = wave_sum_last(fkr);
+            fki = wave_sum_last(fki);
+            if (active && lane == 63) {
+                red[4 * gw + 0] = fjr;
+                red[4 * gw + 1] = fji;
+                red[4 * gw + 2] = fkr;
+                red[4 * gw + 3] = fki;
+            }
         }
         if constexpr (PF > 0) block_sync_lds(); else __syncthreads();
         if (active && gt == 0) {
             R2<R> Fj = mk2<R>(0, 0), Fk = mk2<R>(0, 0);
-            for (int w = 0; w < wpc; ++w) {
-                Fj.x += red[4 * w + 0];
-                Fj.y += red[4 * w + 1];
-                Fk.x += red[4 * w + 2];
-                Fk.y += red[4 * w + 3];
+            if (halves) {
+                for (int w = 0; w < wpc / 2; ++w) {
+                    Fj.x += red[2 * w + 0];
+                    Fj.y += red[2 * w + 1];
+                }
+                for (int w = wpc / 2; w < wpc; ++w) {
+                    Fk.x += red[2 * w + 0];
+                    Fk.y += red[2 * w + 1];
+                }
+            } else {
+                for (int w = 0; w < wpc; ++w) {
+                    Fj.x += red[4 * w + 0];
+                    Fj.y += red[4 * w + 1];
+                    Fk.x += red[4 * w + 2];
+                    Fk.y += red[4 * w + 3];
+                }
             }
             const int j = tab[s].jk & 0xffff, k = tab[s].jk >> 16;
             const R2<R> ako = a[k];
@@ -440,7 +508,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
             for (int s = gt; s < steps; s += nt) tab[s] = draw_step<R>(sh.run_seed, pair_stream, c, sweep0 + sw, s, N, sh.rho);
         __syncthreads();
         if constexpr (PF > 0) {
-            if (active) {
+            if (active && halves) {
+                chunk_prefetch<R, PF>(P, lb, on_k ? (tab[0].jk >> 16) : (tab[0].jk & 0xffff), lt, lnt, pjA);
+                if (steps > 1)
+                    chunk_prefetch<R, PF>(P, lb, on_k ? (tab[1].jk >> 16) : (tab[1].jk & 0xffff), lt, lnt, pjB);
+            } else if (active) {
                 chunk_prefetch<R, PF>(P, lb, tab[0].jk & 0xffff, gt, nt, pjA);
                 chunk_prefetch<R, PF>(P, lb, tab[0].jk >> 16, gt, nt, pkA);
                 if (steps > 1) {
@@ -1400,28 +1472,26 @@ hipError_t launch_sweep_t(const void* ptrs, const ShapeInfo& sh, const SweepLaun
     }
     if (sh.layout == kLayoutChunked) {
         if constexpr (BLOCK == 256 || BLOCK == 512) {
-            switch (L.prefetch) {
+#define RLPT_SWEEP_PF(PFV, SPV)                                                                                   \
+    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, PFV, SPV>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, \
+                       P, sh, L.max_N, n_sweeps)
+            switch (L.prefetch * 2 + (L.split ? 1 : 0)) {
                 case 0: break;
-                case 1:
-                    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 1>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
-                                       st, P, sh, L.max_N, n_sweeps);
-                    return hipGetLastError();
-                case 2:
-                    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 2>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
-                                       st, P, sh, L.max_N, n_sweeps);
-                    return hipGetLastError();
-                case 4:
-                    hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 4>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes,
-                                       st, P, sh, L.max_N, n_sweeps);
-                    return hipGetLastError();
+                case 2: RLPT_SWEEP_PF(1, false); return hipGetLastError();
+                case 3: RLPT_SWEEP_PF(1, true); return hipGetLastError();
+                case 4: RLPT_SWEEP_PF(2, false); return hipGetLastError();
+                case 5: RLPT_SWEEP_PF(2, true); return hipGetLastError();
+                case 8: RLPT_SWEEP_PF(4, false); return hipGetLastError();
+                case 9: RLPT_SWEEP_PF(4, true); return hipGetLastError();
                 default: return hipErrorInvalidValue;
             }
+#undef RLPT_SWEEP_PF
         }
-        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 0>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
-                           L.max_N, n_sweeps);
+        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutChunked, 0, false>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st,
+                           P, sh, L.max_N, n_sweeps);
     } else {
-        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutPacked, 0>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh,
-                           L.max_N, n_sweeps);
+        hipLaunchKernelGGL((k_sweep<R, BLOCK, kLayoutPacked, 0, false>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st,
+                           P, sh, L.max_N, n_sweeps);
     }
     return hipGetLastError();
 }
