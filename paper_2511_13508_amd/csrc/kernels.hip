@@ -355,7 +355,9 @@ __host__ __device__ inline size_t group_bytes(int max_N, int waves_per_block) {
 // PF > 0 (chunked lists short enough for PF chunks per thread): a step's list
 // chunks are loaded into registers two steps earlier, and the step loop's
 // barriers wait for LDS only, so the loads stay in flight across two steps'
-// reductions, decisions and barriers.  Same chain, same arithmetic.
+// reductions, decisions and barriers.  Same chain; with SPLIT each list is
+// summed by half of the copy's waves, which groups the partial sums differently
+// (FP rounding of the fields, not the method, changes).
 template <typename R, int BLOCK, int LAYOUT, int PF, bool SPLIT>
 __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int max_N, int n_sweeps) {
     extern __shared__ __align__(16) unsigned char smem[];
