@@ -188,13 +188,19 @@ def test_trajectory_fp64_tiles(oracle, block, copies):
     compare_fp64(ctx, ors)
 
 
-@pytest.mark.parametrize("N,block,copies", [(20, 256, 1), (64, 256, 1), (128, 512, 1), (128, 512, 2)])
+@pytest.mark.parametrize("N,block,copies", [(20, 256, 1), (64, 256, 1), (128, 512, 1), (128, 512, 2),
+                                            (20, 256, 4), (32, 256, 4), (48, 256, 4)])
 def test_trajectory_fp64_chunks_a_step_ahead(oracle, N, block, copies):
-    """Chunked lists held in registers a step ahead: at most 35 chunks per list
-    at N = 20 (1 per thread of 256), 357 at N = 64 (2 per thread of 256) and
-    1428 at N = 128 (3 per thread of 512, the 4-chunk variant); N = 128 with two
-    copies per 512-thread workgroup needs 6 per thread and streams instead.
-    Every one gives the oracle's trajectory."""
+    """Chunked lists held in registers ahead of their step.  With one copy per
+    workgroup each list goes to half of the copy's waves when it still fits:
+    at most 35 chunks per list at N = 20 (1 per thread of 128) and 357 at
+    N = 64 (3 per thread of 128, the 4-chunk variant); 1428 at N = 128 would
+    need 6 per thread of 256, so both lists go to all 512 threads (3 each,
+    the 4-chunk variant); two copies per 512-thread workgroup need 6 per thread
+    and stream instead.  Four copies per 256-thread workgroup leave one wave
+    per copy, which cannot be halved: N = 20, 32 and 48 then hold 1, 2 and 3
+    chunks per thread of 64 (the 1-, 2- and 4-chunk variants).  Every one
+    gives the oracle's trajectory."""
     ctx, ors = run_pair(oracle, [N], temps_geo(0.5, 1.2, 3), 20, 13, n_reps=2, precision=rlpt.FP64,
                         block_threads=block, copies_per_block=copies, resync_interval=0, n_bins=10,
                         list_layout=CH)
