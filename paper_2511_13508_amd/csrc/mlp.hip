@@ -181,6 +181,114 @@ hipError_t gemm(const Gemm<TB>& g, int nets, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ fused inference forward
+// MFMA fragment order of a weight matrix W [K][n] (K % 16 == 0, columns padded
+// to a multiple of 16): the B operand of v_mfma_f32_16x16x16_bf16 for column
+// block nb and K step ks is W[16 ks + 4 (l / 16) + i][16 nb + l % 16] in lane l,
+// slot i; those 64 x 4 elements are stored consecutively (lane-major), so one
+// wave reads a fragment as 512 contiguous bytes
+__host__ __device__ inline int64_t frag_at(int64_t base, int K, int k, int n) {
+    return base + (((int64_t)(n / 16) * (K / 16) + k / 16) * 64 + (n % 16) + 16 * ((k % 16) / 4)) * 4 + (k % 4);
+}
+__host__ __device__ inline int64_t frag_w2(const MlpDev& M) { return (int64_t)M.In * M.H; }
+__host__ __device__ inline int64_t frag_w3(const MlpDev& M) { return (int64_t)M.In * M.H + (int64_t)M.H * M.H; }
+// Inference batches of at most 16 rows in one launch instead of three GEMMs.
+// Workgroup (tile, net) computes both hidden layers of its net (every tile of
+// a net repeats them; activations stay in LDS as bfloat16) and then output
+// columns [256 tile, 256 tile + 256).  Each wave owns 64 columns of a layer
+// (four 16 x 16 blocks) and loads its weight fragments straight from the
+// fragment-order copy, eight K steps at a time, so no workgroup barrier falls
+// inside a layer.  Every block sums its MFMAs over K in the order k_gemm does,
+// with the same bfloat16 operands, bias and SiLU: the outputs are the same
+// bits as the three-GEMM path.
+constexpr int kFwdRows = 16;
+constexpr int kFwdMaxTiles = 8;   // output tiles (256 columns each) up to which the fused path is used
+constexpr int kFwdSteps = 8;      // K steps of 16 whose fragments are loaded together (K % 128 == 0)
+
+__host__ __device__ inline size_t forward_small_lds(int H) { return (size_t)2 * kFwdRows * (H + 4) * sizeof(uint16_t); }
+
+__global__ __launch_bounds__(256) void k_forward_small(MlpDev M, const float* X, float* O) {
+    extern __shared__ __align__(16) uint16_t fsm[];
+    const int H = M.H, In = M.In, Out = M.Out, B = M.Bm;
+    const int net = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rr = lane & 15, q4 = 4 * (lane >> 4);
+    const int hs = H + 4;  // LDS row stride of an activation tile (8-byte aligned rows)
+    uint16_t* h1 = fsm;
+    uint16_t* h2 = fsm + kFwdRows * hs;
+    const float* Xn = X + (int64_t)net * B * In;
+    const uint16_t* WF = M.wbt + (int64_t)net * M.NPt;
+    const float* bn = M.master + (int64_t)net * M.NP;
+
+    auto from_x = [&](int k) {  // row rr of the features at k .. k + 3, rounded on the way in
+        bf16x4 f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = (short)(rr < B ? f_to_bf16(Xn[(int64_t)rr * In + k + i]) : (uint16_t)0);
+        return f;
+    };
+    auto from_h1 = [&](int k) { return *reinterpret_cast<const bf16x4*>(&h1[rr * hs + k]); };
+    auto from_h2 = [&](int k) { return *reinterpret_cast<const bf16x4*>(&h2[rr * hs + k]); };
+    // C = A W on the columns [n0, n0 + 64) of W [K][ncol] (fragment copy at fb):
+    // this lane's accumulators of the four 16 x 16 blocks
+    auto blocks = [&](auto afrag, int64_t fb, int K, int ncol, int n0, f32x4* acc) {
+        const int nb0 = n0 / 16, nbs = (ncol + 15) / 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < K; k0 += 16 * kFwdSteps) {  // the fragments of kFwdSteps steps in flight together
+            bf16x4 af[kFwdSteps], bf[kFwdSteps][4];
+#pragma unroll
+            for (int t = 0; t < kFwdSteps; ++t) {
+                const int ks = k0 / 16 + t;
+                af[t] = afrag(16 * ks + q4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bf[t][j] = nb0 + j < nbs
+                                   ? *reinterpret_cast<const bf16x4*>(
+                                         &WF[fb + (((int64_t)(nb0 + j) * (K / 16) + ks) * 64 + lane) * 4])
+                                   : bf16x4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int t = 0; t < kFwdSteps; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[t], bf[t][j], acc[j], 0, 0, 0);
+        }
+    };
+    // dst[row][col] = bf16(SiLU(A W + b)) for the batch's rows, 0 beyond
+    auto hidden = [&](auto afrag, int64_t fb, const float* bias, int K, uint16_t* dst) {
+        for (int n0 = 64 * wave; n0 < H; n0 += 256) {
+            f32x4 acc[4];
+            blocks(afrag, fb, K, H, n0, acc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = n0 + 16 * j + rr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = q4 + v;
+                    dst[row * hs + col] = row < B ? f_to_bf16(silu(acc[j][v] + bias[col])) : (uint16_t)0;
+                }
+            }
+        }
+        __syncthreads();
+    };
+    hidden(from_x, 0, bn + M.ob1, In, h1);
+    hidden(from_h1, frag_w2(M), bn + M.ob2, H, h2);
+    const int n0 = blockIdx.x * 256 + 64 * wave;  // output columns of this wave
+    if (n0 >= Out) return;
+    f32x4 acc[4];
+    blocks(from_h2, frag_w3(M), H, Out, n0, acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + 16 * j + rr;
+        if (col >= Out) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = q4 + v;
+            if (row < B) O[(int64_t)net * B * Out + (int64_t)row * Out + col] = acc[j][v] + bn[M.ob3 + col];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ features
 // Re, Im of a rotated so that a_0 is real and positive
 __device__ inline void write_features(const float* a, int N, float* X, int lane) {
@@ -355,6 +463,30 @@ __global__ __launch_bounds__(256) void k_colsum(const float* Y, int rows, int co
     if (slice == 0 && j < cols) out[net * sOut + j] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
 }
 
+// where parameter p of a net sits in the fragment copy (-1: a bias)
+__device__ inline int64_t fragment_at(const MlpDev& M, int64_t p) {
+    if (p >= M.oW1 && p < M.ob1) {
+        const int64_t q = p - M.oW1;
+        return frag_at(0, M.In, (int)(q / M.H), (int)(q % M.H));
+    }
+    if (p >= M.oW2 && p < M.ob2) {
+        const int64_t q = p - M.oW2;
+        return frag_at(frag_w2(M), M.H, (int)(q / M.H), (int)(q % M.H));
+    }
+    if (p >= M.oW3 && p < M.ob3) {
+        const int64_t q = p - M.oW3;
+        return frag_at(frag_w3(M), M.H, (int)(q / M.Out), (int)(q % M.Out));
+    }
+    return -1;
+}
+__device__ inline void store_bf16(const MlpDev& M, int64_t i, float w) {  // i over nets x NP
+    const uint16_t b = f_to_bf16(w);
+    M.wbf[i] = b;
+    if (M.In % 16 != 0 || M.H % 16 != 0) return;  // no fragment order for this shape (the fused path is off)
+    const int64_t net = i / M.NP, f = fragment_at(M, i - net * M.NP);
+    if (f >= 0) M.wbt[net * M.NPt + f] = b;
+}
+
 __global__ void k_adam(MlpDev M, float lr, float c1, float c2) {
     const int64_t n = (int64_t)M.nets * M.NP;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -365,14 +497,14 @@ __global__ void k_adam(MlpDev M, float lr, float c1, float c2) {
         M.av[i] = v;
         const float w = M.master[i] - lr * (m / c1) / (sqrtf(v / c2) + 1e-8f);
         M.master[i] = w;
-        M.wbf[i] = f_to_bf16(w);
+        store_bf16(M, i, w);
     }
 }
 
 __global__ void k_sync_bf16(MlpDev M) {
     const int64_t n = (int64_t)M.nets * M.NP;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        M.wbf[i] = f_to_bf16(M.master[i]);
+        store_bf16(M, i, M.master[i]);
 }
 
 // ------------------------------------------------------------------ the move
@@ -589,6 +721,14 @@ hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int 
 }
 
 hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st) {
+    const int tiles = (M.Out + 255) / 256;
+    if (!train && M.Bm <= kFwdRows && M.H % (16 * kFwdSteps) == 0 && M.In % (16 * kFwdSteps) == 0 &&
+        tiles <= kFwdMaxTiles &&
+        forward_small_lds(M.H) <= 64 * 1024) {
+        hipLaunchKernelGGL(k_forward_small, dim3(tiles, M.nets), dim3(256), forward_small_lds(M.H), st, M, M.X,
+                           into_reverse ? M.Or : M.Of);
+        return hipGetLastError();
+    }
     const int B = train ? M.Bt : M.Bm;
     const float* X = train ? M.tX : M.X;
     float* P1 = train ? M.tP1 : M.P1;

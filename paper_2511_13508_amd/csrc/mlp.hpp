@@ -26,6 +26,8 @@ struct MlpDev {
     int64_t oW1, ob1, oW2, ob2, oW3, ob3;  // offsets inside a parameter vector
     float* master;   // [nets][NP]
     uint16_t* wbf;   // [nets][NP] bfloat16 copies
+    uint16_t* wbt;   // [nets][NPt] bfloat16 weights in MFMA fragment order (see frag_at), zero padded
+    int64_t NPt;     // per net: In H + H H + H ceil(Out / 16) 16 elements (W1, W2, W3 with padded columns)
     float* grad;     // [nets][NP]
     float* am;       // Adam first moments
     float* av;       // Adam second moments

@@ -53,6 +53,11 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
         const size_t o = take(off, n * P * 2);
         m.wbf = base ? (uint16_t*)(base + o) : nullptr;
     }
+    m.NPt = ((int64_t)m.In * m.H + (int64_t)m.H * m.H + (int64_t)m.H * ((m.Out + 15) / 16 * 16) + 3) & ~(int64_t)3;
+    {
+        const size_t o = take(off, n * (size_t)m.NPt * 2);
+        m.wbt = base ? (uint16_t*)(base + o) : nullptr;
+    }
     m.grad = f(n * P);
     m.am = f(n * P);
     m.av = f(n * P);
@@ -176,6 +181,7 @@ int rlpt_mlp_setup(rlpt_ctx* c, const int32_t* temp_index, uint64_t seed) {
     HIP_TRY2(launch_zero(M.acc, (size_t)M.nets * 8, c->stream), "zero counts");
     HIP_TRY2(launch_zero(M.tries, (size_t)M.nets * 8, c->stream), "zero counts");
     HIP_TRY2(launch_zero(M.moves_done, 8, c->stream), "zero counts");
+    HIP_TRY2(launch_zero(M.wbt, (size_t)M.nets * M.NPt * 2, c->stream), "zero fragment copy");  // padded columns
     HIP_TRY2(mlp_sync_bf16(M, c->stream), "bf16 copies");
     HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
     c->mlp_temp.assign(temp_index, temp_index + M.nets);
