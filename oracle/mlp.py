@@ -25,6 +25,15 @@ proposal: a K-component diagonal Gaussian mixture over the displacement
 acceptance: min(1, exp(-beta dH) rho(y')/rho(y) q(y,psi|y',psi')/q(y',psi'|y,psi)).
 training loss: the mean negative log-likelihood of observed displacements
   under the unwrapped mixture (any parameters give an exact proposal).
+the boundary of the chart: y is defined on the interior of the simplex only
+  (every w_k > 0).  A configuration with some a_k = 0 lies on its boundary, a
+  set of measure zero under the reference law that the pair move can still
+  reach in finite precision (a drawn angle of exactly 0 or pi/2).  Rule: a
+  learned move from such a configuration, or one whose proposal has some
+  w'_k = 0, has log acceptance ratio -inf (rejected; both directions of every
+  move touching the set are rejected, so detailed balance holds); a training
+  pair with a zero or non-finite amplitude in either configuration is left out
+  of the loss, which is the mean over the remaining pairs of the minibatch.
 Pins (tests/test_oracle_mlp.py): finite differences of the loss (exact
 arithmetic, gemm_bf16=False; the rounding is an elementwise map), the
 single-Gaussian closed form, torch's bfloat16 rounding, the proposal density
@@ -131,8 +140,20 @@ def backward(params, cache, dO):
     return grads
 
 
+def interior(a) -> np.ndarray:
+    """True for configurations inside the chart: every amplitude finite and nonzero."""
+    a = np.asarray(a)
+    return np.all(np.isfinite(a) & (np.abs(a) > 0.0), axis=-1)
+
+
 def loss_and_grads(params, a_before, a_after, N, K, gemm_bf16=True):
-    """Training loss on pairs of configurations and its parameter gradients."""
+    """Training loss on pairs of configurations and its parameter gradients:
+    the mean over the pairs whose two configurations are both inside the chart
+    (the others are left out).  Raises ValueError when no pair is."""
+    keep = interior(a_before) & interior(a_after)
+    if not np.any(keep):
+        raise ValueError("no training pair inside the chart")
+    a_before, a_after = np.asarray(a_before)[keep], np.asarray(a_after)[keep]
     X = features(a_before)
     o, cache = forward(params, X, gemm_bf16)
     delta = displacement(a_before, a_after)
@@ -221,17 +242,25 @@ def propose(params, a, N, K, scale, g, u_comp):
 
 def move_log_alpha(params, a, dH, beta, N, K, scale, g, u_comp, energy=None):
     """Batched learned move.  Returns (a_new, log acceptance ratio, parts).
-    dH: callable a_new -> energy change per row, or None for infinite temperature."""
-    a_new, delta, o_fwd, m = propose(params, a, N, K, scale, g, u_comp)
+    dH: callable a_new -> energy change per row, or None for infinite temperature.
+    Rows whose current configuration or proposal is not inside the chart get
+    a log acceptance ratio of -inf (their a_new is then meaningless)."""
+    a = np.asarray(a)
+    inside = interior(a)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        a_new, delta, o_fwd, m = propose(params, a, N, K, scale, g, u_comp)
+    inside &= interior(a_new)
+    a_new = np.where(inside[:, None], a_new, a)
     o_rev, _ = forward(params, features(a_new))
     lq_f = log_q(o_fwd, delta[:, :N - 1], delta[:, N - 1:], N, K, scale)
     lq_r = log_q(o_rev, -delta[:, :N - 1], -delta[:, N - 1:], N, K, scale)
-    _, _, w = coords(a)
-    _, _, w2 = coords(a_new)
-    dref = log_ref(w2) - log_ref(w)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        _, _, w = coords(a)
+        _, _, w2 = coords(a_new)
+        dref = log_ref(w2) - log_ref(w)
     de = np.zeros(a.shape[0]) if dH is None else dH(a_new)
-    la = -beta * de + dref + lq_r - lq_f
-    return a_new, la, {"dH": de, "lq_f": lq_f, "lq_r": lq_r, "dlogref": dref, "component": m}
+    la = np.where(inside, -beta * de + dref + lq_r - lq_f, -np.inf)
+    return a_new, la, {"dH": de, "lq_f": lq_f, "lq_r": lq_r, "dlogref": dref, "component": m, "inside": inside}
 
 
 def init_params(N, H, K, rng, out_scale=0.01):

@@ -99,13 +99,20 @@ def var0_energy_sphere(N: int, J: np.ndarray) -> float:
 
 
 def beta0_moments(N: int) -> dict:
-    """Closed forms at infinite temperature."""
+    """Closed forms at infinite temperature.  The intensities are
+    u_k = |a_k|^2 = sqrt(N) |g_k| / ||g|| for a standard normal g in R^N, so with
+    ||g|| independent of the direction g / ||g||: E u_k = sqrt(N) E|g_k| / E||g||,
+    E u_k^2 = 1 and, for k != l, E u_k u_l = N E|g_k| E|g_l| / E||g||^2 = 2 / pi.
+    The total intensity per mode x = I / N = (1/N) sum_k u_k then has
+    E x = E u_k and E x^2 = (N E u^2 + N (N - 1) (2 / pi)) / N^2."""
     ex1 = math.exp(math.lgamma(N / 2) - math.lgamma((N + 1) / 2)) / math.sqrt(math.pi)
     return {
         "E|a|^2": math.sqrt(N) * ex1,
         "E|a|^4": 1.0,
         "E|a|^8": 3.0 * N / (N + 2.0),
         "Var q": ex1 * ex1 / 2.0,
+        "E I/N": math.sqrt(N) * ex1,
+        "E (I/N)^2": (N + N * (N - 1) * 2.0 / math.pi) / N ** 2,
     }
 
 
@@ -121,15 +128,17 @@ def comb_count(N: int) -> int:
     return (N - 1) * (N - 3) * (2 * N - 1) // 24
 
 
-def importance_reference(quads, J, N, temps, M, seed, chunk=200000, draw=None):
+def importance_reference(quads, J, N, temps, M, seed, chunk=200000, draw=None, i_bins=0):
     """Thermal averages at each temperature by reweighting i.i.d. infinite-
     temperature draws: <O>_beta = E0[O w] / E0[w], w = exp(-beta H).  Two
     independent draws give the overlap.  Returns (mean, stderr) dicts of
     arrays over temps; the error is the delta-method error of a ratio
-    estimator, sqrt(sum w^2 (O - mean)^2) / sum w."""
+    estimator, sqrt(sum w^2 (O - mean)^2) / sum w.  i_bins > 0 adds "pI":
+    the probability of each of i_bins equal bins of I / N on [0, 1] (shape
+    [temps][i_bins])."""
     rng = np.random.default_rng(seed)
     draw = draw or beta0_draw
-    cols = {k: [] for k in ("Ha", "Hb", "y2", "y4", "q")}
+    cols = {k: [] for k in ("Ha", "Hb", "y2", "y4", "q", "x")}
     for start in range(0, M, chunk):
         m = min(chunk, M - start)
         a = draw(N, m, rng)
@@ -142,22 +151,30 @@ def importance_reference(quads, J, N, temps, M, seed, chunk=200000, draw=None):
         cols["y2"].append(S2 / I ** 2)
         cols["y4"].append(S4 / S2 ** 2)
         cols["q"].append(np.sum(np.conj(a) * b, axis=1).real / N)
-    Ha, Hb, y2, y4, q = (np.concatenate(cols[k]) for k in ("Ha", "Hb", "y2", "y4", "q"))
+        cols["x"].append(I / N)
+    Ha, Hb, y2, y4, q, x = (np.concatenate(cols[k]) for k in ("Ha", "Hb", "y2", "y4", "q", "x"))
 
     def ratio(w, O):
         r = np.sum(w * O) / np.sum(w)
         return r, math.sqrt(np.sum(w ** 2 * (O - r) ** 2)) / np.sum(w)
 
-    mean = {k: [] for k in ("E", "E2", "y2", "y4", "q2", "q4")}
+    mean = {k: [] for k in ("E", "E2", "y2", "y4", "q2", "q4", "x")}
     err = {k: [] for k in mean}
+    if i_bins:
+        xb = np.clip(np.floor(x * i_bins).astype(np.int64), 0, i_bins - 1)
+        mean["pI"], err["pI"] = [], []
     for T in temps:
         beta = 1.0 / T
         la, lb = -beta * Ha, -beta * Hb
         wa = np.exp(la - la.max())
         wb = np.exp(lb - lb.max())
         for k, w, O in (("E", wa, Ha), ("E2", wa, Ha ** 2), ("y2", wa, y2), ("y4", wa, y4),
-                        ("q2", wa * wb, q ** 2), ("q4", wa * wb, q ** 4)):
+                        ("q2", wa * wb, q ** 2), ("q4", wa * wb, q ** 4), ("x", wa, x)):
             r, e = ratio(w, O)
             mean[k].append(r)
             err[k].append(e)
+        if i_bins:
+            pr = [ratio(wa, (xb == b).astype(np.float64)) for b in range(i_bins)]
+            mean["pI"].append([v[0] for v in pr])
+            err["pI"].append([v[1] for v in pr])
     return ({k: np.array(v) for k, v in mean.items()}, {k: np.array(v) for k, v in err.items()})

@@ -178,3 +178,53 @@ def test_learned_chain_samples_boltzmann_law(oracle):
     se = per_chain.std() / math.sqrt(len(per_chain))
     assert 0.2 < acc < 0.9
     assert per_chain.mean() == pytest.approx(ref["E"][0], abs=4 * math.sqrt(se ** 2 + err["E"][0] ** 2))
+
+
+def test_training_pairs_outside_the_chart_are_left_out(oracle):
+    """A training pair with an exact zero amplitude in either configuration has
+    no displacement in the alr chart (log 0): the loss and its gradients are
+    those of the remaining pairs alone, finite, and a minibatch with no pair
+    inside the chart is an error."""
+    N, H, K, B = 6, 16, 2, 8
+    rng = np.random.default_rng(11)
+    params = M.rounded(M.init_params(N, H, K, rng, out_scale=0.5))
+    a = np.array([oracle.init_copy(N, 12, c) for c in range(B)])
+    b = np.array([oracle.init_copy(N, 13, c) for c in range(B)])
+    a[2, 3] = 0.0
+    b[5, N - 1] = 0.0  # the alr reference mode
+    b[6, 0] = 0.0      # the mode that fixes the gauge of the features
+    with np.errstate(divide="ignore", invalid="ignore"):
+        assert not np.all(np.isfinite(M.displacement(a, b)[[2, 5, 6]]))
+    keep = np.array([i not in (2, 5, 6) for i in range(B)])
+    L, g = M.loss_and_grads(params, a, b, N, K)
+    L_ref, g_ref = M.loss_and_grads(params, a[keep], b[keep], N, K)
+    assert np.isfinite(L) and L == L_ref
+    for k in g:
+        assert np.all(np.isfinite(g[k])) and np.array_equal(g[k], g_ref[k]), k
+    with pytest.raises(ValueError):
+        M.loss_and_grads(params, a[[2, 5]], b[[2, 5]], N, K)
+
+
+def test_learned_moves_touching_the_chart_boundary_are_rejected(oracle):
+    """A learned move from a configuration with a zero amplitude, or whose
+    proposal underflows an intensity to zero, has log acceptance -inf; the
+    other rows of the batch are unaffected (same ratio as alone)."""
+    N, H, K = 5, 12, 2
+    rng = np.random.default_rng(14)
+    params = M.rounded(M.init_params(N, H, K, rng, out_scale=0.2))
+    a = np.array([oracle.init_copy(N, 15, c) for c in range(4)])
+    a[1, 2] = 0.0
+    _, D, _ = M.sizes(N, K)
+    g = rng.standard_normal((4, D))
+    uc = rng.uniform(size=4)
+    _, la, parts = M.move_log_alpha(params, a, None, 0.0, N, K, 0.5, g, uc)
+    assert la[1] == -np.inf and not parts["inside"][1]
+    assert np.all(np.isfinite(la[[0, 2, 3]]))
+    _, la0, _ = M.move_log_alpha(params, a[[0]], None, 0.0, N, K, 0.5, g[[0]], uc[[0]])
+    assert la0[0] == la[0]
+    # a mean displacement of -3000 in y_0 (every component) underflows w'_0 to zero
+    big = {k: v.copy() for k, v in params.items()}
+    big["b3"][K + np.arange(K) * D] = -3000.0
+    a2 = np.array([oracle.init_copy(N, 16, c) for c in range(2)])
+    an, la2, parts2 = M.move_log_alpha(big, a2, None, 0.0, N, K, 1.0, g[:2], uc[:2])
+    assert np.all(la2 == -np.inf) and not np.any(parts2["inside"])

@@ -203,6 +203,38 @@ def test_spectrum_is_flat_at_infinite_temperature(oracle):
     assert np.all(tot >= cold.acc["e_n"] * 1.0 - 1e-9) and np.all(tot <= cold.acc["e_n"] * N + 1e-9)
 
 
+def test_intensity_histogram_at_infinite_temperature(oracle):
+    """P(I), the histogram of I / N on [0, 1] (sec. II.B): at infinite
+    temperature its mean and second moment (bin centres, 400 bins) are the
+    closed forms of the flat constrained law, E I/N = E|a|^2 and
+    E (I/N)^2 = (N + 2N(N-1)/pi)/N^2; no mass lies outside [1/sqrt(N), 1]
+    (sum|a|^2 >= sqrt(sum|a|^4) and Cauchy-Schwarz).  Binning I instead of
+    I / N, or the overlap's bin rule, would fail all three."""
+    N, reps, B, sweeps = 8, 64, 400, 2000
+    g = oracle.Graph(N, 12)
+    pt = oracle.PT(g, [1e11, 1e12], n_reps=reps, run_seed=4, swap_interval=1, resync_interval=0,
+                   measure_start=0, measure_interval=1, n_bins=B)
+    pt.run(sweeps)
+    ref = brute.beta0_moments(N)
+    h = pt.acc["hist_I"]
+    assert np.all(h.sum(axis=1) == pt.acc["e_n"])
+    centre = (np.arange(B) + 0.5) / B
+    lo = int(math.floor(B / math.sqrt(N)))
+    assert np.all(h[:, :lo] == 0)
+    var = ref["E (I/N)^2"] - ref["E I/N"] ** 2
+    n_eff = reps * sweeps / 3.0  # the per-copy series decorrelates within a few sweeps at beta = 0
+    for t in range(2):
+        p = h[t] / h[t].sum()
+        m1 = float(np.sum(p * centre))
+        m2 = float(np.sum(p * centre ** 2))
+        assert m1 == pytest.approx(ref["E I/N"], abs=5 * math.sqrt(var / n_eff) + 1e-5)
+        assert m2 == pytest.approx(ref["E (I/N)^2"], abs=10 * math.sqrt(var / n_eff) + 1.0 / (12 * B * B))
+    cold = oracle.PT(g, [0.3, 0.6], n_reps=2, run_seed=6, swap_interval=1, resync_interval=0, measure_start=0,
+                     measure_interval=1, n_bins=B)
+    cold.run(500)
+    assert np.all(cold.acc["hist_I"][:, :lo] == 0)
+
+
 def test_beta0_chain_preserves_law_and_constraint(oracle):
     """At infinite temperature every move is accepted; starting from the exact
     beta = 0 law the chain must stay on it (the two-mode proposal is exactly
@@ -257,7 +289,7 @@ def _pt_stats(oracle, g, temps, seeds, n_sweeps, burn):
         A = pt.acc
         rows.append(dict(E=A["e_sum"] / A["e_n"], E2=A["e_sq"] / A["e_n"], y2=A["y2_sum"] / A["e_n"],
                          y4=A["y4_sum"] / A["e_n"], q2=A["q_sq"] / A["q_n"], q4=A["q_4"] / A["q_n"],
-                         hist=A["hist"], swap=A["swap_acc"] / A["swap_tries"]))
+                         hist=A["hist"], hist_I=A["hist_I"], swap=A["swap_acc"] / A["swap_tries"]))
     return rows
 
 
@@ -269,7 +301,8 @@ def test_pt_matches_importance_sampling(oracle):
     N = 8
     g = oracle.Graph(N, 31)
     temps = np.array([1.0, 1.25, 1.55, 1.95, 2.4])
-    ref, ref_err = brute.importance_reference(g.quads.astype(np.int64), g.J, N, temps, M=1000000, seed=5)
+    ref, ref_err = brute.importance_reference(g.quads.astype(np.int64), g.J, N, temps, M=1000000, seed=5,
+                                              i_bins=40)
     rows = _pt_stats(oracle, g, temps, seeds=range(1, 9), n_sweeps=12000, burn=1000)
     for key in ("E", "y2", "y4", "q2"):
         vals = np.array([r[key] for r in rows])
@@ -281,6 +314,11 @@ def test_pt_matches_importance_sampling(oracle):
     cv_err = np.sqrt(ref_err["E2"] ** 2 + (2 * ref["E"] * ref_err["E"]) ** 2) / temps ** 2
     m, se = cv.mean(axis=0), cv.std(axis=0, ddof=1) / math.sqrt(len(rows))
     assert np.all(np.abs(m - cv_ref) < 4.5 * np.sqrt(se ** 2 + cv_err ** 2)), (m, cv_ref, se, cv_err)
+    # P(I): every bin's probability against the reweighted i.i.d. draws
+    pI = np.array([r["hist_I"] / r["hist_I"].sum(axis=1, keepdims=True) for r in rows])
+    m, se = pI.mean(axis=0), pI.std(axis=0, ddof=1) / math.sqrt(len(rows))
+    tol = 4.5 * np.sqrt(se ** 2 + ref_err["pI"] ** 2) + 2e-4
+    assert np.all(np.abs(m - ref["pI"]) < tol), (np.max(np.abs(m - ref["pI"]) / tol))
 
 
 def test_overlap_histogram_is_symmetric_and_complete(oracle):
