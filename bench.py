@@ -5,17 +5,21 @@ samples (random frequencies, frequency-matched terms, Gaussian couplings of
 variance N/c), 40 temperatures geometric in [0.25, 1.5], 2 replicas (640
 copies), FP32 fields and energy changes, FP64 energy recomputation every 100
 sweeps, a swap round and a measurement after every sweep.  A step is one
-sweep of every copy (N/2 two-mode updates each) followed by its swap round,
-measurement and, every 100 steps, the recomputation.  Inputs are synthetic
-and already resident in HBM when timing starts.
+recomputation interval: 100 sweeps of every copy (N/2 two-mode updates each),
+each followed by its swap round and measurement, then the FP64
+recomputation -- every part of the path.  Inputs are synthetic and already
+resident in HBM when timing starts.
 
 Prints one JSON line.  ``value`` = mode-updates/s (N mode-updates per copy
 per sweep) over the timed steps.  ``roofline`` describes the sweep kernel:
 algorithmic bytes per launch (every list entry a step streams: 6.25 B in
 the chunked layout, 25 B per chunk of 4 entries sharing their partner mode;
 8 B in the packed one) over its mean duration measured with HIP events on
-the context's stream.  ``cpu_baseline`` times the CPU FP64 oracle on a bounded
-slice of the same workload (sample 0, all 80 copies, whole sweeps for ~10 s).
+the context's stream, against the measured ceiling of the memory hierarchy
+for the same list stream (rlpt_stream_lists: the sweep's grid and reads with
+no arithmetic), beside the published 8 TB/s HBM peak.  ``cpu_baseline``
+times the CPU FP64 oracle on a bounded slice of the same workload (sample 0,
+all 80 copies, whole sweeps for ~10 s).
 """
 from __future__ import annotations
 
@@ -67,17 +71,21 @@ def traffic_for_current_kernel(launch_bytes_alg: float):
 PROFILE_CMDS = {
     "kt": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kt -o kt -- python bench.py --steps 20 --warmup 5 "
           "--tau-sweeps 0 --no-cpu-baseline --no-cached",
-    "kta": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kta -o kta -- python bench.py --steps 100 "
-           "--warmup 300 --tau-sweeps 100 --no-cpu-baseline --no-n64",
+    "kta": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/kta -o kta -- python bench.py --steps 1 "
+           "--warmup 3 --tau-sweeps 100 --no-cpu-baseline --no-n64 --no-batched",
     "ktb": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/ktb -o ktb -- python bench.py --workload batched "
-           "--steps 50",
+           "--steps 5",
     "ktl": "rocprofv3 --kernel-trace --stats -f csv -d {OUT}/ktl -o ktl -- python bench.py --workload learned64 "
-           "--steps 2000",
+           "--steps 20",
     "pmc64": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_LDS SQ_INSTS_VALU SQ_WAVE_CYCLES "
              "SQ_BUSY_CYCLES SQ_INSTS_SALU --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmc64 -o pmc -- "
              "python bench.py --workload n64",
-    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmc_{C} -o pmc -- python bench.py "
-           "--steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
+    "sq256": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_BUSY_CYCLES SQ_WAVE_CYCLES "
+             "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE --kernel-include-regex 'k_sweep<|k_stream_lists' "
+             "-f csv -d {OUT}/sq256 -o pmc -- python bench.py --sweeps-per-step 1 --steps 4 --warmup 2 "
+             "--tau-sweeps 0 --no-cpu-baseline --no-cached",
+    "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<|k_stream_lists' -f csv -d {OUT}/pmc_{C} -o pmc -- "
+           "python bench.py --sweeps-per-step 1 --steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
     "cal": "rocprofv3 --pmc {C} -f csv -d {OUT}/cal_{C} -o cal -- python bench.py --copy-calibration",
 }
 
@@ -101,10 +109,13 @@ def summarize_profiles(d):
     lines = []
     have_headline = all(os.path.exists(os.path.join(d, x)) for x in ("kt", "pmc_FETCH_SIZE", "pmc_WRITE_SIZE",
                                                                     "cal_FETCH_SIZE", "cal_WRITE_SIZE"))
+    is_sweep = lambda n: "k_sweep<" in n  # noqa: E731
+    is_ceiling = lambda n: "k_stream_lists" in n  # noqa: E731
+    is_copy = lambda n: "copyBuffer" in n  # noqa: E731
     if have_headline:
         stats = rows(os.path.join(d, "kt", "kt_kernel_stats.csv"))
         lines = ["# rocprofv3 kernel statistics, headline N=256 workload (8 samples x 40 T x 2 replicas, streaming sweep, "
-                 "per-copy pairs)",
+                 "per-copy pairs); k_stream_lists is the list-stream ceiling the bench measures beside it",
                  "# command (from the repository root):",
                  "#   " + cmd("kt"), "",
                  f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
@@ -112,31 +123,59 @@ def summarize_profiles(d):
             name = r["Name"].replace("rlpt::(anonymous namespace)::", "")[:60]
             lines.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
                          f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
-        sweep = [r for r in stats if "k_sweep<" in r["Name"]][0]
-        is_sweep = lambda n: "k_sweep<" in n  # noqa: E731
-        is_copy = lambda n: "copyBuffer" in n  # noqa: E731
-        fetch_kib, nf = mean_counter(os.path.join(d, "pmc_FETCH_SIZE", "pmc_counter_collection.csv"), is_sweep)
-        write_kib, nw = mean_counter(os.path.join(d, "pmc_WRITE_SIZE", "pmc_counter_collection.csv"), is_sweep)
+        avg_ns = {}
+        for tag, pred in (("k_sweep", is_sweep), ("k_stream_lists", is_ceiling)):
+            hit = [r for r in stats if pred(r["Name"])]
+            if hit:
+                avg_ns[tag] = float(hit[0]["AverageNs"])
         cal_f, _ = mean_counter(os.path.join(d, "cal_FETCH_SIZE", "cal_counter_collection.csv"), is_copy)
         cal_w, _ = mean_counter(os.path.join(d, "cal_WRITE_SIZE", "cal_counter_collection.csv"), is_copy)
         copy_bytes = 512 * 1024 * 1024
         f_scale, w_scale = copy_bytes / (cal_f * 1024), copy_bytes / (cal_w * 1024)
-        hbm = fetch_kib * 1024 * f_scale + write_kib * 1024 * w_scale
         traffic = {"kernel": "k_sweep<float, 256>", "kernel_source_sha": kernel_sha(),
-                   "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib, "dispatches": [nf, nw],
                    "copy_kernel_fetch_kib": cal_f, "copy_kernel_write_kib": cal_w, "copy_bytes": copy_bytes,
-                   "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
-                   "avg_duration_ns_kernel_trace": float(sweep["AverageNs"]),
+                   "fetch_scale": f_scale, "write_scale": w_scale,
                    "commands": [cmd("pmc", "FETCH_SIZE"), cmd("pmc", "WRITE_SIZE"), cmd("cal", "FETCH_SIZE"),
                                 cmd("cal", "WRITE_SIZE")]}
-        lines += ["", "# HBM traffic of k_sweep per dispatch (rocprofv3 --pmc, one counter per run):",
-                  f"#   FETCH_SIZE {fetch_kib:.0f} KiB x {f_scale:.4f} (copy-kernel scale) + WRITE_SIZE {write_kib:.0f} KiB "
-                  f"x {w_scale:.4f} = {hbm / 1e9:.3f} GB per launch",
-                  f"#   over the kernel-trace average {float(sweep['AverageNs']) / 1e6:.3f} ms: "
-                  f"{hbm / float(sweep['AverageNs']):.0f} GB/s"]
+        lines += ["", "# fabric traffic per dispatch (rocprofv3 --pmc, one counter per run; FETCH_SIZE counts every L2 "
+                      "miss, whether the Infinity Cache or HBM serves it):"]
+        for tag, pred in (("k_sweep", is_sweep), ("k_stream_lists", is_ceiling)):
+            try:
+                fetch_kib, nf = mean_counter(os.path.join(d, "pmc_FETCH_SIZE", "pmc_counter_collection.csv"), pred)
+                write_kib, nw = mean_counter(os.path.join(d, "pmc_WRITE_SIZE", "pmc_counter_collection.csv"), pred)
+            except ZeroDivisionError:
+                continue
+            hbm = fetch_kib * 1024 * f_scale + write_kib * 1024 * w_scale
+            key = "" if tag == "k_sweep" else "ceiling_"
+            traffic.update({key + "fetch_kib_per_dispatch": fetch_kib, key + "write_kib_per_dispatch": write_kib,
+                            key + "dispatches": [nf, nw], key + "hbm_bytes_per_launch": hbm,
+                            key + "avg_duration_ns_kernel_trace": avg_ns.get(tag)})
+            lines.append(f"#   {tag}: FETCH_SIZE {fetch_kib:.0f} KiB x {f_scale:.4f} (copy-kernel scale) + WRITE_SIZE "
+                         f"{write_kib:.0f} KiB x {w_scale:.4f} = {hbm / 1e9:.3f} GB per launch"
+                         + (f"; over the kernel-trace average {avg_ns[tag] / 1e6:.3f} ms: {hbm / avg_ns[tag]:.0f} GB/s"
+                            if tag in avg_ns else ""))
         os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
         with open(os.path.join(ROOT, "profiles", "sweep_n256_kernel_stats.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
+    sq = os.path.join(d, "sq256", "pmc_counter_collection.csv")
+    if os.path.exists(sq):
+        rs = rows(sq)
+        bl = ["# rocprofv3 SQ counters, headline N=256 workload: the sweep kernel and the list-stream ceiling kernel "
+              "(same grid, tile and list reads, no arithmetic), mean per dispatch",
+              "# command (from the repository root):", "#   " + cmd("sq256"), ""]
+        for tag, pred in (("k_sweep", is_sweep), ("k_stream_lists", is_ceiling)):
+            acc = {}
+            for r in rs:
+                if pred(r["Kernel_Name"]):
+                    acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            if not acc:
+                continue
+            bl.append(f"# {tag}")
+            for k in sorted(acc):
+                bl.append(f"{k:<24} {sum(acc[k]) / len(acc[k]):>16.1f}   ({len(acc[k])} dispatches)")
+            bl.append("")
+        with open(os.path.join(ROOT, "profiles", "sweep_n256_sq_counters.txt"), "w") as f:
+            f.write("\n".join(bl) + "\n")
     other = (("kta", "bench_all_kernel_stats.txt",
               "N=256 bench with every variant after 300 warm-up sweeps: streaming and cached-field sweeps, shared "
               "pairs, learned proposal (harvest, training, moves), the sparse N=1024 run and the IPR comparison "
@@ -226,11 +265,12 @@ def cpu_model():
     return None
 
 
-def batched(args):
+def batched(args, short=False):
     """The batched uneven-N configuration: N in {32, 48, 64, 96, 128} x 32
     samples x 32 temperatures x 2 replicas in one launch per sweep, a segment of
     10 sweeps captured in a HIP graph and replayed; built-in tiles versus tiles
-    chosen by the autotuner.  Prints its own JSON line (not the headline)."""
+    chosen by the autotuner.  Returns its own result (not the headline);
+    short: 500 sweeps per rate instead of the step count's."""
     import torch
     from paper_2511_13508_amd import rlpt
 
@@ -265,21 +305,24 @@ def batched(args):
         ctx.check()
         kms, launches = ctx.sweep_time()
         tile = ctx.tile()
+        ceil_ms = ctx.stream_lists(5) if len(gs) == len(graphs) else None
         ctx.close()
-        return sum(g.N for g in gs) * T * reps * segments * 10 / el, kms / launches, tile
+        return sum(g.N for g in gs) * T * reps * segments * 10 / el, (kms / launches, ceil_ms), tile
+
+    segs = 50 if short else max(args.sweeps // 10, 1)
 
     def run(tag):
-        v, ms, (block, cp) = rate(graphs, kw, args.steps // 10)
+        v, (ms, ceil_ms), (block, cp) = rate(graphs, kw, segs)
         tile = {int(N): int(cp[i * per_N]) for i, N in enumerate(Ns)}
         log(f"{tag}: {v:.4g} mode-updates/s, block {block}, copies per block {tile}")
-        return v, block, tile, ms
+        return v, block, tile, ms, ceil_ms
 
     rlpt.tune_clear()
-    v0, b0, t0_, ms0 = run("built-in tiles")
+    v0, b0, t0_, ms0, _ = run("built-in tiles")
     # each N class alone (its 32 samples in a launch of their own, built-in tile)
     alone = {}
     for i, N in enumerate(Ns):
-        vN, msN, _ = rate(graphs[i * per_N:(i + 1) * per_N], kw, args.steps // 10)
+        vN, (msN, _), _ = rate(graphs[i * per_N:(i + 1) * per_N], kw, segs)
         alone[N] = {"mode_updates_per_s": vN, "ms_per_launch": msN,
                     "share_of_mixed_mode_updates": N * per_N / sum(g.N for g in graphs)}
         log(f"N={N} alone: {vN:.4g} mode-updates/s, {msN:.3f} ms per sweep launch")
@@ -287,7 +330,7 @@ def batched(args):
     t_tune = time.perf_counter()
     n_trials = rlpt.autotune(graphs, temps, sweeps_per_trial=10, **kw)
     t_tune = time.perf_counter() - t_tune
-    v1, b1, t1_, ms1 = run("tuned tiles")
+    v1, b1, t1_, ms1, ceil1 = run("tuned tiles")
     # the tuner times every trial on the whole launch: per N, the trial of the chosen tile
     per_N = {}
     for e in rlpt.tune_entries():
@@ -296,55 +339,69 @@ def batched(args):
             per_N[N] = {"copies_per_block": t1_[N], "launch_ms_per_sweep": e["ms_per_sweep"]}
     out = {"metric": "aggregate mode-updates/s, batched uneven N (one launch per sweep, HIP graph)",
            "value": v1, "unit": "mode-updates/s", "untuned_value": v0, "tuned_vs_untuned": v1 / v0,
-           "copies": copies, "steps": args.steps // 10 * 10, "dtype": "f32", "data": "synthetic",
+           "copies": copies, "sweeps": segs * 10, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched uneven N: N in {32,48,64,96,128} x 32 samples x 32 temperatures x "
                                   "2 replicas, FP32, 10-sweep HIP-graph segments"},
            "roofline": {"bound": "hbm", "kernel": "k_sweep (one launch for every N)", "unit": "GB/s",
                         "algorithmic_bytes_per_launch": bytes_per_sweep, "ms_per_launch": ms1,
-                        "achieved": bytes_per_sweep / ms1 / 1e6, "peak": HBM_PEAK_GBS,
-                        "frac": bytes_per_sweep / ms1 / 1e6 / HBM_PEAK_GBS,
+                        "achieved": bytes_per_sweep / ms1 / 1e6, "peak": bytes_per_sweep / ceil1 / 1e6,
+                        "frac": ceil1 / ms1, "ceiling_ms_per_launch": ceil1,
+                        "peak_kind": "measured list-stream ceiling of the same launch (rlpt_stream_lists)",
+                        "hbm_peak_published": HBM_PEAK_GBS,
+                        "frac_of_hbm_peak": bytes_per_sweep / ms1 / 1e6 / HBM_PEAK_GBS,
                         "ms_per_launch_builtin_tiles": ms0},
            "per_N_alone": alone,
            "tile_builtin": {"block": b0, "copies_per_block": t0_}, "tile_tuned": {"block": b1, "copies_per_block": t1_},
            "autotune": {"trials": n_trials, "seconds": t_tune,
                         "method": "per workgroup size, each N's copies per workgroup timed on the whole launch "
                                   "with the other N at their current choice", "chosen_trials": per_N}}
-    print(json.dumps(out), flush=True)
+    log(f"batched: {v1:.4g} mode-updates/s tuned, {v0:.4g} built-in")
+    return out
 
 
-def cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out):
+def cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out, src):
     """The headline workload with cached local fields (field_mode = FIELDS_CACHED):
-    the same chain as the streaming run; reports its rate, the speedup, the
-    acceptance and an algorithmic byte count per launch."""
+    the same chain as the streaming run, timed from an equilibrated state (the
+    streaming context src's configurations after its tau_int run, each placed
+    at the temperature it held), since its cost follows the acceptance rate;
+    reports its rate, the speedup over the streaming sweep, the acceptance and
+    an algorithmic byte count per launch."""
     N, S, T, reps = args.n_modes, args.samples, args.temps, args.reps
     ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, field_mode=rlpt.FIELDS_CACHED, **common)
     ctx.init(1)
-    log("cached fields: warmup")
-    ctx.sweep(args.warmup)
+    equilibrated_state(src, ctx, N, S, T, reps)
+    src_sweeps = src.counters()[0]
+    log(f"cached fields: from the streaming run's state after {src_sweeps} sweeps")
+    ctx.sweep(args.sweeps_per_step)
     ctx.check()
     torch.cuda.synchronize()
-    acc0 = ctx.observables()["acc"].sum()
+    o0 = ctx.observables()
+    acc0, tries0 = o0["acc"].sum(), o0["tries"].sum()
     ctx.sweep_timing(True)
     t0 = time.perf_counter()
-    ctx.sweep(args.steps)
+    ctx.sweep(args.sweeps)
     torch.cuda.synchronize()
     el4 = time.perf_counter() - t0
     ctx.check()
     kms4, launches4 = ctx.sweep_time()
     ctx.sweep_timing(False)
-    accepted = ctx.observables()["acc"].sum() - acc0
-    steps_total = n_copies * (N // 2) * args.steps
+    o1 = ctx.observables()
+    accepted = o1["acc"].sum() - acc0
+    steps_total = n_copies * (N // 2) * args.sweeps
     idx_b = 2 if chunked else 4
     pair_b = sum(inf["pair_entries"] / (N * (N - 1)) * 8.0 for inf in infos) / S  # per step
     gather_b = sum(inf["gather_entries"] for inf in infos) / (S * N) * (idx_b + 4)
     bytes4 = (steps_total * pair_b + accepted * 2 * gather_b) / launches4
     tile4 = ctx.tile()
+    acc_T = (o1["acc"] - o0["acc"]).sum(axis=0) / np.maximum((o1["tries"] - o0["tries"]).sum(axis=0), 1)
     ctx.close()
     out["cached_fields"] = {
-        "mode_updates_per_s": N * n_copies * args.steps / el4,
+        "mode_updates_per_s": N * n_copies * args.sweeps / el4,
         "speedup_vs_streaming": el / el4,
+        "start": f"equilibrated: the streaming run's configurations after {src_sweeps} sweeps",
         "ms_per_launch": kms4 / launches4,
         "acceptance": accepted / steps_total,
+        "acceptance_hottest_coldest": [float(acc_T[-1]), float(acc_T[0])],
         "tile": {"block_threads": int(tile4[0]), "copies_per_block": int(tile4[1][0])},
         "algorithmic_bytes_per_launch": bytes4,
         "achieved_GBs": bytes4 / (kms4 / launches4 * 1e-3) / 1e9,
@@ -352,7 +409,8 @@ def cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies,
                 "blocks of j and k; the launch is bound by the hottest copies' accepted steps, not by HBM",
     }
     log(f"cached fields: {out['cached_fields']['mode_updates_per_s']:.4g} mode-updates/s "
-        f"({out['cached_fields']['speedup_vs_streaming']:.2f}x streaming)")
+        f"({out['cached_fields']['speedup_vs_streaming']:.2f}x streaming), acceptance "
+        f"{out['cached_fields']['acceptance']:.4f}")
 
 
 def sparse_graphs(args, rlpt, torch, temps, out, N=1024, z=32):
@@ -362,20 +420,20 @@ def sparse_graphs(args, rlpt, torch, temps, out, N=1024, z=32):
     S, T, reps = args.samples, args.temps, args.reps
     graphs = [rlpt.Graph(N, SEED_BASE + 900 + mu, mean_degree=z) for mu in range(S)]
     ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1,
-                       resync_interval=100, measure_start=args.warmup, measure_interval=1, n_bins=100)
+                       resync_interval=100, measure_start=args.warm_sweeps, measure_interval=1, n_bins=100)
     ctx.init(1)
-    ctx.sweep(args.warmup)
+    ctx.sweep(args.warm_sweeps)
     torch.cuda.synchronize()
     ctx.sweep_timing(True)
     t0 = time.perf_counter()
-    ctx.sweep(args.steps)
+    ctx.sweep(args.sweeps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.check()
     kms, launches = ctx.sweep_time()
     out["sparse_graph"] = {"n_modes": N, "mean_degree": z, "terms_per_sample": z * N // 4,
-                           "copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.steps / el,
-                           "ms_per_launch": kms / launches, "sweeps_per_s": args.steps / el}
+                           "copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.sweeps / el,
+                           "ms_per_launch": kms / launches, "sweeps_per_s": args.sweeps / el}
     ctx.close()
     log(f"sparse N={N} z={z}: {out['sparse_graph']['mode_updates_per_s']:.4g} mode-updates/s")
 
@@ -419,25 +477,25 @@ def n64_configuration(args, rlpt, torch, out):
     temps = 0.3 * (1.5 / 0.3) ** (np.arange(T) / (T - 1))
     graphs = [rlpt.Graph(N, SEED_BASE + 100 + mu) for mu in range(S)]
     ctx = rlpt.Context(graphs, temps, n_temps=T, n_reps=2, precision=rlpt.FP32, swap_interval=1,
-                       resync_interval=100, measure_start=args.warmup, measure_interval=1, n_bins=100)
+                       resync_interval=100, measure_start=args.warm_sweeps, measure_interval=1, n_bins=100)
     ctx.init(1)
-    ctx.sweep(args.warmup)
+    ctx.sweep(args.warm_sweeps)
     torch.cuda.synchronize()
     # wall clock without events (a sweep here is ~80 us, and two event records
     # per launch would add several); then the same number of sweeps with HIP
     # events around each sweep launch for the kernel's own time
     t0 = time.perf_counter()
-    ctx.sweep(args.steps)
+    ctx.sweep(args.sweeps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.sweep_timing(True)
-    ctx.sweep(args.steps)
+    ctx.sweep(args.sweeps)
     torch.cuda.synchronize()
     ctx.check()
     kms, launches = ctx.sweep_time()
     steps = N // 2
-    out["n64_configuration"] = {"copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.steps / el,
-                                "us_per_sweep_wall": el / args.steps * 1e6, "ms_per_launch": kms / launches,
+    out["n64_configuration"] = {"copies": ctx.n_copies, "mode_updates_per_s": N * ctx.n_copies * args.sweeps / el,
+                                "us_per_sweep_wall": el / args.sweeps * 1e6, "ms_per_launch": kms / launches,
                                 "us_per_two_mode_step": kms / launches * 1e3 / steps}
     ctx.close()
     # latency floor: the same kernel and tile (one copy per 512-thread workgroup)
@@ -615,12 +673,16 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         ctx.mlp_harvest(rounds=harvest_rounds, lag=2)
         info = {}
         if learned and train:
-            l0 = ctx.mlp_train(1, 1e-3)
-            l1 = ctx.mlp_train(train_steps, 1e-3)
-            torch.cuda.synchronize()
-            info = {"harvest_and_train_s": time.perf_counter() - t0, "pairs_per_net": harvest_rounds * S * reps,
-                    "train_loss_first_last": [l0.round(2).tolist(), l1.round(2).tolist()]}
-        if learned:
+            try:
+                l0 = ctx.mlp_train(1, 1e-3)
+                l1 = ctx.mlp_train(train_steps, 1e-3)
+                torch.cuda.synchronize()
+                info = {"harvest_and_train_s": time.perf_counter() - t0, "pairs_per_net": harvest_rounds * S * reps,
+                        "train_loss_first_last": [l0.round(2).tolist(), l1.round(2).tolist()]}
+            except rlpt.RlptError as e:
+                info = {"train_error": str(e)}
+                log(f"learned N=64: training failed: {e}")
+        if learned and "train_error" not in info:
             ctx.mlp_enable(1, args.learn_scale)
         ctx.sweep(start - ctx.counters()[0])
         torch.cuda.synchronize()
@@ -648,10 +710,10 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         return 2 + int(np.argmax(cv[2:T - 2]))  # interior maximum (the ladder's ends are not a peak)
 
     def taus(o, t_idx):
+        """per sample tau_int of E and q at t_idx: arrays [len(t_idx)][S]"""
         m = min(int(o["e_n"][0, 0] / reps), sweeps)
         lo = m // 10
-        return [np.array([float(np.median([rlpt.tau_int(o[k][mu, t, lo:m])[0] for mu in range(S)]))
-                          for t in t_idx]) for k in ("series_e", "series_q")]
+        return [tau_per_sample(o[k], t_idx, lo, m) for k in ("series_e", "series_q")]
 
     def jk(v):
         n = v.shape[0]
@@ -681,8 +743,14 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
     dh, sh_ = jk(hl - hp)
     mass = (hp.mean(axis=0) + hl.mean(axis=0)) > 1e-3
     zq = np.abs(dh) / np.maximum(sh_, 1e-12)
-    effp_E, effl_E = sps_p / (2 * tEp), sps_l / (2 * tEl)
-    effp_q, effl_q = sps_p / (2 * tqp), sps_l / (2 * tql)
+    rE = eff_ratio(tEl, tEp, sps_l, sps_p)
+    rq = eff_ratio(tql, tqp, sps_l, sps_p)
+    dead = dead_networks(info.get("move_acceptance", []), np.array(info["train_loss_first_last"])
+                         if "train_loss_first_last" in info else None)
+    for d in dead:
+        rE["status"][d["network"]] = rq["status"][d["network"]] = "failed: " + d["failed"]
+    if "train_error" in info:
+        rE["status"] = rq["status"] = ["failed: " + info["train_error"]] * len(t_learn)
     out["learned_n64"] = {
         "config": f"N={N}, {S} samples x {T} temperatures [0.3, 1.5] x {reps} replicas, FP32; learned rounds "
                   f"(1 per sweep, step scale {args.learn_scale}, {'trained' if train else 'untrained'} networks) at "
@@ -690,26 +758,90 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
                   f"; both runs: {warm} warm-up, {harvest_rounds * 2} harvest (no swaps), {reeq} more sweeps, "
                   f"then {sweeps} measured sweeps",
         "temperatures": [float(temps[t]) for t in t_learn], "cv_peak_T": float(temps[pk]) if pk >= 0 else None,
-        "plain": {"sweeps_per_s": sps_p, "tau_int_E": tEp.round(2).tolist(), "tau_int_q": tqp.round(2).tolist()},
-        "learned": {"sweeps_per_s": sps_l, "tau_int_E": tEl.round(2).tolist(), "tau_int_q": tql.round(2).tolist(),
-                    **info},
-        "learned_vs_plain_eff_E": (effl_E / effp_E).round(3).tolist(),
-        "learned_vs_plain_eff_q": (effl_q / effp_q).round(3).tolist(),
+        "plain": {"sweeps_per_s": sps_p, "tau_int_E": tau_stats(tEp), "tau_int_q": tau_stats(tqp)},
+        "learned": {"sweeps_per_s": sps_l, "tau_int_E": tau_stats(tEl), "tau_int_q": tau_stats(tql), **info,
+                    "failed_networks": dead},
+        "learned_vs_plain_eff_E": rE,
+        "learned_vs_plain_eff_q": rq,
         "agreement": {"E_diff_learned_minus_plain": dE.round(3).tolist(), "E_diff_err": sE.round(3).tolist(),
                       "E_z_all_T": zE.round(2).tolist(), "E_within_2sigma": float(np.mean(zE <= 2)),
                       "Pq_cells": int(mass.sum()), "Pq_within_2sigma": float(np.mean(zq[mass] <= 2)),
                       "test": "paired jackknife over the 8 samples of (learned - plain)"},
     }
-    log(f"learned N=64: eff ratio E {out['learned_n64']['learned_vs_plain_eff_E']}, "
+    log(f"learned N=64: eff ratio E {rE['ratio']} {rE['status']}, "
         f"E within 2 sigma {out['learned_n64']['agreement']['E_within_2sigma']:.2f}, "
         f"P(q) within 2 sigma {out['learned_n64']['agreement']['Pq_within_2sigma']:.2f}")
+
+
+def tau_per_sample(series, t_idx, lo, m):
+    """tau_int (Sokal window) of series[mu, t, lo:m] for every sample mu and
+    temperature index t in t_idx: array [len(t_idx)][samples]"""
+    from paper_2511_13508_amd import rlpt
+    S = series.shape[0]
+    return np.array([[rlpt.tau_int(series[mu, t, lo:m])[0] for mu in range(S)] for t in t_idx])
+
+
+def tau_stats(tau_ps):
+    """median over samples, and mean with its standard error over samples"""
+    S = tau_ps.shape[1]
+    return {"median": np.round(np.median(tau_ps, axis=1), 2).tolist(),
+            "mean": np.round(tau_ps.mean(axis=1), 2).tolist(),
+            "err": np.round(tau_ps.std(axis=1, ddof=1) / np.sqrt(S), 2).tolist()}
+
+
+def eff_ratio(tau_a, tau_b, sps_a, sps_b):
+    """Effective sweeps/s of run a over run b per temperature, sps_a/(2 tau_a)
+    over sps_b/(2 tau_b), paired by disorder sample: the ratio is
+    (sps_a / sps_b) x exp(mean over samples of log(tau_b / tau_a)), its error
+    band exp(+-1 standard error of that mean).  A ratio whose band contains 1
+    is 'unresolved'."""
+    lr = np.log(tau_b) - np.log(tau_a)
+    S = lr.shape[1]
+    m, se = lr.mean(axis=1), lr.std(axis=1, ddof=1) / np.sqrt(S)
+    r = sps_a / sps_b * np.exp(m)
+    lo, hi = r * np.exp(-se), r * np.exp(se)
+    status = ["faster" if l > 1 else "slower" if h < 1 else "unresolved" for l, h in zip(lo, hi)]
+    return {"ratio": np.round(r, 3).tolist(), "lo": np.round(lo, 3).tolist(), "hi": np.round(hi, 3).tolist(),
+            "status": status, "method": "paired over disorder samples: (sweeps/s ratio) x exp(mean log tau ratio), "
+                                        "band = exp(+-1 standard error)"}
+
+
+def dead_networks(acceptance, losses):
+    """Networks that accepted no learned move or trained to a non-finite loss"""
+    bad = []
+    for n, a in enumerate(acceptance):
+        reasons = []
+        if not a > 0:
+            reasons.append("accepted no learned move")
+        if losses is not None and not np.all(np.isfinite(np.asarray(losses)[..., n])):
+            reasons.append("non-finite training loss")
+        if reasons:
+            bad.append({"network": n, "failed": "; ".join(reasons)})
+    return bad
+
+
+def equilibrated_state(src, dst, N, S, T, reps):
+    """Copy the configurations of context src into context dst so that every
+    (sample, ladder, temperature) slot of dst starts from src's configuration
+    at that slot (dst fresh from init: copy mu*R + r*T + t holds temperature t)."""
+    a = src.get_state().reshape(src.n_copies, N)
+    _, temp_of = src.energies()
+    R = T * reps
+    b = np.empty_like(a)
+    for c in range(src.n_copies):
+        mu, r = c // R, (c % R) // T
+        b[mu * R + r * T + temp_of[c]] = a[c]
+    dst.set_state(b.reshape(-1))
+    dst.resync()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (a step is --sweeps-per-step sweeps)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
+    ap.add_argument("--sweeps-per-step", type=int, default=100,
+                    help="sweeps per step; 100 = one FP64 recomputation interval (every part of the path)")
     ap.add_argument("--n-modes", type=int, default=256)
     ap.add_argument("--samples", type=int, default=8)
     ap.add_argument("--temps", type=int, default=40)
@@ -727,8 +859,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--reeq", type=int, default=500, help="sweeps with swaps between harvest and the learned window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-cached", action="store_true", help="skip the cached-field run")
+    ap.add_argument("--no-cached", action="store_true", help="skip the cached-field, sparse, IPR and N=64 runs")
     ap.add_argument("--no-n64", action="store_true", help="skip the N=64 physics run and learned comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-N block")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSVs under DIR and exit")
     ap.add_argument("--workload", choices=["n256", "batched", "learned64", "n64"], default="n256",
@@ -742,6 +875,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
+    args.sweeps = args.steps * args.sweeps_per_step
+    args.warm_sweeps = args.warmup * args.sweeps_per_step
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)
         return
@@ -755,7 +890,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "batched":
-        batched(args)
+        print(json.dumps(batched(args)), flush=True)
         return
     if args.workload == "n64":
         res = {}
@@ -764,7 +899,7 @@ def main():
         return
     if args.workload == "learned64":
         res = {}
-        learned_n64(args, rlpt, torch, res, sweeps=args.steps // 100 * 100 or 100, at=args.n64_learn_at,
+        learned_n64(args, rlpt, torch, res, sweeps=args.sweeps // 100 * 100 or 100, at=args.n64_learn_at,
                     train=not args.n64_untrained)
         print(json.dumps(res["learned_n64"]), flush=True)
         return
@@ -782,33 +917,29 @@ def main():
     log(f"building {S} graphs N={N}")
     graphs = [rlpt.Graph(N, SEED_BASE + mu) for mu in range(S)]
     infos = [g.info() for g in graphs]
-    series_len = args.steps + args.tau_sweeps
+    series_len = args.sweeps + args.tau_sweeps
     common = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=100,
-                  measure_start=args.warmup, measure_interval=1, n_bins=100, series_len=series_len,
+                  measure_start=args.warm_sweeps, measure_interval=1, n_bins=100, series_len=series_len,
                   block_threads=args.block, copies_per_block=args.copies_per_block, list_layout=args.layout)
 
     def timed(ctx, tag):
         """warm-up, then the timed steps with sweep-kernel events; returns (s, kernel ms, launches)"""
         ctx.init(1)
-        log(f"{tag}: warmup {args.warmup} sweeps")
-        ctx.sweep(args.warmup)
+        log(f"{tag}: warmup {args.warmup} steps ({args.warm_sweeps} sweeps)")
+        ctx.sweep(args.warm_sweeps)
         ctx.check()
         torch.cuda.synchronize()
         ctx.sweep_timing(True)
-        log(f"{tag}: timing {args.steps} sweeps")
+        log(f"{tag}: timing {args.steps} steps ({args.sweeps} sweeps)")
         t0 = time.perf_counter()
-        ctx.sweep(args.steps)
+        for _ in range(args.steps):
+            ctx.sweep(args.sweeps_per_step)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ctx.check()
         kms, launches = ctx.sweep_time()
         ctx.sweep_timing(False)
         return el, kms, launches
-
-    def median_tau(series, t_idx, lo, m):
-        """per temperature index: median over samples of tau_int of series[mu, t, lo:m]"""
-        return np.array([float(np.median([rlpt.tau_int(series[mu, t, lo:m])[0] for mu in range(S)]))
-                         for t in t_idx])
 
     def long_run(ctx, n, tag):
         """n sweeps in pieces of 10,000, a progress line after each"""
@@ -822,44 +953,63 @@ def main():
                 log(f"{tag}: {done}/{n} sweeps")
 
     def tau_block(ctx, sweeps_per_s, t_idx, extra_sweeps, tag):
-        """continue extra_sweeps sweeps, then tau_int of E at the temperature
-        indices t_idx from the series (first quarter discarded), median over samples"""
+        """continue extra_sweeps sweeps, then tau_int of E and q at the
+        temperature indices t_idx from the series (first quarter discarded),
+        per sample; returns (summary, tau_E per sample, tau_q per sample)"""
         if extra_sweeps > 0:
             long_run(ctx, extra_sweeps, tag)
         o = ctx.observables()
         m = int(o["e_n"][0, 0] / reps)
         m = min(m, series_len)
         lo = m // 4
-        tau = median_tau(o["series_e"], t_idx, lo, m)
-        return {"temperatures": [float(temps[t]) for t in t_idx], "tau_int_E": tau.round(2).tolist(),
-                "tau_int_q": median_tau(o["series_q"], t_idx, lo, m).round(2).tolist(),
-                "sweeps_per_s": sweeps_per_s, "eff_sweeps_per_s": (sweeps_per_s / (2 * tau)).round(3).tolist(),
-                "series_points": m - lo}
+        tE = tau_per_sample(o["series_e"], t_idx, lo, m)
+        tq = tau_per_sample(o["series_q"], t_idx, lo, m)
+        return ({"temperatures": [float(temps[t]) for t in t_idx], "tau_int_E": tau_stats(tE),
+                 "tau_int_q": tau_stats(tq), "sweeps_per_s": sweeps_per_s,
+                 "eff_sweeps_per_s_E": (sweeps_per_s / (2 * np.median(tE, axis=1))).round(3).tolist(),
+                 "series_points": m - lo}, tE, tq)
 
     # ---------------------------------------------------------------- headline: per-copy pairs
     ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, **common)
     el, kms, launches = timed(ctx, "plain")
     n_copies = ctx.n_copies
-    value = N * n_copies * args.steps / el
+    value = N * n_copies * args.sweeps / el
     # algorithmic bytes of one sweep launch (one sweep): every copy streams, per
     # two-mode step, the lists of j and k; over a sweep of N/2 uniform pairs that
     # is the 4c entries of all lists on average: 8 B per entry in the packed
     # layout, 25 B per 4 entries in the chunked one (padding not counted)
     chunked = args.layout == 2 or (args.layout == 0 and N <= 256 and N >= 32)
     per_entry = 6.25 if chunked else 8.0
-    sweeps_per_launch = args.steps / launches
-    bytes_per_launch = sweeps_per_launch * sum(reps * T * inf["deg_sum"] * per_entry for inf in infos)
+    sweeps_per_launch = args.sweeps / launches
+    entries_per_launch = sweeps_per_launch * sum(reps * T * inf["deg_sum"] for inf in infos)
+    bytes_per_launch = entries_per_launch * per_entry
     t_launch = kms / launches * 1e-3
     achieved = bytes_per_launch / t_launch / 1e9
     traffic = traffic_for_current_kernel(bytes_per_launch)
-    log(f"{value:.4g} mode-updates/s; sweep kernel {kms / launches:.3f} ms/launch, {achieved:.0f} GB/s")
-    sweeps_per_s = args.steps / el
+    log(f"{value:.4g} mode-updates/s; sweep kernel {kms / launches:.3f} ms/launch, {achieved:.0f} GB/s algorithmic")
+    roof = {"bound": "hbm", "achieved": achieved, "unit": "GB/s", "kernel": "k_sweep",
+            "ms_per_launch": kms / launches, "bytes_per_entry": per_entry,
+            "entries_per_launch": entries_per_launch, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "hbm_peak_published": HBM_PEAK_GBS, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None,
+            "traffic_GBps": traffic / t_launch / 1e9 if traffic else None}
+    if chunked and not args.shared_pairs:
+        ms_ceiling = ctx.stream_lists(10)
+        ceiling = bytes_per_launch / (ms_ceiling * 1e-3) / 1e9
+        roof.update({"peak": ceiling, "frac": achieved / ceiling, "ceiling_ms_per_launch": ms_ceiling,
+                     "peak_kind": "measured: the memory hierarchy (L2, Infinity Cache, HBM) streaming exactly the "
+                                  "lists of one sweep launch in the sweep's grid, tile and order with no arithmetic "
+                                  "(rlpt_stream_lists); the algorithmic rate exceeds the published HBM peak because "
+                                  "the lists (270 MB) are re-read from L2 and the Infinity Cache"})
+        log(f"list-stream ceiling {ms_ceiling:.3f} ms/launch = {ceiling:.0f} GB/s; sweep at {achieved / ceiling:.3f}")
+    else:
+        roof.update({"peak": HBM_PEAK_GBS, "frac": achieved / HBM_PEAK_GBS, "peak_kind": "published HBM peak"})
+    sweeps_per_s = args.sweeps / el
     t_learn = [t for t in args.learn_temps if t < T]
-    tau_plain = None
+    tau_plain = tau_plain_E = None
     if args.tau_sweeps > 0:
         log(f"plain: {args.tau_sweeps} more sweeps for tau_int")
-        tau_plain = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps, "plain")
-    ctx.close()
+        tau_plain, tau_plain_E, _ = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps, "plain")
     out = {
         "metric": METRIC,
         "value": value,
@@ -874,44 +1024,41 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"plain PT N={N}, {S} samples x {T} temperatures x {reps} replicas, FP32 fields, "
-                               f"FP64 resync/100, swap+measure every sweep",
+                               f"FP64 resync/100, swap+measure every sweep; one step = {args.sweeps_per_step} sweeps",
                    "n_modes": N, "samples": S, "temperatures": T, "replicas": reps, "copies": n_copies,
+                   "sweeps_per_step": args.sweeps_per_step,
                    "terms_per_sample": [inf["n_terms"] for inf in infos],
                    "pair_schedule": "shared per sample" if args.shared_pairs else "per copy",
                    "list_layout": "chunked" if chunked else "packed"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_sweep", "ms_per_launch": kms / launches,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None,
-                     "traffic_GBps": traffic / t_launch / 1e9 if traffic else None,
-                     "note": "algorithmic bytes: every list entry a step reads; traffic: rocprofv3 fabric bytes "
-                             "(L2 misses) of the same launch; each XCD's L2 serves its sample's repeated lists"},
+        "roofline": roof,
         "sweeps_per_s": sweeps_per_s,
     }
-    # ---------------------------------------------------------------- cached local fields
-    # same chain, fields kept per copy; per step the pair list of (j -> k), per
-    # accepted step the gather blocks of j and k
+    # ---------------------------------------------------------------- other variants and configurations
     if not args.no_cached:
-        cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out)
+        cached_fields(args, rlpt, torch, graphs, infos, temps, common, el, n_copies, chunked, out, ctx)
+    ctx.close()
+    if not args.no_cached:
         sparse_graphs(args, rlpt, torch, temps, out)
         ipr_comparison(args, rlpt, torch, out)
         n64_configuration(args, rlpt, torch, out)
         if not args.no_n64:
             n64_physics(args, rlpt, torch, out)
             n64_protocol(args, rlpt, torch, out, out["n64_physics"]["cv_per_mode"])
+    if not args.no_batched and not args.no_cached:
+        out["batched"] = batched(args, short=True)
     if args.tau_sweeps > 0 and args.learn_temps and not args.no_n64:
         learned_n64(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature); tau_int_q: overlap q of the two "
-                             "replicas, same window", "estimator": "Sokal window c=6",
+                             "replicas, same window", "estimator": "Sokal window c=6, per disorder sample",
                "plain": tau_plain}
         # ------------------------------------------------------------ shared pair schedule
         if not args.shared_pairs:
             ctx = rlpt.Context(graphs, temps, shared_pairs=1, **common)
             el2, _, _ = timed(ctx, "shared pairs")
-            tau["shared_pairs"] = tau_block(ctx, args.steps / el2, t_learn, args.tau_sweeps, "shared pairs")
-            tau["shared_pairs"]["mode_updates_per_s"] = N * n_copies * args.steps / el2
+            tau["shared_pairs"], tE2, _ = tau_block(ctx, args.sweeps / el2, t_learn, args.tau_sweeps, "shared pairs")
+            tau["shared_pairs"]["mode_updates_per_s"] = N * n_copies * args.sweeps / el2
+            tau["shared_vs_plain_eff"] = eff_ratio(tE2, tau_plain_E, args.sweeps / el2, sweeps_per_s)
             ctx.close()
         # ------------------------------------------------------------ learned global moves
         if t_learn:
@@ -919,43 +1066,58 @@ def main():
             ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, mlp_nets=len(t_learn),
                                mlp_hidden=256, mlp_components=4, mlp_capacity=8192, mlp_batch=512, **lcommon)
             ctx.init(1)
-            ctx.sweep(args.warmup)
+            ctx.sweep(args.warm_sweeps)
             ctx.mlp_setup(t_learn, seed=1)
             log("learned: harvest and train")
             t0 = time.perf_counter()
             ctx.mlp_harvest(rounds=args.harvest_rounds, lag=2)
-            loss0 = ctx.mlp_train(1, 1e-3)
-            loss = ctx.mlp_train(args.train_steps, 1e-3)
+            losses, train_error = [], None
+            try:
+                losses.append(ctx.mlp_train(1, 1e-3))
+                losses.append(ctx.mlp_train(args.train_steps, 1e-3))
+            except rlpt.RlptError as e:
+                train_error = str(e)
+                log(f"learned: training failed: {e}")
             t_train = time.perf_counter() - t0
-            ctx.mlp_enable(1, args.learn_scale)
+            if train_error is None:
+                ctx.mlp_enable(1, args.learn_scale)
             # the harvest ran without swaps: re-equilibrate with swaps and learned rounds before the window
             ctx.sweep(args.reeq)
             done = ctx.counters()[0]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ctx.sweep(args.steps)
+            ctx.sweep(args.sweeps)
             torch.cuda.synchronize()
             el3 = time.perf_counter() - t0
-            log(f"learned: {args.steps / el3:.1f} sweeps/s; tau_int run")
+            log(f"learned: {args.sweeps / el3:.1f} sweeps/s; tau_int run")
             # measurements started at the warm-up boundary: the series covers harvest + learned sweeps;
             # tau is taken over the learned part only
             long_run(ctx, args.tau_sweeps, "learned")
             o = ctx.observables()
             m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds + args.reeq)
-            lo = max(done - args.warmup, 0) + (m - max(done - args.warmup, 0)) // 4
-            tl = median_tau(o["series_e"], t_learn, lo, m)
+            lo = max(done - args.warm_sweeps, 0) + (m - max(done - args.warm_sweeps, 0)) // 4
+            tEl = tau_per_sample(o["series_e"], t_learn, lo, m)
+            tql = tau_per_sample(o["series_q"], t_learn, lo, m)
             acc, tries = ctx.mlp_stats()
-            sps3 = args.steps / el3
-            tau["learned"] = {"temperatures": [float(temps[t]) for t in t_learn], "tau_int_E": tl.round(2).tolist(),
-                              "tau_int_q": median_tau(o["series_q"], t_learn, lo, m).round(2).tolist(),
-                              "sweeps_per_s": sps3, "eff_sweeps_per_s": (sps3 / (2 * tl)).round(3).tolist(),
-                              "series_points": m - lo, "move_acceptance": (acc / np.maximum(tries, 1)).round(4).tolist(),
-                              "step_scale": args.learn_scale, "train_loss_first_last": [loss0.round(2).tolist(),
-                                                                                        loss.round(2).tolist()],
-                              "harvest_and_train_s": t_train}
+            acc_rate = acc / np.maximum(tries, 1)
+            sps3 = args.sweeps / el3
+            dead = dead_networks(acc_rate, np.array(losses) if losses else None)
+            if train_error:
+                dead.append({"network": "all", "failed": train_error})
+            tau["learned"] = {"temperatures": [float(temps[t]) for t in t_learn], "tau_int_E": tau_stats(tEl),
+                              "tau_int_q": tau_stats(tql), "sweeps_per_s": sps3,
+                              "series_points": m - lo, "move_acceptance": acc_rate.round(4).tolist(),
+                              "step_scale": args.learn_scale,
+                              "train_loss_first_last": [np.round(x, 2).tolist() for x in losses],
+                              "harvest_and_train_s": t_train, "failed_networks": dead}
             ctx.close()
-            tau["learned_vs_plain_eff"] = (np.array(tau["learned"]["eff_sweeps_per_s"])
-                                           / np.array(tau_plain["eff_sweeps_per_s"])).round(3).tolist()
+            ratio = eff_ratio(tEl, tau_plain_E, sps3, sweeps_per_s)
+            for d in dead:
+                if isinstance(d["network"], int):
+                    ratio["status"][d["network"]] = "failed: " + d["failed"]
+                else:
+                    ratio["status"] = ["failed: " + d["failed"]] * len(ratio["status"])
+            tau["learned_vs_plain_eff"] = ratio
         out["tau_int_corrected"] = tau
     if not args.no_cpu_baseline:
         try:

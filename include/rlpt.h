@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define RLPT_ABI_VERSION 3
+#define RLPT_ABI_VERSION 4
 
 enum {
     RLPT_OK = 0,
@@ -227,6 +227,21 @@ int rlpt_run_graph(rlpt_ctx* ctx, int32_t n_sweeps, int32_t n_segments);
 int rlpt_sweep_timing(rlpt_ctx* ctx, int32_t enable);
 int rlpt_sweep_time_get(rlpt_ctx* ctx, double* total_ms, int64_t* n_launches);
 
+/* Roofline diagnostic of the streaming sweep (sec. III.A "Energy update
+ * parallel computation": each two-mode update streams the lists of j and k).
+ * Runs n_launches launches of a kernel with the sweep kernel's grid, items,
+ * tile and LDS footprint that reads exactly the list chunks one sweep launch
+ * reads (the next sweeps' pair draws, same threads, same order) and does
+ * nothing else: no amplitudes, no arithmetic beyond a checksum, no
+ * reductions or barriers between steps.  *ms_per_launch receives the mean
+ * kernel time (HIP events on the context's stream): the time the memory
+ * hierarchy needs to deliver one sweep's lists in this access pattern, the
+ * ceiling of the sweep's list stream.  The chain, its counters and
+ * accumulators are unchanged (the checksum goes to the context's scratch
+ * buffer).  Synchronous.  FP32 contexts with chunked lists and streaming
+ * fields only (RLPT_E_UNSUPPORTED otherwise); RLPT_E_STATE before rlpt_init. */
+int rlpt_stream_lists(rlpt_ctx* ctx, int32_t n_launches, double* ms_per_launch);
+
 /* ------------------------------------------------------------------------ */
 /* Autotuning of the sweep kernel's launch tile (workgroup size, copies per  */
 /* workgroup).  A process-wide registry holds measured times per sweep; when */
@@ -366,6 +381,11 @@ int rlpt_observables(rlpt_ctx* ctx, rlpt_obs* out);
 /* displacements.  The harvest runs without swaps: sweep with swaps on again  */
 /* before measuring.                                                          */
 /* Random numbers: Philox keyed (run_seed, "LEARN") at (i, round, copy, 0).   */
+/* The chart (y, psi) covers configurations with every a_k != 0 only: a move  */
+/* from a configuration with a zero (or non-finite) amplitude, or to a        */
+/* proposal whose intensity underflowed to zero, is rejected (log acceptance  */
+/* ratio -inf); training pairs with a zero or non-finite amplitude in either  */
+/* configuration are left out of the minibatch mean.                          */
 /* ------------------------------------------------------------------------ */
 
 /* Initialise weights (seeded), Adam moments and counters; temp_index[mlp_nets]
@@ -381,12 +401,26 @@ int rlpt_mlp_set_pairs(rlpt_ctx* ctx, int32_t net, int32_t n, const double* befo
 /* rounds x (record the copies at each network's temperature, `lag` sweeps
  * without swaps, record the same copies again).  Async-safe: synchronises. */
 int rlpt_mlp_harvest(rlpt_ctx* ctx, int32_t rounds, int32_t lag);
-/* Adam steps (lr) on random minibatches; mean_loss[mlp_nets] of the last step (may be NULL). */
+/* Adam steps (lr) on random minibatches; mean_loss[mlp_nets] (may be NULL)
+ * receives each network's loss on the last step's minibatch, averaged over its
+ * pairs inside the chart.  Synchronises.  RLPT_E_STATE when a network's last
+ * loss is not finite or its last minibatch held no pair inside the chart
+ * (mean_loss is filled first; NaN for the latter). */
 int rlpt_mlp_train(rlpt_ctx* ctx, int32_t steps, double lr, double* mean_loss);
 /* Test hooks: outputs of network `net` on the first n stored "before"
- * configurations; loss and gradient on the first mlp_batch stored pairs. */
+ * configurations (the training forward: three matrix-core GEMMs of n <=
+ * mlp_batch rows); loss (mean over the pairs inside the chart; RLPT_E_STATE if
+ * none) and gradient on the first mlp_batch stored pairs. */
 int rlpt_mlp_forward(rlpt_ctx* ctx, int32_t net, int32_t n, double* out);
 int rlpt_mlp_loss_grad(rlpt_ctx* ctx, int32_t net, double* loss, float* grad);
+/* Test hook: the inference forward that learned rounds run (one fused launch
+ * when samples x replicas <= 16 and 2N, mlp_hidden are multiples of 128, the
+ * three GEMMs otherwise) of network `net` on n <= samples x replicas caller
+ * configurations states[n][N] (interleaved complex doubles, converted to
+ * FP32); out[n][outputs].  Uses the network's inference buffers (outputs at
+ * the current configurations of the last learned round are overwritten).
+ * Synchronous.  Errors: RLPT_E_ARG, RLPT_E_STATE (no rlpt_mlp_setup). */
+int rlpt_mlp_infer(rlpt_ctx* ctx, int32_t net, int32_t n, const double* states, double* out);
 /* Learned rounds after every sweep (0 = off) with the given step scale in (0, 1]. */
 int rlpt_mlp_enable(rlpt_ctx* ctx, int32_t moves_per_sweep, double step_scale);
 /* One learned round of every network now (async). */

@@ -993,6 +993,39 @@ int rlpt_sweep_time_get(rlpt_ctx* c, double* total_ms, int64_t* n_launches) {
     return RLPT_OK;
 }
 
+int rlpt_stream_lists(rlpt_ctx* c, int32_t n_launches, double* ms_per_launch) {
+    if (!c || !ms_per_launch) return fail(RLPT_E_ARG, "NULL argument");
+    if (n_launches < 1) return fail(RLPT_E_ARG, "n_launches must be >= 1");
+    if (c->cfg.precision != RLPT_FP32 || c->layout != kLayoutChunked || c->sh.cached || c->sh.short_lists)
+        return fail(RLPT_E_UNSUPPORTED, "the list-stream ceiling covers the FP32 streaming sweep over chunked lists");
+    if (!c->inited) return fail(RLPT_E_STATE, "rlpt_init has not been called");
+    const size_t sink_floats = (size_t)c->launch.n_items * (c->launch.block_threads / 64);
+    if (sink_floats > 2 * c->scratch_doubles) return fail(RLPT_E_ARG, "too many workgroups for the scratch buffer");
+    float* sink = reinterpret_cast<float*>(c->scratch);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RLPT_E_HIP, "event create");
+    }
+    double total = 0.0;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n_launches && e == hipSuccess; ++i) {
+        e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = launch_stream_lists(c->ptrs(), c->sh, c->launch, i, sink, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        total += ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(RLPT_E_HIP, std::string("list-stream ceiling: ") + hipGetErrorString(e));
+    *ms_per_launch = total / n_launches;
+    return RLPT_OK;
+}
+
 int rlpt_counters(rlpt_ctx* c, int64_t* sweeps_done, int64_t* swaps_done, int64_t* n_meas) {
     if (!c) return fail(RLPT_E_ARG, "ctx is NULL");
     if (sweeps_done) *sweeps_done = c->sweeps_done;

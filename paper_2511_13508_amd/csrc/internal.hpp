@@ -174,6 +174,10 @@ size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item
 
 hipError_t launch_init(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int block,
                        hipStream_t st);
+// list-stream ceiling of the streaming sweep (FP32, chunked lists): reads what
+// one sweep launch reads, nothing else; sink holds n_items x waves floats
+hipError_t launch_stream_lists(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int64_t sweep_offset,
+                               float* sink, hipStream_t st);
 hipError_t launch_sweep(int precision, const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L,
                         int n_sweeps, hipStream_t st);
 hipError_t launch_swap(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st);

@@ -550,6 +550,73 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(DevPtrs<R> P, ShapeInfo sh, int
     }
 }
 
+// ---------------------------------------------------------------- list-stream ceiling
+// Diagnostic for the streaming sweep's roofline: the same grid, items, tile
+// and LDS footprint (so the same workgroups per CU) as k_sweep, the same pair
+// draws, and every list chunk of every step read in the same order by the
+// same threads, the copy's threads meeting at a barrier before each step as
+// in the sweep -- but nothing else: no amplitudes, no arithmetic beyond a
+// checksum, no reductions, no decision.  Its rate is what the memory
+// hierarchy (L2, Infinity Cache, HBM) delivers for the sweep's access
+// schedule, the ceiling its list stream can reach.  (Without the per-step
+// barrier the waves of a copy drift apart and the same reads took 17 %
+// longer at N = 256.)  Launch w reads the draws of sweep (sweeps done + sweep_offset + w);
+// nothing of the chain is changed.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_stream_lists(DevPtrs<float> P, ShapeInfo sh, int max_N,
+                                                        int64_t sweep_offset, float* sink) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kWaves = BLOCK / 64;
+    const ItemDev it = P.items[blockIdx.x];
+    const SampleDev sd = P.samples[it.sample];
+    const int N = sd.N, steps = sd.n_steps;
+    const int wpc = kWaves / it.n_copies;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = wave / wpc;
+    const bool active = g < it.n_copies;
+    const int gsel = active ? g : 0;
+    const int gt = threadIdx.x - g * wpc * 64, nt = wpc * 64;
+    uint32_t* lb = reinterpret_cast<uint32_t*>(smem);
+    int32_t* tab = reinterpret_cast<int32_t*>(smem + bounds_bytes(max_N)) + (size_t)gsel * (max_N / 2 + 1);
+    for (int i = threadIdx.x; i <= N; i += BLOCK) lb[i] = P.chunk_start[sd.mode_base + i];
+    const int c = it.first_copy + gsel;
+    const int64_t pair_stream = sh.shared_pairs ? (int64_t)it.sample : (int64_t)c;
+    const int64_t sweep = P.counters->sweeps_done + sweep_offset;
+    if (active)
+        for (int s = gt; s < steps; s += nt) tab[s] = draw_step<float>(sh.run_seed, pair_stream, c, sweep, s, N, sh.rho).jk;
+    __syncthreads();
+    const float4* __restrict__ Jv = reinterpret_cast<const float4*>(P.cJ);
+    float acc = 0.0f;
+    uint32_t h = 0;
+    for (int s = 0; s < steps; ++s) {
+        __syncthreads();
+        if (active) {
+            const int jk = tab[s];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int l = side ? (jk >> 16) : (jk & 0xffff);
+                const uint32_t end = lb[l + 1];
+                uint32_t cc = lb[l] + gt;
+                for (; cc + nt < end; cc += 2 * nt) {
+                    const float4 j0 = Jv[cc], j1 = Jv[cc + nt];
+                    const uint2 y0 = P.cyz[cc], y1 = P.cyz[cc + nt];
+                    h ^= (uint32_t)P.cx[cc] ^ y0.x ^ y0.y ^ ((uint32_t)P.cx[cc + nt] << 8) ^ y1.x ^ y1.y;
+                    acc += (j0.x + j0.y) + (j0.z + j0.w) + (j1.x + j1.y) + (j1.z + j1.w);
+                }
+                if (cc < end) {
+                    const float4 j0 = Jv[cc];
+                    const uint2 y0 = P.cyz[cc];
+                    h ^= (uint32_t)P.cx[cc] ^ y0.x ^ y0.y;
+                    acc += (j0.x + j0.y) + (j0.z + j0.w);
+                }
+            }
+        }
+    }
+    acc += (float)(h & 0xffu);
+    acc = wave_sum(acc);
+    if (lane == 0) sink[(size_t)blockIdx.x * kWaves + wave] = acc;
+}
+
 // ---------------------------------------------------------------- short lists (sparse graphs)
 // When every mode's list is short (sparse mode-locked graphs, a few dozen
 // terms per mode) a step is pure latency: load two lists, reduce, decide.
@@ -1511,7 +1578,28 @@ hipError_t launch_sweep_r(const void* ptrs, const ShapeInfo& sh, const SweepLaun
     }
 }
 
+template <int BLOCK>
+hipError_t stream_lists_t(const DevPtrs<float>& P, const ShapeInfo& sh, const SweepLaunch& L, int64_t offset,
+                          float* sink, hipStream_t st) {
+    hipLaunchKernelGGL((k_stream_lists<BLOCK>), dim3(L.n_items), dim3(BLOCK), L.lds_bytes, st, P, sh, L.max_N, offset,
+                       sink);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_stream_lists(const void* ptrs, const ShapeInfo& sh, const SweepLaunch& L, int64_t sweep_offset,
+                               float* sink, hipStream_t st) {
+    const DevPtrs<float>& P = *static_cast<const DevPtrs<float>*>(ptrs);
+    switch (L.block_threads) {
+        case 64: return stream_lists_t<64>(P, sh, L, sweep_offset, sink, st);
+        case 128: return stream_lists_t<128>(P, sh, L, sweep_offset, sink, st);
+        case 256: return stream_lists_t<256>(P, sh, L, sweep_offset, sink, st);
+        case 512: return stream_lists_t<512>(P, sh, L, sweep_offset, sink, st);
+        case 1024: return stream_lists_t<1024>(P, sh, L, sweep_offset, sink, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 size_t sweep_lds_bytes(int precision, int block_threads, int max_copies_per_item, int max_N, int cached,
                        int short_lists) {

@@ -323,6 +323,23 @@ __device__ inline float log_w(const float* a, int k, float logN) {
     return 2.0f * logf(u) - logN;
 }
 
+// true in every lane when some amplitude of the configuration is zero or not
+// finite: the configuration is then on the boundary of the alr chart (or
+// garbage) and has no coordinates y
+__device__ inline bool off_chart(const float* a, int N, int lane) {
+    int bad = 0;
+    for (int k = lane; k < N; k += 64) {
+        const float x = a[2 * k], y = a[2 * k + 1];
+        const float u = x * x + y * y;
+        bad |= !(u > 0.0f) || !isfinite(x) || !isfinite(y) || !isfinite(u);
+    }
+    return __any(bad);
+}
+
+// a training pair: features of the first configuration and the displacement
+// (dy, dpsi) to the second.  A pair with either configuration off the chart is
+// left out (tvalid = 0; features and displacement written as zeros so that
+// nothing non-finite reaches the products)
 __global__ __launch_bounds__(64) void k_feat_train(MlpDev M, uint64_t seed, int64_t step, int use_first) {
     const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
     const int N = M.N;
@@ -335,16 +352,31 @@ __global__ __launch_bounds__(64) void k_feat_train(MlpDev M, uint64_t seed, int6
     const float* before = M.data + (((int64_t)net * M.cap + idx) * 2 + 0) * 2 * N;
     const float* after = M.data + (((int64_t)net * M.cap + idx) * 2 + 1) * 2 * N;
     const int64_t item = (int64_t)net * M.Bt + b;
+    float* dl = M.tdelta + item * M.D;
+    const bool out = off_chart(before, N, lane) || off_chart(after, N, lane);
+    if (lane == 0) M.tvalid[item] = out ? 0 : 1;
+    if (out) {
+        for (int k = lane; k < M.In; k += 64) M.tX[item * M.In + k] = 0.0f;
+        for (int d = lane; d < M.D; d += 64) dl[d] = 0.0f;
+        return;
+    }
     write_features(before, N, M.tX + item * M.In, lane);
     const float logN = logf((float)N);
     const float lw0 = log_w(before, N - 1, logN), lw1 = log_w(after, N - 1, logN);
-    float* dl = M.tdelta + item * M.D;
     for (int k = lane; k < N; k += 64) {
         if (k < N - 1) dl[k] = (log_w(after, k, logN) - lw1) - (log_w(before, k, logN) - lw0);
         const float p0 = atan2f(before[2 * k + 1], before[2 * k]);
         const float p1 = atan2f(after[2 * k + 1], after[2 * k]);
         dl[N - 1 + k] = wrapf(p1 - p0);
     }
+}
+
+// test hook: features of rows [0, n) of network net from the configurations in M.ap
+__global__ __launch_bounds__(64) void k_feat_ap(MlpDev M, int net, int n) {
+    const int b = blockIdx.x, lane = threadIdx.x;
+    if (b >= n) return;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    write_features(M.ap + item * 2 * M.N, M.N, M.X + item * M.In, lane);
 }
 
 // ------------------------------------------------------------------ mixture head
@@ -404,6 +436,15 @@ __global__ __launch_bounds__(64) void k_head_train(MlpDev M) {
     const float* O = M.tO + item * M.Out;
     const float* dl = M.tdelta + item * D;
     float* dO = M.tdO + item * M.Out;
+    // the loss is the mean over the minibatch's pairs inside the chart; the others get no gradient
+    int nv = 0;
+    for (int i = lane; i < M.Bt; i += 64) nv += M.tvalid[(int64_t)net * M.Bt + i];
+    nv = (int)wsum((float)nv);  // exact: an integer count far below 2^24
+    if (!M.tvalid[item] || nv == 0) {
+        for (int o = lane; o < M.Out; o += 64) dO[o] = 0.0f;
+        if (lane == 0) M.tloss[item] = 0.0f;
+        return;
+    }
     Mix mw;
     mix_weights(O, K, mw);
     float ell[kMaxK], best = -INFINITY;
@@ -420,7 +461,7 @@ __global__ __launch_bounds__(64) void k_head_train(MlpDev M) {
     float s = 0.0f;
     for (int m = 0; m < K; ++m) s += expf(ell[m] - best);
     const float logp = best + logf(s);
-    const float inv = 1.0f / (float)M.Bt;
+    const float inv = 1.0f / (float)nv;
     for (int m = 0; m < K; ++m) {
         const float r = expf(ell[m] - logp);
         if (lane == 0) dO[m] = (expf(mw.lw[m]) - r) * inv;
@@ -573,8 +614,18 @@ __global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, Shap
         ap[2 * k + 1] = A * sn;
     }
     dref = wsum(dref);
-    __syncthreads();  // ap complete: the network's input at the proposal (the current one's forward is done)
-    write_features(ap, N, M.X + item * M.In, lane);
+    __syncthreads();  // ap complete
+    // a move from a configuration off the alr chart (a zero amplitude), or to a
+    // proposal with an intensity that underflowed to zero, is rejected: its
+    // reference-density term is -inf, and the proposal is replaced by the
+    // current configuration so that the later stages see finite values only
+    const bool out = off_chart(a, N, lane) || off_chart(ap, N, lane);
+    if (out) {
+        for (int k = lane; k < 2 * N; k += 64) ap[k] = a[k];
+        dref = -INFINITY;
+    }
+    __syncthreads();
+    write_features(ap, N, M.X + item * M.In, lane);  // the network's input at the proposal
     const float lq = log_mix(O, sdel, 1.0f, scale, N, K, D, lane);
     if (lane == 0) {
         M.lqf[item] = lq;
@@ -669,7 +720,8 @@ __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, Shape
     float dE = 0.0f;  // the energy change's parts, added in order
     for (int p = 0; p < kEnergyParts; ++p) dE += M.dEp[item * kEnergyParts + p];
     const float beta = P.beta[M.temp_index[net]];
-    const float la = -beta * dE + M.dref[item] + lqr - M.lqf[item];
+    const float dref = M.dref[item];
+    const float la = dref == -INFINITY ? -INFINITY : -beta * dE + dref + lqr - M.lqf[item];
     const int nb = (D + 1) / 2;
     const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
     const double ua = uniform01<double>(wu.v[1]);
@@ -828,6 +880,11 @@ hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const Sha
 
 hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st) {
     hipLaunchKernelGGL(k_accept, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
+    return hipGetLastError();
+}
+
+hipError_t mlp_features_from_proposals(const MlpDev& M, int net, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_feat_ap, dim3((unsigned)n), dim3(64), 0, st, M, net, n);
     return hipGetLastError();
 }
 

@@ -58,7 +58,8 @@ struct MlpDev {
     float* tdA;      // [nets][Bt][H] backward scratch
     float* tdB;      // [nets][Bt][H]
     float* tdelta;   // [nets][Bt][D]
-    float* tloss;    // [nets][Bt]
+    float* tloss;    // [nets][Bt] per-pair loss (0 for pairs left out)
+    int32_t* tvalid; // [nets][Bt] 1 when both configurations of the pair are inside the alr chart
     float* data;     // [nets][cap][2][2N] pairs (before, after), interleaved complex
     int32_t* temp_index;  // [nets]
     int32_t* count;  // [nets] stored pairs
@@ -80,5 +81,7 @@ hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const Sha
 hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
 hipError_t mlp_harvest(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, int which, int slot0,
                        hipStream_t st);
+// features of rows [0, n) of network net from configurations held in M.ap (test hook)
+hipError_t mlp_features_from_proposals(const MlpDev& M, int net, int n, hipStream_t st);
 
 }  // namespace rlpt

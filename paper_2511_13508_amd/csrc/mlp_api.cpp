@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.tdB = f(n * Bt * m.H);
     m.tdelta = f(n * Bt * m.D);
     m.tloss = f(n * Bt);
+    m.tvalid = (int32_t*)f(n * Bt);
     m.data = f(n * (size_t)m.cap * 2 * 2 * N);
     m.temp_index = (int32_t*)f(n);
     m.count = (int32_t*)f(n);
@@ -129,6 +131,30 @@ int mlp_ready(rlpt_ctx* c) {
         hipError_t e_ = (expr);                                                          \
         if (e_ != hipSuccess) return fail(RLPT_E_HIP, std::string(what) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// per network, the mean loss of the last training minibatch over its pairs
+// inside the chart and the number of such pairs (synchronous)
+int minibatch_loss(rlpt_ctx* c, std::vector<double>* loss, std::vector<int>* used) {
+    const MlpDev& M = c->mlp;
+    std::vector<float> L((size_t)M.nets * M.Bt);
+    std::vector<int32_t> V((size_t)M.nets * M.Bt);
+    HIP_TRY2(hipMemcpy(L.data(), M.tloss, L.size() * 4, hipMemcpyDeviceToHost), "read loss");
+    HIP_TRY2(hipMemcpy(V.data(), M.tvalid, V.size() * 4, hipMemcpyDeviceToHost), "read pair flags");
+    loss->assign(M.nets, 0.0);
+    used->assign(M.nets, 0);
+    for (int n = 0; n < M.nets; ++n) {
+        double t = 0;
+        int u = 0;
+        for (int b = 0; b < M.Bt; ++b)
+            if (V[(size_t)n * M.Bt + b]) {
+                t += L[(size_t)n * M.Bt + b];
+                ++u;
+            }
+        (*loss)[n] = u ? t / u : NAN;
+        (*used)[n] = u;
+    }
+    return RLPT_OK;
+}
 
 }  // namespace
 
@@ -280,27 +306,34 @@ int rlpt_mlp_train(rlpt_ctx* c, int32_t steps, double lr, double* mean_loss) {
     MlpDev& M = c->mlp;
     for (int n = 0; n < M.nets; ++n)
         if (c->mlp_count[n] < 1) return fail(RLPT_E_STATE, "no training pairs: call rlpt_mlp_harvest first");
-    std::vector<double> loss_sum(M.nets, 0.0);
-    std::vector<float> L((size_t)M.nets * M.Bt);
+    if (steps < 0) return fail(RLPT_E_ARG, "steps must be >= 0");
     for (int s = 0; s < steps; ++s) {
         HIP_TRY2(mlp_features_train(M, c->mlp_seed, c->mlp_adam_t, 0, c->stream), "train features");
         HIP_TRY2(mlp_forward(M, 1, 0, c->stream), "train forward");
         HIP_TRY2(mlp_backward(M, c->stream), "train backward");
         c->mlp_adam_t += 1;
         HIP_TRY2(mlp_adam(M, (float)lr, c->mlp_adam_t, c->stream), "adam");
-        if (mean_loss && s == steps - 1) {
-            HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
-            HIP_TRY2(hipMemcpy(L.data(), M.tloss, L.size() * 4, hipMemcpyDeviceToHost), "read loss");
-            for (int n = 0; n < M.nets; ++n) {
-                double t = 0;
-                for (int b = 0; b < M.Bt; ++b) t += L[(size_t)n * M.Bt + b];
-                loss_sum[n] = t / M.Bt;
-            }
-        }
     }
     HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
+    if (steps == 0) {
+        if (mean_loss)
+            for (int n = 0; n < M.nets; ++n) mean_loss[n] = 0.0;
+        return RLPT_OK;
+    }
+    // the last step's loss: mean over the minibatch's pairs inside the chart
+    std::vector<double> loss;
+    std::vector<int> used;
+    rc = minibatch_loss(c, &loss, &used);
+    if (rc) return rc;
     if (mean_loss)
-        for (int n = 0; n < M.nets; ++n) mean_loss[n] = loss_sum[n];
+        for (int n = 0; n < M.nets; ++n) mean_loss[n] = loss[n];
+    for (int n = 0; n < M.nets; ++n) {
+        if (used[n] == 0)
+            return fail(RLPT_E_STATE, "network " + std::to_string(n) +
+                                          ": no training pair of the last minibatch lies inside the chart");
+        if (!std::isfinite(loss[n]))
+            return fail(RLPT_E_STATE, "network " + std::to_string(n) + ": non-finite training loss");
+    }
     return RLPT_OK;
 }
 
@@ -334,13 +367,33 @@ int rlpt_mlp_loss_grad(rlpt_ctx* c, int32_t net, double* loss, float* grad) {
     HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
     if (grad)
         HIP_TRY2(hipMemcpy(grad, M.grad + (size_t)net * M.NP, (size_t)M.NP * 4, hipMemcpyDeviceToHost), "read grad");
-    if (loss) {
-        std::vector<float> L(M.Bt);
-        HIP_TRY2(hipMemcpy(L.data(), M.tloss + (size_t)net * M.Bt, L.size() * 4, hipMemcpyDeviceToHost), "read loss");
-        double t = 0;
-        for (float v : L) t += v;
-        *loss = t / M.Bt;
-    }
+    std::vector<double> L;
+    std::vector<int> used;
+    rc = minibatch_loss(c, &L, &used);
+    if (rc) return rc;
+    if (loss) *loss = L[net];
+    if (used[net] == 0) return fail(RLPT_E_STATE, "no stored pair of the minibatch lies inside the chart");
+    return RLPT_OK;
+}
+
+// inference forward of network `net` (the path learned rounds take) on n <= S*reps
+// configurations given by the caller (test hook): out = outputs [n][Out]
+int rlpt_mlp_infer(rlpt_ctx* c, int32_t net, int32_t n, const double* states, double* out) {
+    int rc = mlp_ready(c);
+    if (rc) return rc;
+    const MlpDev& M = c->mlp;
+    if (net < 0 || net >= M.nets || n < 1 || n > M.Bm || !states || !out) return fail(RLPT_E_ARG, "bad inference request");
+    std::vector<float> buf((size_t)n * 2 * M.N);
+    for (size_t i = 0; i < buf.size(); ++i) buf[i] = (float)states[i];
+    HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_TRY2(hipMemcpy(M.ap + (size_t)net * M.Bm * 2 * M.N, buf.data(), buf.size() * 4, hipMemcpyHostToDevice),
+             "upload states");
+    HIP_TRY2(mlp_features_from_proposals(M, net, n, c->stream), "features");
+    HIP_TRY2(mlp_forward(M, 0, 0, c->stream), "forward");
+    HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
+    std::vector<float> o((size_t)n * M.Out);
+    HIP_TRY2(hipMemcpy(o.data(), M.Of + (size_t)net * M.Bm * M.Out, o.size() * 4, hipMemcpyDeviceToHost), "read");
+    for (size_t i = 0; i < o.size(); ++i) out[i] = o[i];
     return RLPT_OK;
 }
 

@@ -21,19 +21,20 @@ SPLIT_A, SPLIT_B, SPLIT_C, SPLIT_ALL = 1, 2, 4, 7
 FP32, FP64 = 0, 1
 LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_CHUNKED = 0, 1, 2
 FIELDS_STREAM, FIELDS_CACHED = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 # every symbol declared in include/rlpt.h
 EXPORTS = [
     "rlpt_abi_version", "rlpt_last_error", "rlpt_graph_build", "rlpt_graph_free", "rlpt_graph_info_get",
     "rlpt_graph_export", "rlpt_config_default", "rlpt_workspace_size", "rlpt_create", "rlpt_destroy",
     "rlpt_init", "rlpt_sweep", "rlpt_swap", "rlpt_resync", "rlpt_check", "rlpt_run_graph", "rlpt_sweep_timing",
-    "rlpt_sweep_time_get", "rlpt_counters",
-    "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64", "rlpt_local_fields",
+    "rlpt_sweep_time_get", "rlpt_counters", "rlpt_stream_lists",
+    "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64",
+    "rlpt_local_fields",
     "rlpt_pair_dE", "rlpt_observables", "rlpt_tau_int", "rlpt_tune_clear", "rlpt_tune_set", "rlpt_tune_get",
     "rlpt_tune_save", "rlpt_tune_load", "rlpt_autotune", "rlpt_tile_of", "rlpt_mlp_setup", "rlpt_mlp_n_params",
     "rlpt_mlp_set_params", "rlpt_mlp_get_params", "rlpt_mlp_set_pairs", "rlpt_mlp_harvest", "rlpt_mlp_train",
-    "rlpt_mlp_forward", "rlpt_mlp_loss_grad", "rlpt_mlp_enable", "rlpt_mlp_move", "rlpt_mlp_stats",
+    "rlpt_mlp_forward", "rlpt_mlp_loss_grad", "rlpt_mlp_infer", "rlpt_mlp_enable", "rlpt_mlp_move", "rlpt_mlp_stats",
     "rlpt_mlp_last_move", "rlpt_summarize", "rlpt_adaptive_ladder", "rlpt_window_means",
     "rlpt_checkpoint_save", "rlpt_checkpoint_load"]
 
@@ -118,6 +119,7 @@ def lib() -> C.CDLL:
         "rlpt_sweep_timing": ([P, i32], C.c_int),
         "rlpt_sweep_time_get": ([P, P, P], C.c_int),
         "rlpt_counters": ([P, P, P, P], C.c_int),
+        "rlpt_stream_lists": ([P, i32, P], C.c_int),
         "rlpt_get_state": ([P, i32, i32, P], C.c_int),
         "rlpt_set_state": ([P, i32, i32, P], C.c_int),
         "rlpt_get_energies": ([P, P, P], C.c_int),
@@ -142,6 +144,7 @@ def lib() -> C.CDLL:
         "rlpt_mlp_train": ([P, i32, d, P], C.c_int),
         "rlpt_mlp_forward": ([P, i32, i32, P], C.c_int),
         "rlpt_mlp_loss_grad": ([P, i32, P, P], C.c_int),
+        "rlpt_mlp_infer": ([P, i32, i32, P, P], C.c_int),
         "rlpt_mlp_enable": ([P, i32, d], C.c_int),
         "rlpt_mlp_move": ([P, d], C.c_int),
         "rlpt_mlp_stats": ([P, P, P], C.c_int),
@@ -292,6 +295,12 @@ class Context:
         _check(lib().rlpt_sweep_time_get(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def stream_lists(self, n_launches: int = 5) -> float:
+        """mean ms per launch of the list-stream ceiling kernel (see the header)"""
+        ms = C.c_double()
+        _check(lib().rlpt_stream_lists(self._h, n_launches, C.byref(ms)))
+        return ms.value
+
     def tile(self):
         """(threads per workgroup, copies per workgroup of each sample) of the sweep launch."""
         b = C.c_int32()
@@ -341,6 +350,12 @@ class Context:
         g = np.zeros(self.mlp_sizes()[0], dtype=np.float32)
         _check(lib().rlpt_mlp_loss_grad(self._h, net, C.byref(L), _ptr(g)))
         return L.value, g
+
+    def mlp_infer(self, net: int, states) -> np.ndarray:
+        a = np.ascontiguousarray(states, dtype=np.complex128)
+        out = np.zeros((a.shape[0], self.mlp_sizes()[1]))
+        _check(lib().rlpt_mlp_infer(self._h, net, a.shape[0], _ptr(a), _ptr(out)))
+        return out
 
     def mlp_enable(self, moves_per_sweep: int, step_scale: float = 1.0):
         _check(lib().rlpt_mlp_enable(self._h, moves_per_sweep, step_scale))

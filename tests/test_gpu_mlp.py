@@ -242,3 +242,202 @@ def test_training_lowers_held_out_nll_of_pt_displacements():
         ctx.mlp_set_params(n, p1[n])
         assert np.isfinite(L0) and np.isfinite(L1)
         assert L1 < L0 - 1.0, (n, L0, L1)
+
+
+def _store_pairs(ctx, net, before, after):
+    ctx.mlp_set_pairs(net, before, after)
+    f32 = lambda v: v.astype(np.complex64).astype(np.complex128)  # noqa: E731
+    return f32(before), f32(after)
+
+
+def test_zero_amplitude_training_pairs_are_left_out():
+    """Pairs with an exact zero amplitude (which the FP32 pair move can make)
+    are left out of the training loss, as in the oracle: loss and gradients
+    equal the oracle's over the other pairs, training stays finite, and a
+    store with no usable pair is reported (RLPT_E_STATE), not trained on."""
+    N, H, K, B = 8, 48, 3, 16
+    ctx = mlp_ctx(N, 1, 2, 1, H, K, B, nets=1, cap=B)
+    ctx.init(1)
+    ctx.mlp_setup([0], seed=3)
+    NP, Out = ctx.mlp_sizes()
+    raw = synth.random_mlp_params(2 * N, H, Out, seed=12, out_scale=0.5)
+    ctx.mlp_set_params(0, raw)
+    before = synth.random_constrained_state(N, 22, B)
+    after = synth.random_constrained_state(N, 32, B)
+    before[3, 5] = 0.0
+    after[7, N - 1] = 0.0
+    after[9, 0] = 0.0
+    b, a = _store_pairs(ctx, 0, before, after)
+    params = M.rounded(unflatten(raw, N, H, K))
+    L_ref, g_ref = M.loss_and_grads(params, b, a, N, K)
+    L, g = ctx.mlp_loss_grad(0)
+    assert np.isfinite(L) and L == pytest.approx(L_ref, rel=1e-4)
+    gg = unflatten(g, N, H, K)
+    for k in g_ref:
+        x, y = gg[k].ravel(), g_ref[k].ravel()
+        assert np.all(np.isfinite(x)), k
+        assert np.linalg.norm(x - y) <= 1e-2 * np.linalg.norm(y), k
+    L1 = ctx.mlp_train(20, 1e-3)
+    assert np.all(np.isfinite(L1)) and np.all(np.isfinite(ctx.mlp_get_params(0)))
+    dead = synth.random_constrained_state(N, 40, B)
+    dead[:, 2] = 0.0
+    ctx.mlp_set_pairs(0, dead, after)
+    with pytest.raises(rlpt.RlptError) as e:
+        ctx.mlp_train(1, 1e-3)
+    assert e.value.code == rlpt.RLPT_E_STATE
+    with pytest.raises(rlpt.RlptError):
+        ctx.mlp_loss_grad(0)
+
+
+def test_learned_move_from_a_zero_amplitude_is_rejected(oracle):
+    """A learned item whose copy holds an exact zero amplitude is rejected
+    (log acceptance -inf, state and energy untouched); the other items of the
+    round follow the oracle as usual."""
+    N, S, T, reps, H, K = 8, 2, 2, 2, 32, 2
+    temps = synth.geometric_temps(0.6, 1.4, T)
+    ctx = mlp_ctx(N, S, T, reps, H, K, batch=8, nets=1, temps=temps)
+    ctx.init(5)
+    ctx.mlp_setup([1], seed=1)
+    state = synth.random_constrained_state(N, 51, S * T * reps)
+    zero_copy = 0 * T * reps + 1 * T + 1  # sample 0, ladder 1, temperature 1
+    state[zero_copy, 4] = 0.0
+    ctx.set_state(state)
+    ctx.resync()  # rescales the planted copy onto the constraint; its zero stays zero
+    before = ctx.get_state().reshape(S * T * reps, N)
+    assert before[zero_copy, 4] == 0.0
+    E0, _ = ctx.energies()
+    ctx.mlp_move(0.5)
+    la, copies, _ = ctx.mlp_last_move(0)
+    b = list(copies).index(zero_copy)
+    assert la[b] == -np.inf
+    assert np.all(np.isfinite(np.delete(la, b)))
+    after = ctx.get_state().reshape(S * T * reps, N)
+    assert np.array_equal(after[zero_copy], before[zero_copy])
+    assert ctx.energies()[0][zero_copy] == E0[zero_copy]
+    a_cnt, tries = ctx.mlp_stats()
+    assert tries[0] == S * reps
+
+
+def _infer_ctx(N, S, reps, H, K, batch, seed_graph=0):
+    T = 2
+    graphs = [rlpt.Graph(N, SEED3 + 200 + seed_graph + i) for i in range(S)]
+    return mlp_ctx(N, S, T, reps, H, K, batch, nets=2, cap=max(batch, 64), graphs=graphs,
+                   temps=synth.geometric_temps(0.7, 0.9, T))
+
+
+@pytest.mark.parametrize("S,reps", [(8, 2), (12, 2)])
+def test_inference_forward_at_configured_size(S, reps):
+    """The learned-proposal configuration's network (N = 64: 128 -> 256 -> 256
+    -> 4-component mixture, 1020 outputs).  With samples x replicas = 16 the
+    inference forward is the one-launch fused kernel, otherwise three GEMMs:
+    outputs against the FP64 oracle on the same bfloat16 operands, and bitwise
+    against the training-path GEMMs on the same configurations; again after
+    new parameters are set and after an Adam step (the fragment-order weight
+    copy must follow both)."""
+    N, H, K = 64, 256, 4
+    Bm = S * reps
+    ctx = _infer_ctx(N, S, reps, H, K, batch=Bm)
+    ctx.init(2)
+    ctx.mlp_setup([0, 1], seed=7)
+    NP, Out = ctx.mlp_sizes()
+    assert Out == 1020
+    states = synth.random_constrained_state(N, 60, Bm)
+    b32, a32 = _store_pairs(ctx, 1, states, synth.random_constrained_state(N, 61, Bm))
+
+    def check(net, raw):
+        o = ctx.mlp_infer(net, states)
+        params = M.rounded(unflatten(raw, N, H, K))
+        o_ref, _ = M.forward(params, M.features(b32))
+        rms = np.sqrt(np.mean(o_ref ** 2))
+        assert np.max(np.abs(o - o_ref)) <= 2e-3 * rms
+        return o
+
+    raw = synth.random_mlp_params(2 * N, H, Out, seed=70, out_scale=0.5)
+    ctx.mlp_set_params(1, raw)
+    o = check(1, raw)
+    assert np.array_equal(o, ctx.mlp_forward(1, Bm))  # the same bits as the three GEMMs
+    raw2 = synth.random_mlp_params(2 * N, H, Out, seed=71, out_scale=0.5)
+    ctx.mlp_set_params(1, raw2)
+    check(1, raw2)
+    ctx.mlp_set_pairs(0, states, synth.random_constrained_state(N, 62, Bm))
+    ctx.mlp_train(1, 1e-2)  # one Adam step on both networks
+    raw3 = ctx.mlp_get_params(1)
+    assert not np.array_equal(raw3, raw2)
+    o3 = check(1, raw3)
+    assert np.array_equal(o3, ctx.mlp_forward(1, Bm))
+
+
+@pytest.mark.parametrize("N", [64, 256])
+def test_gradients_at_configured_size(N):
+    """Training gradients of the configured networks (2N -> 256 -> 256 ->
+    4-component mixture) on a minibatch of 512 pairs: every GEMM runs its
+    multi-stage K loop (K = 128 or 512 inputs, 256 hidden, 512 rows for the
+    weight gradients, 1020 or 4092 outputs for the input gradients).  Per
+    tensor |g - g_ora| <= 1e-2 |g_ora| and cosine >= 0.999 against the FP64
+    oracle on the same bfloat16 operands."""
+    H, K, B = 256, 4, 512
+    graphs = [rlpt.Graph(N, SEED3 + 300 + N)]
+    ctx = mlp_ctx(N, 1, 2, 1, H, K, B, nets=1, cap=B, graphs=graphs)
+    ctx.init(3)
+    ctx.mlp_setup([0], seed=8)
+    NP, Out = ctx.mlp_sizes()
+    raw = synth.random_mlp_params(2 * N, H, Out, seed=80 + N, out_scale=0.5)
+    ctx.mlp_set_params(0, raw)
+    before = synth.random_constrained_state(N, 90 + N, B)
+    after = synth.random_constrained_state(N, 91 + N, B)
+    b, a = _store_pairs(ctx, 0, before, after)
+    params = M.rounded(unflatten(raw, N, H, K))
+    L_ref, g_ref = M.loss_and_grads(params, b, a, N, K)
+    L, g = ctx.mlp_loss_grad(0)
+    assert L == pytest.approx(L_ref, rel=1e-4)
+    gg = unflatten(g, N, H, K)
+    for k in g_ref:
+        x, y = gg[k].ravel(), g_ref[k].ravel()
+        assert np.linalg.norm(x - y) <= 1e-2 * np.linalg.norm(y), k
+        assert np.dot(x, y) / (np.linalg.norm(x) * np.linalg.norm(y)) >= 0.999, k
+
+
+def test_learned_move_matches_oracle_at_configured_size(oracle):
+    """A learned round of the N = 64 configuration's networks (H = 256, K = 4;
+    8 samples x 2 replicas = 16 items: the fused inference forward) against
+    the oracle on the same draws: proposals, log acceptance ratios and the
+    decisions taken away from the boundary."""
+    N, S, T, reps, H, K = 64, 8, 4, 2, 256, 4
+    temps = synth.geometric_temps(0.7, 1.0, T)
+    graphs = [rlpt.Graph(N, SEED3 + 400 + i) for i in range(S)]
+    ctx = mlp_ctx(N, S, T, reps, H, K, batch=16, nets=2, graphs=graphs, temps=temps)
+    ctx.init(6)
+    ctx.mlp_setup([1, 2], seed=2)
+    NP, Out = ctx.mlp_sizes()
+    raw = [synth.random_mlp_params(2 * N, H, Out, seed=140 + n, out_scale=0.05) for n in range(2)]
+    for n in range(2):
+        ctx.mlp_set_params(n, raw[n])
+    state = synth.random_constrained_state(N, 150, S * T * reps)
+    ctx.set_state(state)
+    ctx.resync()
+    state32 = state.astype(np.complex64).astype(np.complex128)
+    scale = 0.05
+    ctx.mlp_move(scale)
+    after = ctx.get_state().reshape(S * T * reps, N)
+    ogs = [oracle.Graph(N, SEED3 + 400 + i) for i in range(S)]
+    decided = 0
+    for n, t in enumerate([1, 2]):
+        params = M.rounded(unflatten(raw[n], N, H, K))
+        la, copies, prop = ctx.mlp_last_move(n)
+        for b in range(S * reps):
+            mu, r = divmod(b, reps)
+            c = mu * T * reps + r * T + t
+            assert copies[b] == c
+            g, uc, ua = M.draws(6, 0, c, 2 * N - 1)
+            E0 = oracle.energy(ogs[mu], state32[c])
+            dH = lambda an: np.array([oracle.energy(ogs[mu], x) for x in an]) - E0  # noqa
+            an, la_ref, parts = M.move_log_alpha(params, state32[c][None], dH, 1.0 / temps[t], N, K, scale, g[None],
+                                                 np.array([uc]))
+            np.testing.assert_allclose(prop[b], an[0], rtol=0, atol=5e-4)
+            mag = abs(parts["lq_f"][0]) + abs(parts["lq_r"][0]) + abs(parts["dlogref"][0]) + abs(parts["dH"][0]) / temps[t]
+            assert la[b] == pytest.approx(la_ref[0], abs=5e-3 + 2e-5 * mag), (n, b)
+            if abs(math.log(ua) - la_ref[0]) > 2e-2 + 4e-5 * mag:
+                accepted = math.log(ua) < la_ref[0]
+                np.testing.assert_allclose(after[c], an[0] if accepted else state32[c], rtol=0, atol=5e-4)
+                decided += 1
+    assert decided >= S * reps  # most of the 32 decisions are away from the boundary
