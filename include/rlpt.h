@@ -320,6 +320,19 @@ int rlpt_get_energies(rlpt_ctx* ctx, double* E, int32_t* temp_of);
 /* FP64 energy of every copy (no state change). */
 int rlpt_energy_fp64(rlpt_ctx* ctx, double* E);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * energy of every copy, as rlpt_energy_fp64 computes it (same kernels, same
+ * summation order, the same bits), written to the caller's device array
+ * d_E[n_copies], asynchronously on the context's stream, with no state
+ * change.  It allocates nothing and copies nothing to or from the host: its
+ * partial sums (8 per copy) live in a static device array of the library,
+ * 2 MiB per GPU (at most 32768 copies; RLPT_E_ARG beyond), held until the
+ * process ends.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (contexts on different streams) race.  Errors: RLPT_E_ARG
+ * (NULL, too many copies), RLPT_E_HIP (launch). */
+int rlpt_energy_fp64_noalloc(rlpt_ctx* ctx, double* d_E);
+
 /* Local fields F_l = sum over terms containing l of J conj(a_x) a_y a_z
  * (x: l's partner on its side of the term, (y, z): the other side) of one copy,
  * computed by the sweep kernel's own field code in the context precision.

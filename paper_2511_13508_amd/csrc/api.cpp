@@ -628,6 +628,10 @@ int rlpt_create(const rlpt_config* cfg, const rlpt_graph* const* graphs, int32_t
     if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(RLPT_E_ARG, "workspace must be 256-byte aligned");
     *out = nullptr;
     if ((rc = mlp_check_config(*cfg, graphs, n_graphs))) return rc;
+    {   // set-up of rlpt_energy_fp64_noalloc: the static scratch's address on the current device, once per device
+        void* p = nullptr;
+        HIP_TRY(static_scratch_address(&p), "static scratch address");
+    }
     for (int t = 0; t < cfg->n_temps; ++t) {
         if (!(temps[t] > 0.0) || !isfinite(temps[t])) return fail(RLPT_E_ARG, "temperatures must be finite and > 0");
         if (t > 0 && !(temps[t] > temps[t - 1])) return fail(RLPT_E_ARG, "temperatures must be strictly ascending");
@@ -1108,6 +1112,15 @@ int rlpt_energy_fp64(rlpt_ctx* c, double* E) {
     HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
     const double* ep = c->cfg.precision == RLPT_FP64 ? c->pd.E64 : c->pf.E64;
     HIP_TRY(hipMemcpy(E, ep, c->n_copies * 8, hipMemcpyDeviceToHost), "read energies");
+    return RLPT_OK;
+}
+
+int rlpt_energy_fp64_noalloc(rlpt_ctx* c, double* d_E) {
+    if (!c || !d_E) return fail(RLPT_E_ARG, "NULL argument");
+    if ((size_t)c->n_copies * kResyncParts * sizeof(double) > kStaticScratchBytes)
+        return fail(RLPT_E_ARG, "too many copies for the static scratch (" +
+                                    std::to_string(kStaticScratchBytes / (kResyncParts * sizeof(double))) + " at most)");
+    HIP_TRY(launch_energy_static(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, d_E, c->stream), "energy launch");
     return RLPT_OK;
 }
 

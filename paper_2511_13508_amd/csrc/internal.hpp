@@ -185,6 +185,13 @@ hipError_t launch_tick(const void* ptrs_any, int precision, int64_t d_sweeps, in
                        hipStream_t st);
 // mode 0: periodic recomputation (drift check, renormalisation, store E);
 // mode 1: FP64 energies into E64 only; mode 2: store E = H without checks
+// FP64 energies of every copy into E[n_copies] (device) with the partial sums
+// in the library's static device scratch: no allocation, no host transfer.
+// hipErrorInvalidValue when n_copies x kResyncParts partials exceed it.
+constexpr size_t kStaticScratchBytes = (size_t)2 << 20;
+hipError_t static_scratch_address(void** out);
+hipError_t launch_energy_static(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, double* E,
+                                hipStream_t st);
 hipError_t launch_resync(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int mode,
                          hipStream_t st);
 hipError_t launch_measure(int precision, const void* ptrs, const ShapeInfo& sh, hipStream_t st);

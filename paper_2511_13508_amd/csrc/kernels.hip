@@ -17,6 +17,8 @@
 //     cross-wave sum in LDS, barrier, then one lane decides, updates LDS and
 //     prepares the next step's snapshot.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 
 #include "internal.hpp"
@@ -1678,6 +1680,55 @@ static hipError_t resync_t(const void* ptrs, const ShapeInfo& sh, int n_copies, 
 hipError_t launch_resync(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, int mode, hipStream_t st) {
     return precision == RLPT_FP64 ? resync_t<double>(ptrs, sh, n_copies, mode, st)
                                   : resync_t<float>(ptrs, sh, n_copies, mode, st);
+}
+
+// ---------------------------------------------------------------- FP64 energies without allocation
+// Device scratch of the energy call that allocates nothing: the partial
+// energies of the FP64 recomputation's term ranges, kResyncParts per copy.
+// One array per GPU for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress gives on that GPU (the array's
+// name is a host-side stand-in there).  Every call on a GPU shares it.
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+template <typename R>
+static hipError_t energy_static_t(const void* ptrs, const ShapeInfo& sh, int n_copies, void* scratch_ptr, double* E,
+                                  hipStream_t st) {
+    DevPtrs<R> P = *static_cast<const DevPtrs<R>*>(ptrs);
+    P.rs_part = static_cast<double*>(scratch_ptr);  // every partial is written before it is read
+    P.E64 = E;                                      // mode 1 writes E64 only
+    return resync_t<R>(&P, sh, n_copies, 1, st);
+}
+
+hipError_t launch_energy_static(int precision, const void* ptrs, const ShapeInfo& sh, int n_copies, double* E,
+                                hipStream_t st) {
+    if ((size_t)n_copies * kResyncParts * sizeof(double) > kStaticScratchBytes) return hipErrorInvalidValue;
+    void* p = nullptr;
+    hipError_t e = static_scratch_address(&p);
+    if (e != hipSuccess) return e;
+    return precision == RLPT_FP64 ? energy_static_t<double>(ptrs, sh, n_copies, p, E, st)
+                                  : energy_static_t<float>(ptrs, sh, n_copies, p, E, st);
 }
 
 template <typename R>

@@ -29,7 +29,7 @@ EXPORTS = [
     "rlpt_graph_export", "rlpt_config_default", "rlpt_workspace_size", "rlpt_create", "rlpt_destroy",
     "rlpt_init", "rlpt_sweep", "rlpt_swap", "rlpt_resync", "rlpt_check", "rlpt_run_graph", "rlpt_sweep_timing",
     "rlpt_sweep_time_get", "rlpt_counters", "rlpt_stream_lists",
-    "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64",
+    "rlpt_get_state", "rlpt_set_state", "rlpt_get_energies", "rlpt_energy_fp64", "rlpt_energy_fp64_noalloc",
     "rlpt_local_fields",
     "rlpt_pair_dE", "rlpt_observables", "rlpt_tau_int", "rlpt_tune_clear", "rlpt_tune_set", "rlpt_tune_get",
     "rlpt_tune_save", "rlpt_tune_load", "rlpt_autotune", "rlpt_tile_of", "rlpt_mlp_setup", "rlpt_mlp_n_params",
@@ -124,6 +124,7 @@ def lib() -> C.CDLL:
         "rlpt_set_state": ([P, i32, i32, P], C.c_int),
         "rlpt_get_energies": ([P, P, P], C.c_int),
         "rlpt_energy_fp64": ([P, P], C.c_int),
+        "rlpt_energy_fp64_noalloc": ([P, P], C.c_int),
         "rlpt_local_fields": ([P, i32, P], C.c_int),
         "rlpt_pair_dE": ([P, i32, i32, P, P, P, P, P], C.c_int),
         "rlpt_observables": ([P, P], C.c_int),
@@ -408,6 +409,14 @@ class Context:
         E = np.zeros(self.n_copies)
         _check(lib().rlpt_energy_fp64(self._h, _ptr(E)))
         return E
+
+    def energy_fp64_noalloc(self, out) -> None:
+        """FP64 energies into a caller-owned float64 device tensor `out` of
+        n_copies elements, asynchronously on the context's stream (the library
+        allocates nothing; see the header)."""
+        import torch
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous() and out.numel() >= self.n_copies
+        _check(lib().rlpt_energy_fp64_noalloc(self._h, C.c_void_p(out.data_ptr())))
 
     def checkpoint_save(self, path: str):
         _check(lib().rlpt_checkpoint_save(self._h, str(path).encode()))
