@@ -294,8 +294,9 @@ int rlpt_counters(rlpt_ctx* ctx, int64_t* sweeps_done, int64_t* swaps_done, int6
 
 /* Amplitudes of n_copies copies starting at first_copy, each 2*N doubles
  * (interleaved re, im); all copies in the range must belong to samples of one N.
- * set_state converts to the context precision and does NOT update energies
- * (call rlpt_resync afterwards). */
+ * set_state converts to the context precision and sets every copy's running
+ * energy to its FP64 recomputation (no drift check, no rescaling onto the
+ * constraint: rlpt_resync does that). */
 int rlpt_get_state(rlpt_ctx* ctx, int32_t first_copy, int32_t n_copies, double* a);
 int rlpt_set_state(rlpt_ctx* ctx, int32_t first_copy, int32_t n_copies, const double* a);
 

@@ -274,3 +274,179 @@ def rounded(params):
     """Weights as the GPU uses them: bfloat16 matrices, FP32 biases."""
     return {k: (bf16_round(v) if k.startswith("W") else np.asarray(v, np.float32).astype(np.float64))
             for k, v in params.items()}
+
+
+# ----------------------------------------------------------------- the subset move
+# A structured variant of the learned move (also not in the paper): each move
+# redraws a random subset S of m modes and leaves the others where they are.
+#   S: m distinct modes drawn uniformly (a partial Fisher-Yates shuffle), in
+#     ascending order s_1 < ... < s_m; the draw does not depend on the state,
+#     so its probability cancels in the acceptance ratio.
+#   chart of the subset: with w = |a|^4 / N and W_S = sum_{i in S} w_i fixed,
+#     u_i = log(w_{s_i} / w_{s_m}) (i < m) and the phases psi_{s_i}.  Under
+#     the flat law of eq. ProbDistr the other modes fixed leave w_S / W_S
+#     Dirichlet(1/2, ..., 1/2), whose density in u is prod_{i in S} w_i^(1/2)
+#     up to a constant: the reference ratio only involves S.
+#   proposal: the network's mixture at a (same outputs as the all-mode move):
+#     component c from its weights, du_i = s (mu_c[s_i] + sigma_c[s_i] g_i) from
+#     the y channel of mode s_i (i < m), dpsi_i = s (mu_c[N-1+s_i] +
+#     sigma_c[N-1+s_i] g_{m-1+i}) from its phase channel; wrapped phases.
+#   acceptance: min(1, exp(-beta dH) prod_S (w'/w)^(1/2) q(-d | a') / q(d | a)),
+#     q the subset mixture density at the network's outputs; a move touching a
+#     zero amplitude of S is rejected as for the all-mode move.
+#   training: the negative log-likelihood of a harvested pair's displacement
+#     in the chart of a random subset drawn for each training item.
+def index_below(w: int, n: int) -> int:
+    """index in [0, n) from the top 32 bits of a 64-bit word"""
+    return ((int(w) >> 32) * n) >> 32
+
+
+def subset_draw(words, N: int, m: int) -> np.ndarray:
+    """m distinct modes, ascending: a partial Fisher-Yates shuffle of 0..N-1
+    whose step t swaps position t with t + index_below(word_t, N - t)."""
+    perm = list(range(N))
+    for t in range(m):
+        j = t + index_below(words[t], N - t)
+        perm[t], perm[j] = perm[j], perm[t]
+    return np.array(sorted(perm[:m]), dtype=np.int64)
+
+
+def subset_draws(run_seed: int, move: int, copy: int, N: int, m: int):
+    """Draws of one subset move: Philox (run_seed, LEARN) at counter
+    (i, move, copy, 1): blocks i < nb = ceil((2m-1)/2) give the Gaussians
+    (Box-Muller on word pairs, as draws()), block nb the component and
+    acceptance uniforms (words 0, 1), blocks nb+1+t//4 word t%4 the shuffle
+    words.  Returns (S, g [2m-1], u_comp, u_acc)."""
+    D = 2 * m - 1
+    nb = (D + 1) // 2
+    g = np.zeros(2 * nb)
+    for i in range(nb):
+        w = O.philox([i, move, copy, 1], [run_seed, TAG_LEARN])
+        for h in range(2):
+            u1 = 1.0 - (int(w[2 * h]) >> 11) * 2.0 ** -53
+            u2 = (int(w[2 * h + 1]) >> 11) * 2.0 ** -53
+            g[2 * i + h] = math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+    w = O.philox([nb, move, copy, 1], [run_seed, TAG_LEARN])
+    uc, ua = (int(w[0]) >> 11) * 2.0 ** -53, (int(w[1]) >> 11) * 2.0 ** -53
+    words = []
+    for b in range((m + 3) // 4):
+        words.extend(int(x) for x in O.philox([nb + 1 + b, move, copy, 1], [run_seed, TAG_LEARN]))
+    return subset_draw(words[:m], N, m), g[:D], uc, ua
+
+
+def subset_coords(a: np.ndarray, S: np.ndarray):
+    """(u [m-1], psi_S [m], w_S [m]) of one configuration in the chart of S"""
+    N = a.shape[-1]
+    w = np.abs(a[S]) ** 4 / N
+    return np.log(w[:-1]) - np.log(w[-1]), np.angle(a[S]), w
+
+
+def subset_channels(N: int, S: np.ndarray):
+    """output indices (within a component's D values) of the subset's
+    coordinates: y channel of s_1..s_{m-1}, then phase channel of s_1..s_m"""
+    return np.concatenate([S[:-1], N - 1 + S])
+
+
+def subset_log_q(o: np.ndarray, S: np.ndarray, du: np.ndarray, dpsi: np.ndarray, N: int, K: int,
+                 scale: float):
+    """log density of the subset displacement (du [..., m-1], dpsi [..., m])
+    under the scaled mixture of one output row o: unwrapped in u, wrapped
+    (|n| <= 3) in psi.  A float for one displacement, an array for a batch."""
+    lw, mu, sigma, _ = mixture(o[None], N, K)
+    ch = subset_channels(N, S)
+    m = len(S)
+    mu, sigma = scale * mu[0][:, ch], scale * sigma[0][:, ch]  # [K][2m-1]
+    du = np.asarray(du, dtype=np.float64)[..., None, :]        # [..., 1, m-1]
+    dpsi = np.asarray(dpsi, dtype=np.float64)[..., None, :]    # [..., 1, m]
+    ly = -np.sum(np.log(sigma[:, :m - 1]) + 0.5 * LOG2PI + 0.5 * ((du - mu[:, :m - 1]) / sigma[:, :m - 1]) ** 2,
+                 axis=-1)
+    d = wrap(dpsi - mu[:, m - 1:])
+    t = [(d + 2.0 * math.pi * n) / sigma[:, m - 1:] for n in range(-3, 4)]
+    lp = np.log(sum(np.exp(-0.5 * x * x) for x in t)) - np.log(sigma[:, m - 1:]) - 0.5 * LOG2PI
+    r = np.logaddexp.reduce(lw[0] + ly + np.sum(lp, axis=-1), axis=-1)
+    return float(r) if np.ndim(r) == 0 else r
+
+
+def subset_move_log_alpha(params, a: np.ndarray, S: np.ndarray, dH, beta: float, N: int, K: int, scale: float,
+                          g: np.ndarray, u_comp: float):
+    """One subset move of one configuration a [N].  Returns (a_new, log
+    acceptance ratio, parts).  dH: callable a_new -> energy change, or None
+    for infinite temperature."""
+    m = len(S)
+    inside = bool(np.all(np.isfinite(a[S]) & (np.abs(a[S]) > 0.0)))
+    o_f, _ = forward(params, features(a[None]))
+    lw, mu, sigma, _ = mixture(o_f, N, K)
+    c = min(int(np.sum(np.cumsum(np.exp(lw[0])) <= u_comp)), K - 1)
+    ch = subset_channels(N, S)
+    d = scale * mu[0, c, ch] + scale * sigma[0, c, ch] * g
+    du, dpsi = d[:m - 1], d[m - 1:]
+    a_new = a.copy()
+    if inside:
+        u, psi, w = subset_coords(a, S)
+        e = np.concatenate([np.exp(u + du), [1.0]])
+        wn = w.sum() * e / e.sum()
+        a_new[S] = (N * wn) ** 0.25 * np.exp(1j * (psi + dpsi))
+        inside = bool(np.all(np.abs(a_new[S]) > 0.0))
+    if not inside:
+        return a.copy(), -np.inf, {"inside": False, "component": c, "du": du, "dpsi": dpsi}
+    o_r, _ = forward(params, features(a_new[None]))
+    lq_f = subset_log_q(o_f[0], S, du, dpsi, N, K, scale)
+    lq_r = subset_log_q(o_r[0], S, -du, -dpsi, N, K, scale)
+    w0 = np.abs(a[S]) ** 4 / N
+    w1 = np.abs(a_new[S]) ** 4 / N
+    dref = 0.5 * float(np.sum(np.log(w1) - np.log(w0)))
+    de = 0.0 if dH is None else float(dH(a_new))
+    la = -beta * de + dref + lq_r - lq_f
+    return a_new, la, {"inside": True, "component": c, "du": du, "dpsi": dpsi, "dH": de, "lq_f": lq_f,
+                       "lq_r": lq_r, "dlogref": dref}
+
+
+def subset_displacement(a: np.ndarray, b: np.ndarray, S: np.ndarray):
+    """(du, dpsi) from a to b in the chart of S (b's subset intensity need
+    not equal a's: only the ratios enter u)"""
+    ua, pa, _ = subset_coords(a, S)
+    ub, pb, _ = subset_coords(b, S)
+    return ub - ua, wrap(pb - pa)
+
+
+def subset_nll_and_grad(o: np.ndarray, subsets, deltas, N: int, K: int):
+    """Mean negative log-likelihood of the subset displacements (one subset
+    and one displacement [2m-1] per row of o [B, Out]) under the unwrapped
+    mixture restricted to the subset's channels, and its gradient with
+    respect to o (zero outside the logits and those channels)."""
+    B, Out = o.shape
+    D = 2 * N - 1
+    lw, mu, sigma, smax = mixture(o, N, K)
+    g = np.zeros_like(o)
+    L = 0.0
+    for b in range(B):
+        ch = subset_channels(N, subsets[b])
+        z = (deltas[b][None, :] - mu[b][:, ch]) / sigma[b][:, ch]
+        ell = lw[b] - np.sum(np.log(sigma[b][:, ch]) + 0.5 * LOG2PI + 0.5 * z * z, axis=-1)
+        logp = np.logaddexp.reduce(ell)
+        r = np.exp(ell - logp)
+        L -= logp
+        g[b, :K] = (np.exp(lw[b]) - r) / B
+        for k in range(K):
+            g[b, K + k * D + ch] = -(r[k] * z[k] / sigma[b][k, ch]) / B
+            g[b, K + K * D + k * D + ch] = -(r[k] * (z[k] ** 2 - 1.0) * (1.0 - sigma[b][k, ch] / smax[ch])) / B
+    return L / B, g
+
+
+def subset_loss_and_grads(params, a_before, a_after, subsets, N, K, gemm_bf16=True):
+    """Training loss of the subset move on pairs of configurations (one subset
+    per pair) and its parameter gradients; pairs with a zero or non-finite
+    amplitude in their subset are left out (ValueError when none is left)."""
+    keep = np.array([bool(np.all(np.isfinite(x[S]) & (np.abs(x[S]) > 0)) and np.all(np.isfinite(y[S]) &
+                                                                                      (np.abs(y[S]) > 0)))
+                     for x, y, S in zip(a_before, a_after, subsets)])
+    if not np.any(keep):
+        raise ValueError("no training pair inside the chart")
+    a_before = np.asarray(a_before)[keep]
+    a_after = np.asarray(a_after)[keep]
+    subsets = [S for S, k in zip(subsets, keep) if k]
+    X = features(a_before)
+    o, cache = forward(params, X, gemm_bf16)
+    deltas = [np.concatenate(subset_displacement(x, y, S)) for x, y, S in zip(a_before, a_after, subsets)]
+    L, dO = subset_nll_and_grad(o, subsets, deltas, N, K)
+    return L, backward(params, cache, dO)

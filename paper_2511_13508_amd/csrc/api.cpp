@@ -1082,6 +1082,8 @@ int rlpt_set_state(rlpt_ctx* c, int32_t first, int32_t n, const double* a) {
     HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
     HIP_TRY(hipMemcpy(c->scratch, a, k * 16, hipMemcpyHostToDevice), "state write");
     HIP_TRY(launch_convert_state(c->cfg.precision, amp + off * 2 * c->real_bytes(), c->scratch, k, 1, c->stream), "convert");
+    // the running energies follow the new configurations (FP64, as at init; no drift check, no rescaling)
+    HIP_TRY(launch_resync(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, 2, c->stream), "energies");
     if ((rc = refresh_fields(c))) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
     return RLPT_OK;

@@ -228,3 +228,135 @@ def test_learned_moves_touching_the_chart_boundary_are_rejected(oracle):
     a2 = np.array([oracle.init_copy(N, 16, c) for c in range(2)])
     an, la2, parts2 = M.move_log_alpha(big, a2, None, 0.0, N, K, 1.0, g[:2], uc[:2])
     assert np.all(la2 == -np.inf) and not np.any(parts2["inside"])
+
+
+# ------------------------------------------------------------------ the subset move
+def test_subset_draw_is_a_uniform_subset():
+    """The partial Fisher-Yates shuffle gives m distinct ascending modes, each
+    mode with probability m/N and each pair of modes with m(m-1)/(N(N-1))
+    (a uniform m-subset); m = N gives every mode."""
+    N, m, n = 9, 3, 20000
+    rng = np.random.default_rng(21)
+    cnt = np.zeros(N)
+    pair = np.zeros((N, N))
+    for _ in range(n):
+        S = M.subset_draw([int(x) for x in rng.integers(0, 2 ** 64, size=m, dtype=np.uint64)], N, m)
+        assert len(set(S)) == m and np.all(np.diff(S) > 0)
+        cnt[S] += 1
+        pair[np.ix_(S, S)] += 1
+    p = m / N
+    assert np.all(np.abs(cnt / n - p) < 5 * math.sqrt(p * (1 - p) / n))
+    q = m * (m - 1) / (N * (N - 1))
+    off = pair[~np.eye(N, dtype=bool)] / n
+    assert np.all(np.abs(off - q) < 5 * math.sqrt(q * (1 - q) / n))
+    assert np.array_equal(M.subset_draw([5, 7, 9, 11, 13], 5, 5), np.arange(5))
+
+
+def test_subset_move_changes_only_the_subset_and_keeps_the_constraint(oracle):
+    N, H, K = 7, 12, 2
+    rng = np.random.default_rng(22)
+    params = M.rounded(M.init_params(N, H, K, rng, out_scale=0.5))
+    a = oracle.init_copy(N, 23, 0)
+    S = np.array([1, 4, 6])
+    g = rng.standard_normal(5)
+    an, la, parts = M.subset_move_log_alpha(params, a, S, None, 0.0, N, K, 0.7, g, 0.3)
+    rest = np.setdiff1d(np.arange(N), S)
+    assert np.array_equal(an[rest], a[rest])
+    assert np.sum(np.abs(an) ** 4) == pytest.approx(N, rel=1e-12)
+    assert np.sum(np.abs(an[S]) ** 4) == pytest.approx(np.sum(np.abs(a[S]) ** 4), rel=1e-12)
+    du, dpsi = M.subset_displacement(a, an, S)
+    np.testing.assert_allclose(du, parts["du"], atol=1e-12)
+    np.testing.assert_allclose(M.wrap(dpsi - parts["dpsi"]), 0.0, atol=1e-12)
+    assert np.isfinite(la)
+    z = a.copy()
+    z[4] = 0.0
+    assert M.subset_move_log_alpha(params, z, S, None, 0.0, N, K, 0.7, g, 0.3)[1] == -np.inf
+    assert np.isfinite(M.subset_move_log_alpha(params, z, np.array([0, 2, 3]), None, 0.0, N, K, 0.7, g, 0.3)[1])
+
+
+def test_subset_proposal_density_integrates_to_one():
+    """m = 2: one u coordinate and two phases; q over R x T^2 on a grid."""
+    N, K = 5, 2
+    rng = np.random.default_rng(24)
+    _, D, Out = M.sizes(N, K)
+    o = rng.standard_normal(Out)
+    o[K + K * D:] += 1.0
+    S = np.array([1, 3])
+    us = np.linspace(-14, 14, 561)
+    ps = np.linspace(-math.pi, math.pi, 73)[:-1]
+    U, P1, P2 = np.meshgrid(us, ps, ps, indexing="ij")
+    lq = M.subset_log_q(o, S, U.reshape(-1, 1), np.stack([P1.reshape(-1), P2.reshape(-1)], axis=1), N, K, 1.0)
+    tot = np.exp(lq).sum() * (us[1] - us[0]) * (ps[1] - ps[0]) ** 2
+    assert tot == pytest.approx(1.0, rel=3e-3)
+
+
+def test_subset_nll_gradient_finite_differences(oracle):
+    N, H, K = 5, 10, 2
+    rng = np.random.default_rng(25)
+    params = M.init_params(N, H, K, rng, out_scale=0.5)
+    a = np.array([oracle.init_copy(N, 26, c) for c in range(6)])
+    b = np.array([oracle.init_copy(N, 27, c) for c in range(6)])
+    subsets = [np.sort(rng.choice(N, 3, replace=False)) for _ in range(6)]
+    L, grads = M.subset_loss_and_grads(params, a, b, subsets, N, K, gemm_bf16=False)
+    h = 1e-6
+    for name in ("W1", "b2", "W3", "b3"):
+        flat = params[name].reshape(-1)
+        for i in rng.choice(flat.size, 4, replace=False):
+            old = flat[i]
+            flat[i] = old + h
+            Lp, _ = M.subset_loss_and_grads(params, a, b, subsets, N, K, gemm_bf16=False)
+            flat[i] = old - h
+            Lm, _ = M.subset_loss_and_grads(params, a, b, subsets, N, K, gemm_bf16=False)
+            flat[i] = old
+            assert grads[name].reshape(-1)[i] == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5, abs=1e-8), name
+
+
+def _subset_chain(oracle, N, m, beta, graph, n_chains, n_moves, scale, seed, H=16, K=2):
+    rng = np.random.default_rng(seed)
+    params = M.init_params(N, H, K, rng, out_scale=1.0)
+    a = np.array([oracle.init_copy(N, seed, c) for c in range(n_chains)])
+    q = None if graph is None else graph.quads.astype(np.int64)
+    E = None if graph is None else brute.energy_batch(q, graph.J, a)
+    hist, ehist, acc = [], [], 0
+    for _ in range(n_moves):
+        for c in range(n_chains):
+            S = np.sort(rng.choice(N, m, replace=False))
+            g = rng.standard_normal(2 * m - 1)
+            dH = None if graph is None else (lambda an: brute.energy_batch(q, graph.J, an[None])[0] - E[c])  # noqa
+            an, la, parts = M.subset_move_log_alpha(params, a[c], S, dH, beta, N, K, scale, g, rng.uniform())
+            if math.log(rng.uniform()) < la:
+                a[c] = an
+                acc += 1
+                if graph is not None:
+                    E[c] += parts["dH"]
+        hist.append(a.copy())
+        if graph is not None:
+            ehist.append(E.copy())
+    return np.array(hist), (np.array(ehist) if ehist else None), acc / (n_chains * n_moves)
+
+
+def test_subset_chain_keeps_infinite_temperature_law(oracle):
+    """Subset moves alone from exact beta = 0 draws keep the closed-form
+    marginals: a wrong subset reference ratio or reverse density would not."""
+    N, m = 5, 3
+    hist, _, acc = _subset_chain(oracle, N, m, 0.0, None, n_chains=800, n_moves=25, scale=0.8, seed=28)
+    assert 0.1 < acc < 0.95
+    ref = brute.beta0_moments(N)
+    u = np.abs(hist[5:]) ** 2
+    assert u.mean() == pytest.approx(ref["E|a|^2"], abs=5 * u.std() / math.sqrt(800 * N))
+    assert (u ** 4).mean() == pytest.approx(ref["E|a|^8"], abs=5 * (u ** 4).std() / math.sqrt(800 * N))
+
+
+@pytest.mark.slow
+def test_subset_chain_samples_boltzmann_law(oracle):
+    """At finite beta, subset moves alone reproduce the importance-sampling
+    reference <E> of the N = 4 comb (one term)."""
+    N = 4
+    g = oracle.Graph(N, 0, oracle.OMEGA_COMB)
+    g.J = np.array([2.0])
+    _, E, acc = _subset_chain(oracle, N, 2, 1.0, g, n_chains=200, n_moves=400, scale=0.8, seed=29)
+    ref, err = brute.importance_reference(g.quads.astype(np.int64), g.J, N, [1.0], M=1000000, seed=30)
+    per_chain = E[150:].mean(axis=0)
+    se = per_chain.std() / math.sqrt(len(per_chain))
+    assert 0.1 < acc < 0.95
+    assert per_chain.mean() == pytest.approx(ref["E"][0], abs=4 * math.sqrt(se ** 2 + err["E"][0] ** 2))
