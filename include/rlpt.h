@@ -162,6 +162,10 @@ typedef struct rlpt_config {
                                  K^2 = |a_j|^2 + |a_k|^2 and sin^2 theta uniform, the flat law on the
                                  pair's circle, so the energy-only Metropolis test stays exact.
                                  Learned moves need rho = 4. */
+    int32_t mlp_subset;       /* learned move kind: 0 (default) moves every mode at once (the chart of
+                                 all modes); m >= 2 redraws a random subset of m modes (2 <= m <= min(N, 64))
+                                 in the chart of the subset and leaves the others unchanged, its energy
+                                 change summed from the m modes' lists (O(m N^2) per move) */
 } rlpt_config;
 
 /* Fill *cfg with defaults: FP32, per-copy pairs, swap every sweep, FP64
@@ -435,6 +439,17 @@ int rlpt_mlp_loss_grad(rlpt_ctx* ctx, int32_t net, double* loss, float* grad);
  * the current configurations of the last learned round are overwritten).
  * Synchronous.  Errors: RLPT_E_ARG, RLPT_E_STATE (no rlpt_mlp_setup). */
 int rlpt_mlp_infer(rlpt_ctx* ctx, int32_t net, int32_t n, const double* states, double* out);
+/* Subset move (mlp_subset = m >= 2): per move, S = m distinct modes from a
+ * partial Fisher-Yates shuffle of 0..N-1 (step t swaps position t with
+ * t + floor(hi32(word_t) (N - t) / 2^32)), sorted ascending; chart u_i =
+ * log(w_{s_i} / w_{s_m}) (i < m) and the phases of S, the sum of w over S
+ * fixed; the displacement of u_i uses the y channel of mode s_i, that of
+ * psi_{s_i} its phase channel; reference ratio prod_S (w'/w)^(1/2).  Draws:
+ * Philox (run_seed, "LEARN") at (i, round, copy, 1): blocks i < m Gaussians
+ * (2 per block), block m the component and acceptance uniforms, blocks
+ * m + 1 + t/4 word t%4 the shuffle.  Training draws the subset of minibatch
+ * item b at step s from Philox (setup seed, "TRAIN") at (s, net, b, 1 + t/4)
+ * word t%4 and fits the displacement in its chart. */
 /* Learned rounds after every sweep (0 = off) with the given step scale in (0, 1]. */
 int rlpt_mlp_enable(rlpt_ctx* ctx, int32_t moves_per_sweep, double step_scale);
 /* One learned round of every network now (async). */

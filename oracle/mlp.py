@@ -51,6 +51,7 @@ LOG2PI = math.log(2.0 * math.pi)
 SMAX_Y = 2.0
 SMAX_PSI = math.pi / 2.0
 TAG_LEARN = 0x4C4541524E  # "LEARN"
+TAG_TRAIN = 0x545241494E  # "TRAIN"
 
 
 def bf16_round(x) -> np.ndarray:
@@ -332,6 +333,15 @@ def subset_draws(run_seed: int, move: int, copy: int, N: int, m: int):
     for b in range((m + 3) // 4):
         words.extend(int(x) for x in O.philox([nb + 1 + b, move, copy, 1], [run_seed, TAG_LEARN]))
     return subset_draw(words[:m], N, m), g[:D], uc, ua
+
+
+def train_subset(seed: int, step: int, net: int, item: int, N: int, m: int) -> np.ndarray:
+    """The subset of training item `item` of network `net` at training step
+    `step`: Philox (seed, TRAIN) at counter (step, net, item, 1 + t//4), word t%4."""
+    words = []
+    for b in range((m + 3) // 4):
+        words.extend(int(x) for x in O.philox([step, net, item, 1 + b], [seed, TAG_TRAIN]))
+    return subset_draw(words[:m], N, m)
 
 
 def subset_coords(a: np.ndarray, S: np.ndarray):

@@ -604,6 +604,7 @@ int rlpt_config_default(rlpt_config* cfg) {
     cfg->mlp_batch = 512;
     cfg->field_mode = RLPT_FIELDS_STREAM;
     cfg->rho = 4;
+    cfg->mlp_subset = 0;
     return RLPT_OK;
 }
 

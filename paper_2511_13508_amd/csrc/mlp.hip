@@ -336,6 +336,48 @@ __device__ inline bool off_chart(const float* a, int N, int lane) {
     return __any(bad);
 }
 
+// the subset of a subset move or training item: a partial Fisher-Yates
+// shuffle of 0..N-1 in LDS whose step t swaps position t with
+// t + index_below(word(t), N - t), then the m drawn modes in ascending order.
+// Called by every lane of a single-wave workgroup.
+template <typename Word>
+__device__ inline void draw_subset(int N, int m, Word word, int* perm, int* S, int lane) {
+    for (int k = lane; k < N; k += 64) perm[k] = k;
+    __syncthreads();
+    if (lane == 0)
+        for (int t = 0; t < m; ++t) {
+            const int j = t + index_below(word(t), N - t);
+            const int x = perm[t];
+            perm[t] = perm[j];
+            perm[j] = x;
+        }
+    __syncthreads();
+    if (lane < m) {
+        const int v = perm[lane];
+        int r = 0;
+        for (int t = 0; t < m; ++t) r += perm[t] < v ? 1 : 0;
+        S[r] = v;
+    }
+    __syncthreads();
+}
+
+// the output channel (within a component's D values) of subset coordinate d:
+// the y channel of s_d for d < m - 1, then the phase channels of s_1 .. s_m
+__device__ inline int subset_channel(const int* S, int d, int m, int N) {
+    return d < m - 1 ? S[d] : N - 1 + S[d - (m - 1)];
+}
+
+// true in every lane when a mode of S is zero or not finite in configuration a
+__device__ inline bool subset_off_chart(const float* a, const int* S, int m, int lane) {
+    int bad = 0;
+    for (int i = lane; i < m; i += 64) {
+        const float x = a[2 * S[i]], y = a[2 * S[i] + 1];
+        const float u = x * x + y * y;
+        bad |= !(u > 0.0f) || !isfinite(x) || !isfinite(y) || !isfinite(u);
+    }
+    return __any(bad);
+}
+
 // a training pair: features of the first configuration and the displacement
 // (dy, dpsi) to the second.  A pair with either configuration off the chart is
 // left out (tvalid = 0; features and displacement written as zeros so that
@@ -353,6 +395,34 @@ __global__ __launch_bounds__(64) void k_feat_train(MlpDev M, uint64_t seed, int6
     const float* after = M.data + (((int64_t)net * M.cap + idx) * 2 + 1) * 2 * N;
     const int64_t item = (int64_t)net * M.Bt + b;
     float* dl = M.tdelta + item * M.D;
+    if (M.m > 0) {  // subset move: a subset per item, the displacement in its chart
+        __shared__ int perm[kMaxModes / 2];
+        __shared__ int S[kMaxSubset];
+        const int m = M.m;
+        draw_subset(N, m, [&](int t) {
+            return philox4x64((uint64_t)step, (uint64_t)net, (uint64_t)b, (uint64_t)(1 + t / 4), seed, kTagTrain).v[t & 3];
+        }, perm, S, lane);
+        for (int i = lane; i < m; i += 64) M.tsub[item * kMaxSubset + i] = S[i];
+        const bool out = subset_off_chart(before, S, m, lane) || subset_off_chart(after, S, m, lane);
+        if (lane == 0) M.tvalid[item] = out ? 0 : 1;
+        if (out) {
+            for (int k = lane; k < M.In; k += 64) M.tX[item * M.In + k] = 0.0f;
+            for (int d = lane; d < M.D; d += 64) dl[d] = 0.0f;
+            return;
+        }
+        write_features(before, N, M.tX + item * M.In, lane);
+        const float logN = logf((float)N);
+        const int sl = S[m - 1];
+        const float lw0 = log_w(before, sl, logN), lw1 = log_w(after, sl, logN);
+        for (int i = lane; i < m; i += 64) {
+            const int k = S[i];
+            if (i < m - 1) dl[i] = (log_w(after, k, logN) - lw1) - (log_w(before, k, logN) - lw0);
+            const float p0 = atan2f(before[2 * k + 1], before[2 * k]);
+            const float p1 = atan2f(after[2 * k + 1], after[2 * k]);
+            dl[m - 1 + i] = wrapf(p1 - p0);
+        }
+        return;
+    }
     const bool out = off_chart(before, N, lane) || off_chart(after, N, lane);
     if (lane == 0) M.tvalid[item] = out ? 0 : 1;
     if (out) {
@@ -428,6 +498,41 @@ __device__ float log_mix(const float* O, const float* delta, float sign, float s
     return best + logf(s);
 }
 
+// the same over the coordinates of a subset S (2m - 1 values in delta)
+__device__ float log_mix_subset(const float* O, const int* S, const float* delta, float sign, float scale, int N,
+                                int K, int D, int m, int lane) {
+    Mix mw;
+    mix_weights(O, K, mw);
+    float best = -INFINITY, terms[kMaxK];
+    for (int mc = 0; mc < K; ++mc) {
+        float part = 0.0f;
+        for (int d = lane; d < 2 * m - 1; d += 64) {
+            const int ch = subset_channel(S, d, m, N);
+            const float mu = scale * O[K + mc * D + ch];
+            const float sg = scale * smax_of(ch, N) * sigm(O[K + K * D + mc * D + ch]);
+            const float x = sign * delta[d];
+            if (d < m - 1) {
+                const float z = (x - mu) / sg;
+                part += -logf(sg) - 0.5f * kLog2Pi - 0.5f * z * z;
+            } else {
+                const float t0 = wrapf(x - mu);
+                float sw = 0.0f;
+#pragma unroll
+                for (int n = -3; n <= 3; ++n) {
+                    const float t = (t0 + 2.0f * kPiF * n) / sg;
+                    sw += expf(-0.5f * t * t);
+                }
+                part += logf(sw) - logf(sg) - 0.5f * kLog2Pi;
+            }
+        }
+        terms[mc] = mw.lw[mc] + wsum(part);
+        best = fmaxf(best, terms[mc]);
+    }
+    float se = 0.0f;
+    for (int mc = 0; mc < K; ++mc) se += expf(terms[mc] - best);
+    return best + logf(se);
+}
+
 // training head: mean NLL of the unwrapped mixture and its gradient w.r.t. the outputs
 __global__ __launch_bounds__(64) void k_head_train(MlpDev M) {
     const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
@@ -443,6 +548,44 @@ __global__ __launch_bounds__(64) void k_head_train(MlpDev M) {
     if (!M.tvalid[item] || nv == 0) {
         for (int o = lane; o < M.Out; o += 64) dO[o] = 0.0f;
         if (lane == 0) M.tloss[item] = 0.0f;
+        return;
+    }
+    if (M.m > 0) {  // subset move: the likelihood of the subset's coordinates only
+        const int m = M.m, nd = 2 * m - 1;
+        const int* S = M.tsub + item * kMaxSubset;
+        for (int o = lane; o < M.Out; o += 64) dO[o] = 0.0f;
+        __syncthreads();  // the zeros are written before the subset's channels
+        Mix mw;
+        mix_weights(O, K, mw);
+        float ell[kMaxK], best = -INFINITY;
+        for (int mc = 0; mc < K; ++mc) {
+            float part = 0.0f;
+            for (int d = lane; d < nd; d += 64) {
+                const int ch = subset_channel(S, d, m, N);
+                const float sg = smax_of(ch, N) * sigm(O[K + K * D + mc * D + ch]);
+                const float z = (dl[d] - O[K + mc * D + ch]) / sg;
+                part += logf(sg) + 0.5f * kLog2Pi + 0.5f * z * z;
+            }
+            ell[mc] = mw.lw[mc] - wsum(part);
+            best = fmaxf(best, ell[mc]);
+        }
+        float se = 0.0f;
+        for (int mc = 0; mc < K; ++mc) se += expf(ell[mc] - best);
+        const float logp = best + logf(se);
+        const float inv = 1.0f / (float)nv;
+        for (int mc = 0; mc < K; ++mc) {
+            const float r = expf(ell[mc] - logp);
+            if (lane == 0) dO[mc] = (expf(mw.lw[mc]) - r) * inv;
+            for (int d = lane; d < nd; d += 64) {
+                const int ch = subset_channel(S, d, m, N);
+                const float sm = smax_of(ch, N);
+                const float sg = sm * sigm(O[K + K * D + mc * D + ch]);
+                const float z = (dl[d] - O[K + mc * D + ch]) / sg;
+                dO[K + mc * D + ch] = -r * z / sg * inv;
+                dO[K + K * D + mc * D + ch] = -r * (z * z - 1.0f) * (1.0f - sg / sm) * inv;
+            }
+        }
+        if (lane == 0) M.tloss[item] = -logp;
         return;
     }
     Mix mw;
@@ -707,6 +850,191 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
     }
 }
 
+// one standard normal of a subset move's draw (Box-Muller in FP64 on Philox words)
+__device__ inline float subset_gauss(uint64_t seed, int64_t move, int c, int d) {
+    const Philox4 w = philox4x64((uint64_t)(d >> 1), (uint64_t)move, (uint64_t)c, 1, seed, kTagLearn);
+    const int h = d & 1;
+    const double u1 = 1.0 - uniform01<double>(w.v[2 * h]);
+    const double u2 = uniform01<double>(w.v[2 * h + 1]);
+    return (float)(sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2));
+}
+
+// subset move, stage one: the subset, the component, the displacement in the
+// subset's chart, the proposal (other modes copied), the reference ratio, the
+// forward log density and the network's input at the proposal
+__global__ __launch_bounds__(64) void k_propose_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+    __shared__ int perm[kMaxModes / 2];
+    __shared__ int S[kMaxSubset];
+    __shared__ float sdel[2 * kMaxSubset];
+    __shared__ float slw[kMaxSubset];
+    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    const int N = M.N, K = M.K, D = M.D, m = M.m;
+    const int64_t item = (int64_t)net * M.Bm + b;
+    const int c = M.item_copy[item];
+    const int64_t move = *M.moves_done - 1;
+    const float* O = M.Of + item * M.Out;
+    const float* a = copy_amp(P, sh, N, c);
+    Mix mw;
+    mix_weights(O, K, mw);
+    const Philox4 wu = philox4x64((uint64_t)m, (uint64_t)move, (uint64_t)c, 1, sh.run_seed, kTagLearn);
+    const double uc = uniform01<double>(wu.v[0]);
+    int mc = K - 1;
+    double cum = 0.0;
+    for (int i = 0; i < K; ++i) {
+        cum += (double)expf(mw.lw[i]);
+        if (cum > uc) {
+            mc = i;
+            break;
+        }
+    }
+    draw_subset(N, m, [&](int t) {
+        return philox4x64((uint64_t)(m + 1 + t / 4), (uint64_t)move, (uint64_t)c, 1, sh.run_seed, kTagLearn).v[t & 3];
+    }, perm, S, lane);
+    for (int d = lane; d < 2 * m - 1; d += 64) {
+        const int ch = subset_channel(S, d, m, N);
+        const float mu = scale * O[K + mc * D + ch];
+        const float sg = scale * smax_of(ch, N) * sigm(O[K + K * D + mc * D + ch]);
+        const float del = mu + sg * subset_gauss(sh.run_seed, move, c, d);
+        sdel[d] = del;
+        M.delta[item * D + d] = del;
+    }
+    const float logN = logf((float)N);
+    for (int i = lane; i < m; i += 64) {
+        slw[i] = log_w(a, S[i], logN);
+        M.subset[item * kMaxSubset + i] = S[i];
+    }
+    __syncthreads();
+    // u' = u + du (u'_m = 0); the subset's total intensity is kept:
+    // log w'_i = v_i - logsumexp(v) + logsumexp(log w_S)
+    float mx = -INFINITY, mx0 = -INFINITY;
+    for (int i = lane; i < m; i += 64) {
+        mx = fmaxf(mx, i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f);
+        mx0 = fmaxf(mx0, slw[i]);
+    }
+    mx = wmax(mx);
+    mx0 = wmax(mx0);
+    float se = 0.0f, se0 = 0.0f;
+    for (int i = lane; i < m; i += 64) {
+        se += expf((i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f) - mx);
+        se0 += expf(slw[i] - mx0);
+    }
+    const float lse = mx + logf(wsum(se)), ltot = mx0 + logf(wsum(se0));
+    float* ap = M.ap + item * 2 * N;
+    for (int k = lane; k < 2 * N; k += 64) ap[k] = a[k];
+    __syncthreads();
+    float dref = 0.0f;
+    for (int i = lane; i < m; i += 64) {
+        const int k = S[i];
+        const float lwn = (i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f) - lse + ltot;
+        dref += 0.5f * (lwn - slw[i]);
+        const float A = expf(0.25f * (logN + lwn));
+        const float ph = atan2f(a[2 * k + 1], a[2 * k]) + sdel[m - 1 + i];
+        float sn, cs;
+        sincosf(ph, &sn, &cs);
+        ap[2 * k] = A * cs;
+        ap[2 * k + 1] = A * sn;
+    }
+    dref = wsum(dref);
+    __syncthreads();
+    // a move touching a zero amplitude of S (now or in the proposal) is rejected
+    const bool out = subset_off_chart(a, S, m, lane) || subset_off_chart(ap, S, m, lane);
+    if (out) {
+        for (int i = lane; i < m; i += 64) {
+            ap[2 * S[i]] = a[2 * S[i]];
+            ap[2 * S[i] + 1] = a[2 * S[i] + 1];
+        }
+        dref = -INFINITY;
+    }
+    __syncthreads();
+    write_features(ap, N, M.X + item * M.In, lane);
+    const float lq = log_mix_subset(O, S, sdel, 1.0f, scale, N, K, D, m, lane);
+    if (lane == 0) {
+        M.lqf[item] = lq;
+        M.dref[item] = dref;
+    }
+}
+
+// field F_l = sum over l's list of J conj(a_x) a_y a_z from amplitudes a in
+// LDS; thread t of nt takes every nt-th chunk (chunked lists) or group of 4
+// entries (packed lists)
+__device__ inline void list_field(const DevPtrs<float>& P, const SampleDev& sd, int layout, int l, const float2* a,
+                                  int t, int nt, float& fr, float& fi) {
+    if (layout == kLayoutChunked) {
+        const uint32_t* cs = P.chunk_start + sd.mode_base;
+        const float4* Jv = reinterpret_cast<const float4*>(P.cJ);
+        for (uint32_t q = cs[l] + t; q < cs[l + 1]; q += nt) {
+            const float2 ax = a[P.cx[q]];
+            const uint2 yz = P.cyz[q];
+            const float4 j = Jv[q];
+            const uint32_t v[4] = {yz.x & 0xffffu, yz.x >> 16, yz.y & 0xffffu, yz.y >> 16};
+            const float jj[4] = {j.x, j.y, j.z, j.w};
+            float gr = 0.0f, gi = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 ay = a[v[i] & 0xffu], az = a[(v[i] >> 8) & 0xffu];
+                gr += jj[i] * (ay.x * az.x - ay.y * az.y);
+                gi += jj[i] * (ay.x * az.y + ay.y * az.x);
+            }
+            fr += ax.x * gr + ax.y * gi;
+            fi += ax.x * gi - ax.y * gr;
+        }
+    } else {
+        const uint32_t* ms = P.mode_start + sd.mode_base;
+        for (uint32_t q = ms[l] + t; q < ms[l + 1]; q += nt) {
+            const uint32_t e = P.idx[q];
+            const float2 ax = a[e & 1023u], ay = a[(e >> 10) & 1023u], az = a[e >> 20];
+            const float pr = ax.x * ay.x + ax.y * ay.y, pi = ax.x * ay.y - ax.y * ay.x;
+            fr += P.J[q] * (pr * az.x - pi * az.y);
+            fi += P.J[q] * (pr * az.y + pi * az.x);
+        }
+    }
+}
+
+// subset move, stage two: the energy change, mode by mode on a snapshot that
+// already holds the proposal for the modes before: dE = sum_i -2 Re(conj(a'_i - a_i) F_i)
+// (exact: every term holds a mode at most once).  One 256-thread workgroup per item.
+__global__ __launch_bounds__(256) void k_energy_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
+    extern __shared__ float2 sa[];  // [N] the snapshot
+    __shared__ float red[4][2];
+    const int64_t item = blockIdx.x;
+    const int N = M.N, m = M.m;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (M.dref[item] == -INFINITY) {  // rejected in stage one
+        if (threadIdx.x == 0) M.dE[item] = 0.0f;
+        return;
+    }
+    const int c = M.item_copy[item];
+    const SampleDev sd = P.samples[c / sh.copies_per_sample];
+    const float* a = copy_amp(P, sh, N, c);
+    const float* ap = M.ap + item * 2 * N;
+    const int* S = M.subset + item * kMaxSubset;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) sa[k] = make_float2(a[2 * k], a[2 * k + 1]);
+    __syncthreads();
+    float dE = 0.0f;
+    for (int i = 0; i < m; ++i) {
+        const int l = S[i];
+        float fr = 0.0f, fi = 0.0f;
+        list_field(P, sd, sh.layout, l, sa, threadIdx.x, blockDim.x, fr, fi);
+        fr = wsum(fr);
+        fi = wsum(fi);
+        if (lane == 0) {
+            red[wave][0] = fr;
+            red[wave][1] = fi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const float Fr = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+            const float Fi = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+            const float2 o = sa[l];
+            const float nr = ap[2 * l], ni = ap[2 * l + 1];
+            dE += -2.0f * ((nr - o.x) * Fr + (ni - o.y) * Fi);
+            sa[l] = make_float2(nr, ni);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) M.dE[item] = dE;
+}
+
 __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
     __shared__ float sdel[2 * kMaxModes];
     const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
@@ -714,16 +1042,26 @@ __global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, Shape
     const int64_t item = (int64_t)net * M.Bm + b;
     const int c = M.item_copy[item];
     const int64_t move = *M.moves_done - 1;
-    for (int d = lane; d < D; d += 64) sdel[d] = M.delta[item * D + d];
+    __shared__ int S[kMaxSubset];
+    const int m = M.m;
+    const int nd = m > 0 ? 2 * m - 1 : D;
+    for (int d = lane; d < nd; d += 64) sdel[d] = M.delta[item * D + d];
+    for (int i = lane; i < m; i += 64) S[i] = M.subset[item * kMaxSubset + i];
     __syncthreads();
-    const float lqr = log_mix(M.Or + item * M.Out, sdel, -1.0f, scale, N, K, D, lane);
-    float dE = 0.0f;  // the energy change's parts, added in order
-    for (int p = 0; p < kEnergyParts; ++p) dE += M.dEp[item * kEnergyParts + p];
+    float lqr, dE = 0.0f;
+    if (m > 0) {
+        lqr = log_mix_subset(M.Or + item * M.Out, S, sdel, -1.0f, scale, N, K, D, m, lane);
+        dE = M.dE[item];
+    } else {
+        lqr = log_mix(M.Or + item * M.Out, sdel, -1.0f, scale, N, K, D, lane);
+        for (int p = 0; p < kEnergyParts; ++p) dE += M.dEp[item * kEnergyParts + p];  // the parts, added in order
+    }
     const float beta = P.beta[M.temp_index[net]];
     const float dref = M.dref[item];
     const float la = dref == -INFINITY ? -INFINITY : -beta * dE + dref + lqr - M.lqf[item];
-    const int nb = (D + 1) / 2;
-    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
+    // the acceptance uniform: word 1 of the block after the Gaussians (counter word 3: 0 all-mode, 1 subset)
+    const int nb = m > 0 ? m : (D + 1) / 2;
+    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, m > 0 ? 1 : 0, sh.run_seed, kTagLearn);
     const double ua = uniform01<double>(wu.v[1]);
     const bool accept = log(ua) < (double)la;
     if (accept) {
@@ -875,6 +1213,18 @@ hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const Sha
     const size_t lds = (size_t)gsize * 2 * M.N * sizeof(float2);
     hipLaunchKernelGGL(k_energy_change, dim3((unsigned)(samples * groups * kEnergyParts)), dim3(256), lds, st, M, P,
                        sh, groups, gsize);
+    return hipGetLastError();
+}
+
+hipError_t mlp_propose_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_propose_subset, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
+    return hipGetLastError();
+}
+
+hipError_t mlp_energy_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_subset, dim3((unsigned)(M.Bm * M.nets)), dim3(256), (size_t)M.N * sizeof(float2), st,
+                       M, P, sh);
     return hipGetLastError();
 }
 

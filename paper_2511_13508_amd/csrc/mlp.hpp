@@ -16,10 +16,12 @@
 namespace rlpt {
 
 constexpr int kEnergyParts = 32;  // workgroups sharing one learned move's energy change
+constexpr int kMaxSubset = 64;    // largest subset of the subset move
 
 struct MlpDev {
     int32_t nets, N, In, H, K, D, Out;
     int32_t Bm;      // inference items per net (samples x replicas)
+    int32_t m;       // subset move: modes per move (0: the all-mode move)
     int32_t Bt;      // training minibatch
     int32_t cap;     // stored training pairs per net
     int64_t NP;      // parameters per net
@@ -47,6 +49,7 @@ struct MlpDev {
     float* dEp;      // [nets][Bm][kEnergyParts] partial energy changes (term ranges)
     float* la;       // [nets][Bm] log acceptance ratio
     int32_t* item_copy;  // [nets][Bm]
+    int32_t* subset;     // [nets][Bm][kMaxSubset] the subset of the last move, ascending (subset move)
     // training
     float* tX;       // [nets][Bt][In]
     float* tP1;      // [nets][Bt][H]
@@ -60,6 +63,7 @@ struct MlpDev {
     float* tdelta;   // [nets][Bt][D]
     float* tloss;    // [nets][Bt] per-pair loss (0 for pairs left out)
     int32_t* tvalid; // [nets][Bt] 1 when both configurations of the pair are inside the alr chart
+    int32_t* tsub;   // [nets][Bt][kMaxSubset] the training item's subset (subset move)
     float* data;     // [nets][cap][2][2N] pairs (before, after), interleaved complex
     int32_t* temp_index;  // [nets]
     int32_t* count;  // [nets] stored pairs
@@ -78,6 +82,10 @@ hipError_t mlp_adam(const MlpDev& M, float lr, int64_t t, hipStream_t st);
 hipError_t mlp_sync_bf16(const MlpDev& M, hipStream_t st);
 hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
 hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
+// subset move: proposal, energy change from the subset's lists, acceptance
+hipError_t mlp_propose_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale,
+                              hipStream_t st);
+hipError_t mlp_energy_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
 hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
 hipError_t mlp_harvest(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, int which, int slot0,
                        hipStream_t st);

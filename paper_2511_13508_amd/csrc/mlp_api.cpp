@@ -38,6 +38,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.D = 2 * N - 1;
     m.Out = m.K * (2 * m.D + 1);
     m.Bm = S * cfg.n_reps;
+    m.m = cfg.mlp_subset;
     m.Bt = cfg.mlp_batch;
     m.cap = cfg.mlp_capacity;
     m.oW1 = 0;
@@ -77,6 +78,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.dEp = f(n * Bm * kEnergyParts);
     m.la = f(n * Bm);
     m.item_copy = (int32_t*)f(n * Bm);
+    m.subset = (int32_t*)f(n * Bm * kMaxSubset);
     m.tX = f(n * Bt * m.In);
     m.tP1 = f(n * Bt * m.H);
     m.tH1 = f(n * Bt * m.H);
@@ -89,6 +91,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.tdelta = f(n * Bt * m.D);
     m.tloss = f(n * Bt);
     m.tvalid = (int32_t*)f(n * Bt);
+    m.tsub = (int32_t*)f(n * Bt * kMaxSubset);
     m.data = f(n * (size_t)m.cap * 2 * 2 * N);
     m.temp_index = (int32_t*)f(n);
     m.count = (int32_t*)f(n);
@@ -109,6 +112,8 @@ int mlp_check_config(const rlpt_config& cfg, const rlpt_graph* const* g, int S) 
     for (int i = 1; i < S; ++i)
         if (g[i]->N != g[0]->N) return fail(RLPT_E_ARG, "learned moves need one N for every sample");
     if (g[0]->N > kMaxModes / 2) return fail(RLPT_E_ARG, "learned moves support N <= 512");
+    if (cfg.mlp_subset != 0 && (cfg.mlp_subset < 2 || cfg.mlp_subset > kMaxSubset || cfg.mlp_subset > g[0]->N))
+        return fail(RLPT_E_ARG, "mlp_subset must be 0 or in [2, min(N, 64)]");
     return RLPT_OK;
 }
 
@@ -164,8 +169,13 @@ int mlp_enqueue_round(rlpt_ctx* c) {
     const float s = (float)c->mlp_scale;
     HIP_TRY2(mlp_features_current(M, c->pf, c->sh, c->stream), "learned features");
     HIP_TRY2(mlp_forward(M, 0, 0, c->stream), "learned forward");
-    HIP_TRY2(mlp_propose(M, c->pf, c->sh, s, c->stream), "learned propose");
-    HIP_TRY2(mlp_energy_change(M, c->pf, c->sh, c->stream), "learned energy");
+    if (M.m > 0) {
+        HIP_TRY2(mlp_propose_subset(M, c->pf, c->sh, s, c->stream), "learned propose");
+        HIP_TRY2(mlp_energy_subset(M, c->pf, c->sh, c->stream), "learned energy");
+    } else {
+        HIP_TRY2(mlp_propose(M, c->pf, c->sh, s, c->stream), "learned propose");
+        HIP_TRY2(mlp_energy_change(M, c->pf, c->sh, c->stream), "learned energy");
+    }
     HIP_TRY2(mlp_forward(M, 0, 1, c->stream), "learned forward");
     HIP_TRY2(mlp_accept(M, c->pf, c->sh, s, c->stream), "learned accept");
     if (c->sh.cached) HIP_TRY2(launch_fields_all(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, c->stream), "fields");

@@ -71,7 +71,7 @@ class Config(C.Structure):
                 ("block_threads", C.c_int32), ("copies_per_block", C.c_int32), ("list_layout", C.c_int32),
                 ("mlp_nets", C.c_int32), ("mlp_hidden", C.c_int32), ("mlp_components", C.c_int32),
                 ("mlp_capacity", C.c_int32), ("mlp_batch", C.c_int32), ("field_mode", C.c_int32),
-                ("rho", C.c_int32)]
+                ("rho", C.c_int32), ("mlp_subset", C.c_int32)]
 
 
 OBS_FIELDS = ["e_n", "e_sum", "e_sq", "y2_sum", "y4_sum", "q_n", "q_sum", "q_sq", "q_4", "hist", "acc", "tries",

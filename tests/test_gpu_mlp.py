@@ -441,3 +441,142 @@ def test_learned_move_matches_oracle_at_configured_size(oracle):
                 np.testing.assert_allclose(after[c], an[0] if accepted else state32[c], rtol=0, atol=5e-4)
                 decided += 1
     assert decided >= S * reps  # most of the 32 decisions are away from the boundary
+
+
+# ------------------------------------------------------------------ the subset move
+def subset_ctx(N, S, T, reps, H, K, batch, m, nets=2, cap=64, graphs=None, temps=None, seed0=500):
+    graphs = graphs or [rlpt.Graph(N, SEED3 + seed0 + i) for i in range(S)]
+    temps = synth.geometric_temps(0.5, 1.5, T) if temps is None else temps
+    return make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=nets, mlp_hidden=H,
+                    mlp_components=K, mlp_capacity=cap, mlp_batch=batch, mlp_subset=m, resync_interval=0,
+                    drift_tol=0.0), graphs
+
+
+@pytest.mark.parametrize("N,S,T,reps,H,K,m,layout", [(16, 2, 3, 2, 32, 2, 4, rlpt.LAYOUT_CHUNKED),
+                                                      (16, 2, 3, 2, 32, 2, 16, rlpt.LAYOUT_PACKED),
+                                                      (64, 8, 4, 2, 256, 4, 8, rlpt.LAYOUT_AUTO)])
+def test_subset_move_matches_oracle(oracle, N, S, T, reps, H, K, m, layout):
+    """One subset round against the oracle on the same draws: the subset, the
+    proposal (modes outside the subset untouched), the energy change summed
+    from the subset's lists against the exact FP64 difference, the log
+    acceptance ratio and the decisions away from the boundary."""
+    temps = synth.geometric_temps(0.6, 1.2, T)
+    graphs = [rlpt.Graph(N, SEED3 + 600 + i) for i in range(S)]
+    ctx = make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=2, mlp_hidden=H,
+                   mlp_components=K, mlp_capacity=64, mlp_batch=16, mlp_subset=m, resync_interval=0, drift_tol=0.0,
+                   list_layout=layout)
+    ctx.init(7)
+    ctx.mlp_setup([1, 2], seed=3)
+    NP, Out = ctx.mlp_sizes()
+    raw = [synth.random_mlp_params(2 * N, H, Out, seed=160 + n, out_scale=0.3) for n in range(2)]
+    for n in range(2):
+        ctx.mlp_set_params(n, raw[n])
+    state = synth.random_constrained_state(N, 170, S * T * reps)
+    ctx.set_state(state)
+    s32 = state.astype(np.complex64).astype(np.complex128)
+    scale = 0.5
+    ctx.mlp_move(scale)
+    after = ctx.get_state().reshape(S * T * reps, N)
+    ogs = [oracle.Graph(N, SEED3 + 600 + i) for i in range(S)]
+    decided = 0
+    for n, t in enumerate([1, 2]):
+        params = M.rounded(unflatten(raw[n], N, H, K))
+        la, copies, prop = ctx.mlp_last_move(n)
+        for b in range(S * reps):
+            mu, r = divmod(b, reps)
+            c = mu * T * reps + r * T + t
+            assert copies[b] == c
+            Ss, g, uc, ua = M.subset_draws(7, 0, c, N, m)
+            E0 = oracle.energy(ogs[mu], s32[c])
+            dH = lambda an: oracle.energy(ogs[mu], an) - E0  # noqa
+            an, la_ref, parts = M.subset_move_log_alpha(params, s32[c], Ss, dH, 1.0 / temps[t], N, K, scale, g, uc)
+            rest = np.setdiff1d(np.arange(N), Ss)
+            assert np.array_equal(prop[b][rest], s32[c][rest]), (n, b)
+            np.testing.assert_allclose(prop[b], an, rtol=0, atol=5e-4)
+            mag = abs(parts["lq_f"]) + abs(parts["lq_r"]) + abs(parts["dlogref"]) + abs(parts["dH"]) / temps[t]
+            assert la[b] == pytest.approx(la_ref, abs=3e-3 + 2e-5 * mag), (n, b)
+            if abs(math.log(ua) - la_ref) > 2e-2 + 4e-5 * mag:
+                accepted = math.log(ua) < la_ref
+                np.testing.assert_allclose(after[c], an if accepted else s32[c], rtol=0, atol=5e-4)
+                decided += 1
+    assert decided >= S * reps
+    acc, tries = ctx.mlp_stats()
+    assert np.all(tries == S * reps)
+
+
+@pytest.mark.parametrize("N,H,K,B,m", [(16, 48, 3, 16, 5), (64, 256, 4, 512, 8)])
+def test_subset_gradients_match_oracle(N, H, K, B, m):
+    """Training loss and gradients of the subset move (each minibatch item in
+    the chart of its own subset, drawn from the training stream) against the
+    FP64 oracle on the same bfloat16 operands."""
+    ctx, _ = subset_ctx(N, 1, 2, 1, H, K, B, m, nets=1, cap=B)
+    ctx.init(1)
+    ctx.mlp_setup([0], seed=9)
+    NP, Out = ctx.mlp_sizes()
+    raw = synth.random_mlp_params(2 * N, H, Out, seed=180 + N, out_scale=0.5)
+    ctx.mlp_set_params(0, raw)
+    before = synth.random_constrained_state(N, 181 + N, B)
+    after = synth.random_constrained_state(N, 182 + N, B)
+    b, a = _store_pairs(ctx, 0, before, after)
+    subsets = [M.train_subset(9, 0, 0, i, N, m) for i in range(B)]
+    params = M.rounded(unflatten(raw, N, H, K))
+    L_ref, g_ref = M.subset_loss_and_grads(params, b, a, subsets, N, K)
+    L, g = ctx.mlp_loss_grad(0)
+    assert L == pytest.approx(L_ref, rel=1e-4)
+    gg = unflatten(g, N, H, K)
+    for k in g_ref:
+        x, y = gg[k].ravel(), g_ref[k].ravel()
+        assert np.linalg.norm(x - y) <= 1e-2 * np.linalg.norm(y), k
+        assert np.dot(x, y) / (np.linalg.norm(x) * np.linalg.norm(y)) >= 0.999, k
+
+
+def test_subset_moves_keep_infinite_temperature_law():
+    """Exact draws at beta ~ 0, then subset rounds only: the closed-form
+    marginals of the reference law stay put."""
+    N, reps = 6, 512
+    ctx, _ = subset_ctx(N, 1, 1, reps, 16, 2, 8, 3, nets=1, temps=[1e7])
+    ctx.init(9)
+    ctx.mlp_setup([0], seed=4)
+    for _ in range(40):
+        ctx.mlp_move(0.8)
+    acc, tries = ctx.mlp_stats()
+    assert 0.1 < acc[0] / tries[0] < 0.98
+    a = ctx.get_state().reshape(reps, N)
+    ref = brute.beta0_moments(N)
+    u = np.abs(a) ** 2
+    assert np.mean(u) == pytest.approx(ref["E|a|^2"], abs=5 * u.std() / math.sqrt(u.size))
+    assert np.mean(u ** 4) == pytest.approx(ref["E|a|^8"], abs=5 * (u ** 4).std() / math.sqrt(u.size))
+    np.testing.assert_allclose(np.sum(np.abs(a) ** 4, axis=1), N, rtol=2e-5)
+
+
+def test_subset_learned_pt_is_unbiased(oracle):
+    """Harvest, train and run PT with a subset round after every sweep: the
+    per-temperature laws agree with the plain FP64 oracle (the t-law rule)."""
+    from tests.test_gpu_parity import check_same_law, same_law_report
+    N, S, T, reps = 16, 8, 6, 2
+    temps = synth.geometric_temps(0.5, 1.5, T)
+    graphs = [rlpt.Graph(N, SEED3 + 650 + i) for i in range(S)]
+    ctx = make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=2, mlp_hidden=64,
+                   mlp_components=2, mlp_capacity=4096, mlp_batch=128, mlp_subset=4, swap_interval=1,
+                   resync_interval=100, measure_start=1000, measure_interval=1, n_bins=20)
+    ctx.init(7)
+    ctx.sweep(300)
+    ctx.mlp_setup([1, 3], seed=2)
+    ctx.mlp_harvest(rounds=200, lag=2)
+    L0 = ctx.mlp_train(1, 1e-3)
+    L1 = ctx.mlp_train(300, 1e-3)
+    assert np.all(L1 < L0)
+    ctx.mlp_enable(1, 0.5)
+    ctx.sweep(4000 - ctx.counters()[0])
+    ctx.check()
+    acc, tries = ctx.mlp_stats()
+    assert np.all(acc > 0)
+    g = per_sample_obs(ctx.observables(), temps)
+    ors = []
+    for mu in range(S):
+        pt = oracle.PT(oracle.Graph(N, SEED3 + 650 + mu), temps, n_reps=reps, run_seed=98, sample=mu,
+                       swap_interval=1, resync_interval=100, measure_start=1000, measure_interval=1, n_bins=20)
+        pt.run(4000)
+        ors.append(pt)
+    o = per_sample_obs(oracle_stack(ors), temps)
+    check_same_law(same_law_report(g, o, keys=("E", "C_V", "q2", "Y2")))
