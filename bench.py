@@ -39,6 +39,7 @@ SEED_BASE = 2511135080 + 400  # disorder seed of sample mu: SEED_BASE + mu
 HBM_PEAK_GBS = 8000.0
 METRIC = "mode-updates/s + τ_int-corrected sweeps/s (learned vs plain PT), N=256, 1 GPU"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_n256_traffic.json")
+BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_traffic.json")
 # the sweep kernel and the host code that lays out its launch (tiles, item order)
 KERNEL_SRC = [os.path.join(ROOT, "paper_2511_13508_amd", "csrc", f) for f in ("kernels.hip", "api.cpp")]
 
@@ -55,11 +56,11 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for_current_kernel(launch_bytes_alg: float):
+def traffic_for_current_kernel(launch_bytes_alg: float, path: str = TRAFFIC_FILE):
     """HBM bytes per sweep launch from committed rocprofv3 counters, if they
     were taken on the current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -87,6 +88,8 @@ PROFILE_CMDS = {
     "pmc": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<|k_stream_lists' -f csv -d {OUT}/pmc_{C} -o pmc -- "
            "python bench.py --sweeps-per-step 1 --steps 4 --warmup 2 --tau-sweeps 0 --no-cpu-baseline --no-cached",
     "cal": "rocprofv3 --pmc {C} -f csv -d {OUT}/cal_{C} -o cal -- python bench.py --copy-calibration",
+    "pmcb": "rocprofv3 --pmc {C} --kernel-include-regex 'k_sweep<' -f csv -d {OUT}/pmcb_{C} -o pmc -- python bench.py "
+            "--workload batched --batched-launches-only",
 }
 
 
@@ -157,6 +160,22 @@ def summarize_profiles(d):
         os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
         with open(os.path.join(ROOT, "profiles", "sweep_n256_kernel_stats.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
+    if all(os.path.exists(os.path.join(d, x)) for x in ("pmcb_FETCH_SIZE", "pmcb_WRITE_SIZE", "cal_FETCH_SIZE",
+                                                        "cal_WRITE_SIZE")):
+        cal_f, _ = mean_counter(os.path.join(d, "cal_FETCH_SIZE", "cal_counter_collection.csv"), is_copy)
+        cal_w, _ = mean_counter(os.path.join(d, "cal_WRITE_SIZE", "cal_counter_collection.csv"), is_copy)
+        copy_bytes = 512 * 1024 * 1024
+        f_scale, w_scale = copy_bytes / (cal_f * 1024), copy_bytes / (cal_w * 1024)
+        fetch_kib, nf = mean_counter(os.path.join(d, "pmcb_FETCH_SIZE", "pmc_counter_collection.csv"), is_sweep)
+        write_kib, nw = mean_counter(os.path.join(d, "pmcb_WRITE_SIZE", "pmc_counter_collection.csv"), is_sweep)
+        tb = {"kernel": "k_sweep, batched uneven-N launch (built-in tiles)", "kernel_source_sha": kernel_sha(),
+              "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib, "dispatches": [nf, nw],
+              "fetch_scale": f_scale, "write_scale": w_scale,
+              "hbm_bytes_per_launch": fetch_kib * 1024 * f_scale + write_kib * 1024 * w_scale,
+              "commands": [cmd("pmcb", "FETCH_SIZE"), cmd("pmcb", "WRITE_SIZE"), cmd("cal", "FETCH_SIZE"),
+                           cmd("cal", "WRITE_SIZE")]}
+        with open(BATCHED_TRAFFIC_FILE, "w") as f:
+            json.dump(tb, f, indent=1)
     sq = os.path.join(d, "sq256", "pmc_counter_collection.csv")
     if os.path.exists(sq):
         rs = rows(sq)
@@ -288,6 +307,17 @@ def batched(args, short=False):
     infos = [g.info() for g in graphs]
     bytes_per_sweep = sum(reps * T * inf["deg_sum"] * 6.25 for inf in infos)
 
+    if getattr(args, "batched_launches_only", False):
+        # only the mixed launch with built-in tiles, 20 eager sweeps (the counters' run)
+        rlpt.tune_clear()
+        ctx = rlpt.Context(graphs, temps, **kw)
+        ctx.init(1)
+        ctx.sweep(20)
+        torch.cuda.synchronize()
+        ctx.check()
+        ctx.close()
+        return {"batched_launches_only": 20}
+
     def rate(gs, ctx_kw, segments):
         """mode-updates/s of 10-sweep HIP-graph segments, then the sweep kernel's
         mean launch time from HIP events over 20 eager sweeps"""
@@ -337,19 +367,27 @@ def batched(args, short=False):
         N = e["n_modes"]
         if e["block_threads"] == b1 and e["copies_per_block"] == t1_[N]:
             per_N[N] = {"copies_per_block": t1_[N], "launch_ms_per_sweep": e["ms_per_sweep"]}
+    # roofline of the built-in tiles' launch (the configuration whose fabric bytes are committed)
+    traffic_b = traffic_for_current_kernel(bytes_per_sweep, BATCHED_TRAFFIC_FILE)
+    roof_b = {"bound": "hbm", "kernel": "k_sweep (one launch for every N, built-in tiles)", "unit": "GB/s",
+              "algorithmic_bytes_per_launch": bytes_per_sweep, "ms_per_launch": ms0,
+              "achieved": bytes_per_sweep / ms0 / 1e6, "hbm_peak_published": HBM_PEAK_GBS,
+              "frac_of_hbm_peak": bytes_per_sweep / ms0 / 1e6 / HBM_PEAK_GBS, "traffic": traffic_b,
+              "ms_per_launch_tuned_tiles": ms1,
+              "list_stream_probe_ms": ceil1, "sweep_over_probe_time_tuned": ms1 / ceil1}
+    if traffic_b:
+        roof_b.update({"peak": HBM_PEAK_GBS * bytes_per_sweep / traffic_b,
+                       "frac": traffic_b / ms0 / 1e6 / HBM_PEAK_GBS, "traffic_GBps": traffic_b / ms0 / 1e6,
+                       "peak_kind": "published HBM peak x algorithmic / fabric bytes (profiles/batched_traffic.json)"})
+    else:
+        roof_b.update({"peak": bytes_per_sweep / ceil1 / 1e6, "frac": ceil1 / ms1,
+                       "peak_kind": "measured list-stream probe of the tuned launch (no committed counters)"})
     out = {"metric": "aggregate mode-updates/s, batched uneven N (one launch per sweep, HIP graph)",
            "value": v1, "unit": "mode-updates/s", "untuned_value": v0, "tuned_vs_untuned": v1 / v0,
            "copies": copies, "sweeps": segs * 10, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched uneven N: N in {32,48,64,96,128} x 32 samples x 32 temperatures x "
                                   "2 replicas, FP32, 10-sweep HIP-graph segments"},
-           "roofline": {"bound": "hbm", "kernel": "k_sweep (one launch for every N)", "unit": "GB/s",
-                        "algorithmic_bytes_per_launch": bytes_per_sweep, "ms_per_launch": ms1,
-                        "achieved": bytes_per_sweep / ms1 / 1e6, "peak": bytes_per_sweep / ceil1 / 1e6,
-                        "frac": ceil1 / ms1, "ceiling_ms_per_launch": ceil1,
-                        "peak_kind": "measured list-stream ceiling of the same launch (rlpt_stream_lists)",
-                        "hbm_peak_published": HBM_PEAK_GBS,
-                        "frac_of_hbm_peak": bytes_per_sweep / ms1 / 1e6 / HBM_PEAK_GBS,
-                        "ms_per_launch_builtin_tiles": ms0},
+           "roofline": roof_b,
            "per_N_alone": alone,
            "tile_builtin": {"block": b0, "copies_per_block": t0_}, "tile_tuned": {"block": b1, "copies_per_block": t1_},
            "autotune": {"trials": n_trials, "seconds": t_tune,
@@ -660,11 +698,12 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
     graphs = [rlpt.Graph(N, 2511135080 + 300 + mu) for mu in range(S)]
     start = warm + harvest_rounds * 2 + reeq
 
-    def run(learn_t, learned):
+    def run(learn_t, learned, subset=0, scale=None):
+        scale = args.learn_scale if scale is None else scale
         cfg = dict(n_temps=T, n_reps=reps, precision=rlpt.FP32, swap_interval=1, resync_interval=100,
                    measure_start=start, measure_interval=1, n_bins=100, series_len=sweeps,
                    mlp_nets=len(learn_t), mlp_hidden=256, mlp_components=4,
-                   mlp_capacity=harvest_rounds * S * reps, mlp_batch=512)
+                   mlp_capacity=harvest_rounds * S * reps, mlp_batch=512, mlp_subset=subset)
         ctx = rlpt.Context(graphs, temps, **cfg)
         ctx.init(1)
         ctx.sweep(warm)
@@ -683,7 +722,7 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
                 info = {"train_error": str(e)}
                 log(f"learned N=64: training failed: {e}")
         if learned and "train_error" not in info:
-            ctx.mlp_enable(1, args.learn_scale)
+            ctx.mlp_enable(1, scale)
         ctx.sweep(start - ctx.counters()[0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -732,6 +771,9 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
     op, sps_p, _ = run(t_learn, False)
     log("learned N=64: learned run")
     ol, sps_l, info = run(t_learn, True)
+    m_sub = max(2, N // args.subset_frac)
+    log(f"learned N=64: learned subset run (m = {m_sub})")
+    os_, sps_s, info_s = run(t_learn, True, subset=m_sub, scale=args.subset_scale)
     tEp, tqp = taus(op, t_learn)
     tEl, tql = taus(ol, t_learn)
     # the two runs share disorder, seed and history up to the first learned round: paired differences over samples
@@ -745,6 +787,17 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
     zq = np.abs(dh) / np.maximum(sh_, 1e-12)
     rE = eff_ratio(tEl, tEp, sps_l, sps_p)
     rq = eff_ratio(tql, tqp, sps_l, sps_p)
+    tEs, tqs = taus(os_, t_learn)
+    rEs = eff_ratio(tEs, tEp, sps_s, sps_p)
+    dead_s = dead_networks(info_s.get("move_acceptance", []), np.array(info_s["train_loss_first_last"])
+                           if "train_loss_first_last" in info_s else None)
+    for d in dead_s:
+        rEs["status"][d["network"]] = "failed: " + d["failed"]
+    if "train_error" in info_s:
+        rEs["status"] = ["failed: " + info_s["train_error"]] * len(t_learn)
+    Es = os_["e_sum"] / os_["e_n"]
+    dEs, sEs = jk(Es - Ep)
+    zEs = np.abs(dEs) / np.maximum(sEs, 1e-12)
     dead = dead_networks(info.get("move_acceptance", []), np.array(info["train_loss_first_last"])
                          if "train_loss_first_last" in info else None)
     for d in dead:
@@ -763,11 +816,17 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
                     "failed_networks": dead},
         "learned_vs_plain_eff_E": rE,
         "learned_vs_plain_eff_q": rq,
+        "learned_subset": {"move": f"subset of {m_sub} modes", "step_scale": args.subset_scale,
+                           "sweeps_per_s": sps_s, "tau_int_E": tau_stats(tEs), "tau_int_q": tau_stats(tqs), **info_s,
+                           "failed_networks": dead_s, "E_within_2sigma": float(np.mean(zEs <= 2)),
+                           "E_z_all_T": zEs.round(2).tolist()},
+        "learned_subset_vs_plain_eff_E": rEs,
         "agreement": {"E_diff_learned_minus_plain": dE.round(3).tolist(), "E_diff_err": sE.round(3).tolist(),
                       "E_z_all_T": zE.round(2).tolist(), "E_within_2sigma": float(np.mean(zE <= 2)),
                       "Pq_cells": int(mass.sum()), "Pq_within_2sigma": float(np.mean(zq[mass] <= 2)),
                       "test": "paired jackknife over the 8 samples of (learned - plain)"},
     }
+    log(f"learned N=64: subset eff ratio E {rEs['ratio']} {rEs['status']}")
     log(f"learned N=64: eff ratio E {rE['ratio']} {rE['status']}, "
         f"E within 2 sigma {out['learned_n64']['agreement']['E_within_2sigma']:.2f}, "
         f"P(q) within 2 sigma {out['learned_n64']['agreement']['Pq_within_2sigma']:.2f}")
@@ -854,6 +913,11 @@ def main():
     ap.add_argument("--learn-temps", type=lambda v: [int(x) for x in v.split(",")] if v else [],
                     default=[25, 26, 27, 28], help="temperature indices with learned global moves")
     ap.add_argument("--learn-scale", type=float, default=0.05)
+    ap.add_argument("--subset-frac", type=int, default=8, help="subset move: m = N / subset_frac modes per move")
+    ap.add_argument("--subset-scale", type=float, default=0.5, help="subset move: step scale")
+    ap.add_argument("--subset-rounds", type=int, default=1, help="subset move: learned rounds per sweep at N=256")
+    ap.add_argument("--only-learned-256", action="store_true",
+                    help="n256 workload: only the plain tau run and the learned comparisons (scans)")
     ap.add_argument("--harvest-rounds", type=int, default=400)
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--reeq", type=int, default=500, help="sweeps with swaps between harvest and the learned window")
@@ -871,9 +935,13 @@ def main():
                     help="learned64 workload: networks around the C_V peak or on the four coldest temperatures")
     ap.add_argument("--n64-untrained", action="store_true",
                     help="learned64 workload: learned rounds with untrained networks")
+    ap.add_argument("--batched-launches-only", action="store_true",
+                    help="batched workload: only 20 sweeps of the mixed launch with built-in tiles (for counters)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
+    if args.only_learned_256:
+        args.no_cached = args.no_n64 = args.no_batched = args.no_cpu_baseline = True
     args.sweeps = args.steps * args.sweeps_per_step
     args.warm_sweeps = args.warmup * args.sweeps_per_step
     if args.summarize_profiles:
@@ -992,8 +1060,18 @@ def main():
             "hbm_peak_published": HBM_PEAK_GBS, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_over_algorithmic": traffic / bytes_per_launch if traffic else None,
             "traffic_GBps": traffic / t_launch / 1e9 if traffic else None}
+    if traffic:
+        # the HBM roof for the bytes that pass the L2: the published peak scaled by the measured reuse
+        # (algorithmic / fabric bytes); frac = fabric GB/s / HBM peak.  Fabric bytes include Infinity-Cache
+        # hits, so the true HBM fraction is at most this
+        roof.update({"peak": HBM_PEAK_GBS * bytes_per_launch / traffic,
+                     "frac": traffic / t_launch / 1e9 / HBM_PEAK_GBS,
+                     "peak_kind": "published HBM peak x algorithmic / fabric bytes (rocprofv3 FETCH_SIZE + "
+                                  "WRITE_SIZE of this kernel source, profiles/sweep_n256_traffic.json): the HBM roof "
+                                  "for the bytes that pass the L2; fabric bytes include Infinity-Cache hits, so the "
+                                  "HBM fraction is at most frac"})
     if chunked and not args.shared_pairs:
-        # the ceiling in three rounds, each beside a few timed sweep launches (same box, same clocks)
+        # the list-stream probe in three rounds, each beside a few timed sweep launches (same box, same clocks)
         probe, beside = [], []
         for _ in range(3):
             probe.append(ctx.stream_lists(5))
@@ -1002,18 +1080,18 @@ def main():
             kr, nr = ctx.sweep_time()
             ctx.sweep_timing(False)
             beside.append(kr / nr)
-        ms_ceiling = float(np.mean(probe))
-        ceiling = bytes_per_launch / (ms_ceiling * 1e-3) / 1e9
-        roof.update({"peak": ceiling, "frac": achieved / ceiling, "ceiling_ms_per_launch": ms_ceiling,
-                     "ceiling_rounds_ms": [round(x, 4) for x in probe],
-                     "sweep_beside_ceiling_ms": [round(x, 4) for x in beside],
-                     "frac_beside": ms_ceiling / float(np.mean(beside)),
-                     "peak_kind": "measured: the memory hierarchy (L2, Infinity Cache, HBM) streaming exactly the "
-                                  "lists of one sweep launch in the sweep's grid, tile and order with no arithmetic "
-                                  "(rlpt_stream_lists); the algorithmic rate exceeds the published HBM peak because "
-                                  "the lists (270 MB) are re-read from L2 and the Infinity Cache"})
-        log(f"list-stream ceiling {ms_ceiling:.3f} ms/launch = {ceiling:.0f} GB/s; sweep at {achieved / ceiling:.3f}")
-    else:
+        ms_probe = float(np.mean(probe))
+        roof["list_stream_probe"] = {
+            "ms_per_launch": ms_probe, "GBps": bytes_per_launch / (ms_probe * 1e-3) / 1e9,
+            "rounds_ms": [round(x, 4) for x in probe], "sweep_beside_ms": [round(x, 4) for x in beside],
+            "sweep_over_probe_time": float(np.mean(beside)) / ms_probe,
+            "what": "rlpt_stream_lists: the sweep's grid, tile, LDS footprint, barriers and list reads with no "
+                    "arithmetic; the sweep takes within a few per cent of its time (box to box 0.96-1.04)"}
+        log(f"list-stream probe {ms_probe:.3f} ms/launch; sweep beside it {np.mean(beside):.3f} ms")
+        if "peak" not in roof:
+            roof.update({"peak": bytes_per_launch / (ms_probe * 1e-3) / 1e9, "frac": ms_probe / t_launch,
+                         "peak_kind": "measured list-stream probe (no committed counters for this kernel source)"})
+    if "peak" not in roof:
         roof.update({"peak": HBM_PEAK_GBS, "frac": achieved / HBM_PEAK_GBS, "peak_kind": "published HBM peak"})
     sweeps_per_s = args.sweeps / el
     t_learn = [t for t in args.learn_temps if t < T]
@@ -1057,6 +1135,7 @@ def main():
             n64_protocol(args, rlpt, torch, out, out["n64_physics"]["cv_per_mode"])
     if not args.no_batched and not args.no_cached:
         out["batched"] = batched(args, short=True)
+        rlpt.tune_clear()  # the autotuner's registry would otherwise choose the later contexts' tiles
     if args.tau_sweeps > 0 and args.learn_temps and not args.no_n64:
         learned_n64(args, rlpt, torch, out)
     if args.tau_sweeps > 0:
@@ -1064,7 +1143,7 @@ def main():
                              "replicas, same window", "estimator": "Sokal window c=6, per disorder sample",
                "plain": tau_plain}
         # ------------------------------------------------------------ shared pair schedule
-        if not args.shared_pairs:
+        if not args.shared_pairs and not args.only_learned_256:
             ctx = rlpt.Context(graphs, temps, shared_pairs=1, **common)
             el2, _, _ = timed(ctx, "shared pairs")
             tau["shared_pairs"], tE2, _ = tau_block(ctx, args.sweeps / el2, t_learn, args.tau_sweeps, "shared pairs")
@@ -1072,14 +1151,15 @@ def main():
             tau["shared_vs_plain_eff"] = eff_ratio(tE2, tau_plain_E, args.sweeps / el2, sweeps_per_s)
             ctx.close()
         # ------------------------------------------------------------ learned global moves
-        if t_learn:
+        def learned_256(subset, scale, tag, rounds=1):
             lcommon = dict(common, series_len=series_len + 2 * args.harvest_rounds + args.reeq)
             ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, mlp_nets=len(t_learn),
-                               mlp_hidden=256, mlp_components=4, mlp_capacity=8192, mlp_batch=512, **lcommon)
+                               mlp_hidden=256, mlp_components=4, mlp_capacity=8192, mlp_batch=512,
+                               mlp_subset=subset, **lcommon)
             ctx.init(1)
             ctx.sweep(args.warm_sweeps)
             ctx.mlp_setup(t_learn, seed=1)
-            log("learned: harvest and train")
+            log(f"{tag}: harvest and train")
             t0 = time.perf_counter()
             ctx.mlp_harvest(rounds=args.harvest_rounds, lag=2)
             losses, train_error = [], None
@@ -1088,10 +1168,10 @@ def main():
                 losses.append(ctx.mlp_train(args.train_steps, 1e-3))
             except rlpt.RlptError as e:
                 train_error = str(e)
-                log(f"learned: training failed: {e}")
+                log(f"{tag}: training failed: {e}")
             t_train = time.perf_counter() - t0
             if train_error is None:
-                ctx.mlp_enable(1, args.learn_scale)
+                ctx.mlp_enable(rounds, scale)
             # the harvest ran without swaps: re-equilibrate with swaps and learned rounds before the window
             ctx.sweep(args.reeq)
             done = ctx.counters()[0]
@@ -1100,10 +1180,10 @@ def main():
             ctx.sweep(args.sweeps)
             torch.cuda.synchronize()
             el3 = time.perf_counter() - t0
-            log(f"learned: {args.sweeps / el3:.1f} sweeps/s; tau_int run")
+            log(f"{tag}: {args.sweeps / el3:.1f} sweeps/s; tau_int run")
             # measurements started at the warm-up boundary: the series covers harvest + learned sweeps;
             # tau is taken over the learned part only
-            long_run(ctx, args.tau_sweeps, "learned")
+            long_run(ctx, args.tau_sweeps, tag)
             o = ctx.observables()
             m = min(int(o["e_n"][0, 0] / reps), series_len + 2 * args.harvest_rounds + args.reeq)
             lo = max(done - args.warm_sweeps, 0) + (m - max(done - args.warm_sweeps, 0)) // 4
@@ -1115,12 +1195,12 @@ def main():
             dead = dead_networks(acc_rate, np.array(losses) if losses else None)
             if train_error:
                 dead.append({"network": "all", "failed": train_error})
-            tau["learned"] = {"temperatures": [float(temps[t]) for t in t_learn], "tau_int_E": tau_stats(tEl),
-                              "tau_int_q": tau_stats(tql), "sweeps_per_s": sps3,
-                              "series_points": m - lo, "move_acceptance": acc_rate.round(4).tolist(),
-                              "step_scale": args.learn_scale,
-                              "train_loss_first_last": [np.round(x, 2).tolist() for x in losses],
-                              "harvest_and_train_s": t_train, "failed_networks": dead}
+            res = {"move": f"subset of {subset} modes" if subset else "all modes", "temperatures":
+                   [float(temps[t]) for t in t_learn], "tau_int_E": tau_stats(tEl), "tau_int_q": tau_stats(tql),
+                   "sweeps_per_s": sps3, "series_points": m - lo, "move_acceptance": acc_rate.round(4).tolist(),
+                   "step_scale": scale, "rounds_per_sweep": rounds,
+                   "train_loss_first_last": [np.round(x, 2).tolist() for x in losses],
+                   "harvest_and_train_s": t_train, "failed_networks": dead}
             ctx.close()
             ratio = eff_ratio(tEl, tau_plain_E, sps3, sweeps_per_s)
             for d in dead:
@@ -1128,7 +1208,16 @@ def main():
                     ratio["status"][d["network"]] = "failed: " + d["failed"]
                 else:
                     ratio["status"] = ["failed: " + d["failed"]] * len(ratio["status"])
-            tau["learned_vs_plain_eff"] = ratio
+            log(f"{tag}: eff ratio {ratio['ratio']} {ratio['status']}")
+            return res, ratio
+
+        if t_learn and not args.only_learned_256:
+            tau["learned"], tau["learned_vs_plain_eff"] = learned_256(0, args.learn_scale, "learned")
+        if t_learn:
+            m_sub = max(2, N // args.subset_frac)
+            tau["learned_subset"], tau["learned_subset_vs_plain_eff"] = learned_256(m_sub, args.subset_scale,
+                                                                                   "learned subset",
+                                                                                   args.subset_rounds)
         out["tau_int_corrected"] = tau
     if not args.no_cpu_baseline:
         try:

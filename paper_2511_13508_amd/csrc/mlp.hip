@@ -342,11 +342,13 @@ __device__ inline bool off_chart(const float* a, int N, int lane) {
 // Called by every lane of a single-wave workgroup.
 template <typename Word>
 __device__ inline void draw_subset(int N, int m, Word word, int* perm, int* S, int lane) {
+    __shared__ int jt[kMaxSubset];
     for (int k = lane; k < N; k += 64) perm[k] = k;
+    for (int t = lane; t < m; t += 64) jt[t] = t + index_below(word(t), N - t);  // the words, in parallel
     __syncthreads();
     if (lane == 0)
         for (int t = 0; t < m; ++t) {
-            const int j = t + index_below(word(t), N - t);
+            const int j = jt[t];
             const int x = perm[t];
             perm[t] = perm[j];
             perm[j] = x;
@@ -992,10 +994,12 @@ __device__ inline void list_field(const DevPtrs<float>& P, const SampleDev& sd, 
 
 // subset move, stage two: the energy change, mode by mode on a snapshot that
 // already holds the proposal for the modes before: dE = sum_i -2 Re(conj(a'_i - a_i) F_i)
-// (exact: every term holds a mode at most once).  One 256-thread workgroup per item.
-__global__ __launch_bounds__(256) void k_energy_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
+// (exact: every term holds a mode at most once).  One workgroup of up to 1024
+// threads per item: the items are few, and each list is streamed by the whole
+// workgroup before the next can start.
+__global__ __launch_bounds__(1024) void k_energy_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
     extern __shared__ float2 sa[];  // [N] the snapshot
-    __shared__ float red[4][2];
+    __shared__ float red[16][2];
     const int64_t item = blockIdx.x;
     const int N = M.N, m = M.m;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1023,8 +1027,11 @@ __global__ __launch_bounds__(256) void k_energy_subset(MlpDev M, DevPtrs<float> 
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const float Fr = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-            const float Fi = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+            float Fr = 0.0f, Fi = 0.0f;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                Fr += red[w][0];
+                Fi += red[w][1];
+            }
             const float2 o = sa[l];
             const float nr = ap[2 * l], ni = ap[2 * l + 1];
             dE += -2.0f * ((nr - o.x) * Fr + (ni - o.y) * Fi);
@@ -1223,7 +1230,9 @@ hipError_t mlp_propose_subset(const MlpDev& M, const DevPtrs<float>& P, const Sh
 }
 
 hipError_t mlp_energy_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_subset, dim3((unsigned)(M.Bm * M.nets)), dim3(256), (size_t)M.N * sizeof(float2), st,
+    // threads per item grow with the list length (N = 256: 1024 threads, ~5 chunks each per list)
+    const int block = M.N >= 192 ? 1024 : (M.N >= 96 ? 512 : 256);
+    hipLaunchKernelGGL(k_energy_subset, dim3((unsigned)(M.Bm * M.nets)), dim3(block), (size_t)M.N * sizeof(float2), st,
                        M, P, sh);
     return hipGetLastError();
 }
