@@ -38,6 +38,11 @@ __device__ inline float wmax(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
 }
+// word i (0..3) of a Philox block, chosen without indexing (an indexed pick
+// of a register array would go through scratch memory)
+__device__ inline uint64_t word_of(const Philox4& w, int i) {
+    return i == 0 ? w.v[0] : (i == 1 ? w.v[1] : (i == 2 ? w.v[2] : w.v[3]));
+}
 __device__ inline float wrapf(float x) { return x - 2.0f * kPiF * ceilf((x - kPiF) / (2.0f * kPiF)); }
 
 // ------------------------------------------------------------------ GEMM
@@ -181,129 +186,194 @@ hipError_t gemm(const Gemm<TB>& g, int nets, hipStream_t st) {
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ fused inference forward
-// MFMA fragment order of a weight matrix W [K][n] (K % 16 == 0, columns padded
-// to a multiple of 16): the B operand of v_mfma_f32_16x16x16_bf16 for column
-// block nb and K step ks is W[16 ks + 4 (l / 16) + i][16 nb + l % 16] in lane l,
-// slot i; those 64 x 4 elements are stored consecutively (lane-major), so one
-// wave reads a fragment as 512 contiguous bytes
-__host__ __device__ inline int64_t frag_at(int64_t base, int K, int k, int n) {
-    return base + (((int64_t)(n / 16) * (K / 16) + k / 16) * 64 + (n % 16) + 16 * ((k % 16) / 4)) * 4 + (k % 4);
-}
-__host__ __device__ inline int64_t frag_w2(const MlpDev& M) { return (int64_t)M.In * M.H; }
-__host__ __device__ inline int64_t frag_w3(const MlpDev& M) { return (int64_t)M.In * M.H + (int64_t)M.H * M.H; }
-// Inference batches of at most 16 rows in one launch instead of three GEMMs.
-// Workgroup (tile, net) computes both hidden layers of its net (every tile of
-// a net repeats them; activations stay in LDS as bfloat16) and then output
-// columns [256 tile, 256 tile + 256).  Each wave owns 64 columns of a layer
-// (four 16 x 16 blocks) and loads its weight fragments straight from the
-// fragment-order copy, eight K steps at a time, so no workgroup barrier falls
-// inside a layer.  Every block sums its MFMAs over K in the order k_gemm does,
-// with the same bfloat16 operands, bias and SiLU: the outputs are the same
-// bits as the three-GEMM path.
-constexpr int kFwdRows = 16;
-constexpr int kFwdMaxTiles = 8;   // output tiles (256 columns each) up to which the fused path is used
-constexpr int kFwdSteps = 8;      // K steps of 16 whose fragments are loaded together (K % 128 == 0)
-
-__host__ __device__ inline size_t forward_small_lds(int H) { return (size_t)2 * kFwdRows * (H + 4) * sizeof(uint16_t); }
-
-__global__ __launch_bounds__(256) void k_forward_small(MlpDev M, const float* X, float* O) {
-    extern __shared__ __align__(16) uint16_t fsm[];
-    const int H = M.H, In = M.In, Out = M.Out, B = M.Bm;
-    const int net = blockIdx.y;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int rr = lane & 15, q4 = 4 * (lane >> 4);
-    const int hs = H + 4;  // LDS row stride of an activation tile (8-byte aligned rows)
-    uint16_t* h1 = fsm;
-    uint16_t* h2 = fsm + kFwdRows * hs;
-    const float* Xn = X + (int64_t)net * B * In;
-    const uint16_t* WF = M.wbt + (int64_t)net * M.NPt;
-    const float* bn = M.master + (int64_t)net * M.NP;
-
-    auto from_x = [&](int k) {  // row rr of the features at k .. k + 3, rounded on the way in
-        bf16x4 f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) f[i] = (short)(rr < B ? f_to_bf16(Xn[(int64_t)rr * In + k + i]) : (uint16_t)0);
-        return f;
-    };
-    auto from_h1 = [&](int k) { return *reinterpret_cast<const bf16x4*>(&h1[rr * hs + k]); };
-    auto from_h2 = [&](int k) { return *reinterpret_cast<const bf16x4*>(&h2[rr * hs + k]); };
-    // C = A W on the columns [n0, n0 + 64) of W [K][ncol] (fragment copy at fb):
-    // this lane's accumulators of the four 16 x 16 blocks
-    auto blocks = [&](auto afrag, int64_t fb, int K, int ncol, int n0, f32x4* acc) {
-        const int nb0 = n0 / 16, nbs = (ncol + 15) / 16;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < K; k0 += 16 * kFwdSteps) {  // the fragments of kFwdSteps steps in flight together
-            bf16x4 af[kFwdSteps], bf[kFwdSteps][4];
-#pragma unroll
-            for (int t = 0; t < kFwdSteps; ++t) {
-                const int ks = k0 / 16 + t;
-                af[t] = afrag(16 * ks + q4);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bf[t][j] = nb0 + j < nbs
-                                   ? *reinterpret_cast<const bf16x4*>(
-                                         &WF[fb + (((int64_t)(nb0 + j) * (K / 16) + ks) * 64 + lane) * 4])
-                                   : bf16x4{0, 0, 0, 0};
-            }
-#pragma unroll
-            for (int t = 0; t < kFwdSteps; ++t)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[t], bf[t][j], acc[j], 0, 0, 0);
-        }
-    };
-    // dst[row][col] = bf16(SiLU(A W + b)) for the batch's rows, 0 beyond
-    auto hidden = [&](auto afrag, int64_t fb, const float* bias, int K, uint16_t* dst) {
-        for (int n0 = 64 * wave; n0 < H; n0 += 256) {
-            f32x4 acc[4];
-            blocks(afrag, fb, K, H, n0, acc);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = n0 + 16 * j + rr;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = q4 + v;
-                    dst[row * hs + col] = row < B ? f_to_bf16(silu(acc[j][v] + bias[col])) : (uint16_t)0;
-                }
-            }
-        }
-        __syncthreads();
-    };
-    hidden(from_x, 0, bn + M.ob1, In, h1);
-    hidden(from_h1, frag_w2(M), bn + M.ob2, H, h2);
-    const int n0 = blockIdx.x * 256 + 64 * wave;  // output columns of this wave
-    if (n0 >= Out) return;
-    f32x4 acc[4];
-    blocks(from_h2, frag_w3(M), H, Out, n0, acc);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = n0 + 16 * j + rr;
-        if (col >= Out) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = q4 + v;
-            if (row < B) O[(int64_t)net * B * Out + (int64_t)row * Out + col] = acc[j][v] + bn[M.ob3 + col];
-        }
-    }
-}
-
 // ------------------------------------------------------------------ features
-// Re, Im of a rotated so that a_0 is real and positive
-__device__ inline void write_features(const float* a, int N, float* X, int lane) {
+// Re, Im of mode k of a rotated so that a_0 is real and positive (the
+// network's input; one definition for every kernel that forms it, evaluated
+// without contraction so that every caller rounds the same way)
+__device__ inline void feature_of(const float* a, int k, float& fr, float& fi) {
+#pragma clang fp contract(off)
     const float x0 = a[0], y0 = a[1];
     const float r = sqrtf(x0 * x0 + y0 * y0);
     const float cr = r > 0.0f ? x0 / r : 1.0f, ci = r > 0.0f ? -y0 / r : 0.0f;
+    const float x = a[2 * k], y = a[2 * k + 1];
+    fr = x * cr - y * ci;
+    fi = x * ci + y * cr;
+}
+
+__device__ inline void write_features(const float* a, int N, float* X, int lane) {
     for (int k = lane; k < N; k += 64) {
-        const float x = a[2 * k], y = a[2 * k + 1];
-        X[k] = x * cr - y * ci;
-        X[N + k] = x * ci + y * cr;
+        float fr, fi;
+        feature_of(a, k, fr, fi);
+        X[k] = fr;
+        X[N + k] = fi;
     }
 }
 
 __device__ inline const float* copy_amp(const DevPtrs<float>& P, const ShapeInfo& sh, int N, int c) {
     return P.amp + 2 * (int64_t)c * N;  // one N for every sample: copies are contiguous
+}
+
+// ------------------------------------------------------------------ fused inference forward
+// MFMA fragment order of a weight matrix W [K][n] (K % 32 == 0, columns padded
+// with zeros to a multiple of 64): the B operand of v_mfma_f32_16x16x16_bf16 for column
+// block nb and K step ks is W[16 ks + 4 (l / 16) + i][16 nb + l % 16] in lane l,
+// slot i.  The operands of the steps 2p and 2p + 1 of a block sit together,
+// lane-major, 8 values per lane (step 2p in slots 0-3, step 2p + 1 in 4-7), so
+// one wave reads both steps as 1024 contiguous bytes, 16 per lane.
+__host__ __device__ inline int64_t frag_at(int64_t base, int K, int k, int n) {
+    const int ks = k / 16;
+    return base + (((int64_t)(n / 16) * (K / 32) + ks / 2) * 64 + (n % 16) + 16 * ((k % 16) / 4)) * 8 + 4 * (ks % 2) +
+           (k % 4);
+}
+__host__ __device__ inline int64_t frag_w2(const MlpDev& M) { return (int64_t)M.In * M.H; }
+__host__ __device__ inline int64_t frag_w3(const MlpDev& M) { return (int64_t)M.In * M.H + (int64_t)M.H * M.H; }
+// Inference batches of at most 16 rows in one launch instead of the feature
+// kernel and three GEMMs.  Workgroup (tile, net) forms the features of its
+// net's rows (from the copies at the net's temperature slot, or from the
+// proposals), computes both hidden layers (every tile of a net repeats them;
+// activations stay in LDS as bfloat16) and then output columns [256 tile,
+// 256 tile + 256).  Each of the 16 waves owns one 16 x 16 block of a layer at
+// a time (16-column block w, w + 16, ...), so a wave's chain of products is
+// short; it loads the block's weight fragments straight from the
+// fragment-order copy, sixteen K steps (8 loads of 16 bytes) at a time, so no
+// workgroup barrier falls inside a layer.  Every block sums its MFMAs over K
+// in the order k_gemm does, with the same bfloat16 operands, bias and SiLU:
+// the outputs are the same bits as the feature kernel followed by the three
+// GEMMs.
+constexpr int kFwdRows = 16;
+constexpr int kFwdWaves = 16;     // workgroup of 1024 threads
+constexpr int kFwdMaxTiles = 16;  // output tiles (256 columns each) up to which the fused path is used
+constexpr int kFwdPairs = 8;      // step pairs loaded together: 16 K steps, 256 inputs (a 128 tail: 4 pairs)
+enum FwdSource { kFwdCurrent = 0, kFwdProposal = 1 };
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+__host__ __device__ inline size_t forward_small_lds(int In, int H) {
+    return (size_t)kFwdRows * ((In + 4) + 2 * (H + 4)) * sizeof(uint16_t);
+}
+__host__ __device__ inline bool forward_small_fits(const MlpDev& M) {
+    return M.Bm <= kFwdRows && M.H % 128 == 0 && M.In % 128 == 0 && (M.Out + 255) / 256 <= kFwdMaxTiles &&
+           forward_small_lds(M.In, M.H) <= 64 * 1024;
+}
+
+// this lane's weight fragments of W[k0, k0 + 32 PAIRS)[16 nb ..]
+template <int PAIRS>
+__device__ inline void fwd_load(const uint16_t* WF, int64_t fb, int K, int nb, int k0, int lane, bf16x8 (&bw)[PAIRS]) {
+#pragma unroll
+    for (int p = 0; p < PAIRS; ++p)
+        bw[p] = *reinterpret_cast<const bf16x8*>(&WF[fb + (((int64_t)nb * (K / 32) + k0 / 32 + p) * 64 + lane) * 8]);
+}
+
+// acc += A[rows][k0, k0 + 32 PAIRS) W[k0, k0 + 32 PAIRS)[block]; A is a
+// bfloat16 tile in LDS (row stride as)
+template <int PAIRS>
+__device__ inline void fwd_mma(const uint16_t* A, int as, int k0, int rr, int q4, const bf16x8 (&bw)[PAIRS],
+                               f32x4& acc) {
+    bf16x4 af[2 * PAIRS];
+#pragma unroll
+    for (int t = 0; t < 2 * PAIRS; ++t) af[t] = *reinterpret_cast<const bf16x4*>(&A[rr * as + k0 + 16 * t + q4]);
+#pragma unroll
+    for (int p = 0; p < PAIRS; ++p) {
+        const bf16x4 lo = __builtin_shufflevector(bw[p], bw[p], 0, 1, 2, 3);
+        const bf16x4 hi = __builtin_shufflevector(bw[p], bw[p], 4, 5, 6, 7);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[2 * p], lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[2 * p + 1], hi, acc, 0, 0, 0);
+    }
+}
+
+template <int PAIRS>
+__device__ inline void fwd_batch(const uint16_t* A, int as, const uint16_t* WF, int64_t fb, int K, int nb, int k0,
+                                 int rr, int q4, int lane, f32x4& acc) {
+    bf16x8 bw[PAIRS];
+    fwd_load<PAIRS>(WF, fb, K, nb, k0, lane, bw);
+    // every load of the batch is issued before the first product waits (the
+    // scheduler would otherwise interleave them with the MFMAs, one memory
+    // round trip after another)
+    __builtin_amdgcn_sched_barrier(0);
+    fwd_mma<PAIRS>(A, as, k0, rr, q4, bw, acc);
+}
+
+// acc += A W on the 16-column block nb of W [K][.] over inputs [k0, K)
+// (fragment copy at fb; its columns are padded with zeros to a multiple of
+// 64, so every block of a 256-column tile exists; K - k0 is a multiple of 128)
+__device__ inline void fwd_block(const uint16_t* A, int as, const uint16_t* WF, int64_t fb, int K, int nb, int k0,
+                                 int rr, int q4, int lane, f32x4& acc) {
+    for (; k0 + 32 * kFwdPairs <= K; k0 += 32 * kFwdPairs)
+        fwd_batch<kFwdPairs>(A, as, WF, fb, K, nb, k0, rr, q4, lane, acc);
+    if (k0 < K) fwd_batch<kFwdPairs / 2>(A, as, WF, fb, K, nb, k0, rr, q4, lane, acc);
+}
+
+__global__ __launch_bounds__(1024) void k_forward_small(MlpDev M, DevPtrs<float> P, ShapeInfo sh, int src, float* O) {
+    extern __shared__ __align__(16) uint16_t fsm[];
+    const int N = M.N, H = M.H, In = M.In, Out = M.Out, B = M.Bm;
+    const int net = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rr = lane & 15, q4 = 4 * (lane >> 4);
+    const int xs = In + 4, hs = H + 4;  // LDS row strides (8-byte aligned rows)
+    uint16_t* x0 = fsm;
+    uint16_t* h1 = x0 + kFwdRows * xs;
+    uint16_t* h2 = h1 + kFwdRows * hs;
+    const uint16_t* WF = M.wbt + (int64_t)net * M.NPt;
+    const float* bn = M.master + (int64_t)net * M.NP;
+    // the wave's first layer-1 fragments (inputs 0..127) do not depend on the
+    // features: their loads are in flight while the features are formed
+    bf16x8 w1[kFwdPairs / 2];
+    if (16 * wave < H) fwd_load<kFwdPairs / 2>(WF, 0, In, wave, 0, lane, w1);
+    asm volatile("" ::: "memory");  // keep the loads ahead of the feature loop
+    // the input tile: features of each row's configuration rounded to bfloat16, zero rows beyond the batch
+    const int slot = M.temp_index[net];
+    for (int i = threadIdx.x; i < kFwdRows * N; i += blockDim.x) {
+        const int row = i / N, k = i - row * N;
+        uint16_t re = 0, im = 0;
+        if (row < B) {
+            const float* a = src == kFwdCurrent ? copy_amp(P, sh, N, P.copy_at[(int64_t)row * sh.n_temps + slot])
+                                                : M.ap + ((int64_t)net * B + row) * 2 * N;
+            float fr, fi;
+            feature_of(a, k, fr, fi);
+            re = f_to_bf16(fr);
+            im = f_to_bf16(fi);
+        }
+        x0[row * xs + k] = re;
+        x0[row * xs + N + k] = im;
+    }
+    if (src == kFwdCurrent && blockIdx.x == 0) {
+        if ((int)threadIdx.x < B) M.item_copy[(int64_t)net * B + threadIdx.x] = P.copy_at[(int64_t)threadIdx.x * sh.n_temps + slot];
+        // the round's index for the move draws: the later kernels of the round read it minus one
+        if (net == 0 && threadIdx.x == 0) *M.moves_done += 1;
+    }
+    __syncthreads();
+    // dst[row][col] = bf16(SiLU(A W + b)) for the batch's rows, 0 beyond
+    auto hidden = [&](const uint16_t* A, int as, int64_t fb, const float* bias, int K, uint16_t* dst, bool first) {
+        for (int nb = wave; 16 * nb < H; nb += kFwdWaves) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (first && nb == wave) {  // the prefetched fragments, then the rest of K
+                fwd_mma<kFwdPairs / 2>(A, as, 0, rr, q4, w1, acc);
+                fwd_block(A, as, WF, fb, K, nb, 128, rr, q4, lane, acc);
+            } else {
+                fwd_block(A, as, WF, fb, K, nb, 0, rr, q4, lane, acc);
+            }
+            const int col = 16 * nb + rr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = q4 + v;
+                dst[row * hs + col] = row < B ? f_to_bf16(silu(acc[v] + bias[col])) : (uint16_t)0;
+            }
+        }
+        __syncthreads();
+    };
+    hidden(x0, xs, 0, bn + M.ob1, In, h1, true);
+    hidden(h1, hs, frag_w2(M), bn + M.ob2, H, h2, false);
+    const int nb = blockIdx.x * 16 + wave;  // the output block of this wave
+    if (16 * nb >= Out) return;
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    fwd_block(h2, hs, WF, frag_w3(M), H, nb, 0, rr, q4, lane, acc);
+    const int col = 16 * nb + rr;
+    if (col >= Out) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = q4 + v;
+        if (row < B) O[(int64_t)net * B * Out + (int64_t)row * Out + col] = acc[v] + bn[M.ob3 + col];
+    }
 }
 
 __global__ __launch_bounds__(64) void k_feat_current(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
@@ -339,14 +409,14 @@ __device__ inline bool off_chart(const float* a, int N, int lane) {
 // the subset of a subset move or training item: a partial Fisher-Yates
 // shuffle of 0..N-1 in LDS whose step t swaps position t with
 // t + index_below(word(t), N - t), then the m drawn modes in ascending order.
-// Called by every lane of a single-wave workgroup.
+// Called by every thread (tid of nt) of the workgroup.
 template <typename Word>
-__device__ inline void draw_subset(int N, int m, Word word, int* perm, int* S, int lane) {
+__device__ inline void draw_subset(int N, int m, Word word, int* perm, int* S, int tid, int nt) {
     __shared__ int jt[kMaxSubset];
-    for (int k = lane; k < N; k += 64) perm[k] = k;
-    for (int t = lane; t < m; t += 64) jt[t] = t + index_below(word(t), N - t);  // the words, in parallel
+    for (int k = tid; k < N; k += nt) perm[k] = k;
+    for (int t = tid; t < m; t += nt) jt[t] = t + index_below(word(t), N - t);  // the words, in parallel
     __syncthreads();
-    if (lane == 0)
+    if (tid == 0)
         for (int t = 0; t < m; ++t) {
             const int j = jt[t];
             const int x = perm[t];
@@ -354,8 +424,8 @@ __device__ inline void draw_subset(int N, int m, Word word, int* perm, int* S, i
             perm[j] = x;
         }
     __syncthreads();
-    if (lane < m) {
-        const int v = perm[lane];
+    if (tid < m) {
+        const int v = perm[tid];
         int r = 0;
         for (int t = 0; t < m; ++t) r += perm[t] < v ? 1 : 0;
         S[r] = v;
@@ -402,8 +472,9 @@ __global__ __launch_bounds__(64) void k_feat_train(MlpDev M, uint64_t seed, int6
         __shared__ int S[kMaxSubset];
         const int m = M.m;
         draw_subset(N, m, [&](int t) {
-            return philox4x64((uint64_t)step, (uint64_t)net, (uint64_t)b, (uint64_t)(1 + t / 4), seed, kTagTrain).v[t & 3];
-        }, perm, S, lane);
+            return word_of(philox4x64((uint64_t)step, (uint64_t)net, (uint64_t)b, (uint64_t)(1 + t / 4), seed, kTagTrain),
+                           t & 3);
+        }, perm, S, lane, 64);
         for (int i = lane; i < m; i += 64) M.tsub[item * kMaxSubset + i] = S[i];
         const bool out = subset_off_chart(before, S, m, lane) || subset_off_chart(after, S, m, lane);
         if (lane == 0) M.tvalid[item] = out ? 0 : 1;
@@ -452,87 +523,119 @@ __global__ __launch_bounds__(64) void k_feat_ap(MlpDev M, int net, int n) {
 }
 
 // ------------------------------------------------------------------ mixture head
+// log normaliser of the mixture weights: log w_c = O[c] - mix_lse(O, K)
+__device__ inline float mix_lse(const float* O, int K) {
+    float mx = -INFINITY;
+    for (int i = 0; i < K; ++i) mx = fmaxf(mx, O[i]);
+    float s = 0.0f;
+    for (int i = 0; i < K; ++i) s += expf(O[i] - mx);
+    return mx + logf(s);
+}
+
 struct Mix {
     float lw[kMaxK];
 };
 
 __device__ inline void mix_weights(const float* O, int K, Mix& m) {
-    float mx = -INFINITY;
-    for (int i = 0; i < K; ++i) mx = fmaxf(mx, O[i]);
-    float s = 0.0f;
-    for (int i = 0; i < K; ++i) s += expf(O[i] - mx);
-    const float lse = mx + logf(s);
+    const float lse = mix_lse(O, K);
     for (int i = 0; i < K; ++i) m.lw[i] = O[i] - lse;
 }
 
 __device__ inline float smax_of(int d, int N) { return d < N - 1 ? kSmaxY : kSmaxPsi; }
 
-// log density of the (signed) displacement under the scaled mixture, wave-cooperative
-__device__ float log_mix(const float* O, const float* delta, float sign, float scale, int N, int K, int D, int lane) {
-    Mix mw;
-    mix_weights(O, K, mw);
-    float best = -INFINITY, terms[kMaxK];
-    for (int m = 0; m < K; ++m) {
-        float part = 0.0f;
-        for (int d = lane; d < D; d += 64) {
-            const float mu = scale * O[K + m * D + d];
-            const float sg = scale * smax_of(d, N) * sigm(O[K + K * D + m * D + d]);
-            const float x = sign * delta[d];
-            if (d < N - 1) {
-                const float z = (x - mu) / sg;
-                part += -logf(sg) - 0.5f * kLog2Pi - 0.5f * z * z;
-            } else {
-                const float t0 = wrapf(x - mu);
-                float s = 0.0f;
-#pragma unroll
-                for (int n = -3; n <= 3; ++n) {
-                    const float t = (t0 + 2.0f * kPiF * n) / sg;
-                    s += expf(-0.5f * t * t);
-                }
-                part += logf(s) - logf(sg) - 0.5f * kLog2Pi;
-            }
-        }
-        terms[m] = mw.lw[m] + wsum(part);
-        best = fmaxf(best, terms[m]);
+// the component of a move: the first c with sum_{i <= c} w_i > u
+__device__ inline int mix_component(const float* O, int K, double u) {
+    const float lse = mix_lse(O, K);
+    double cum = 0.0;
+    for (int i = 0; i < K; ++i) {
+        cum += (double)expf(O[i] - lse);
+        if (cum > u) return i;
     }
+    return K - 1;
+}
+
+// log of one coordinate's density: a Gaussian (chart coordinate) or a wrapped
+// Gaussian summed over |n| <= 3 (phase)
+__device__ inline float log_coord(float x, float mu, float sg, bool phase) {
+    if (!phase) {
+        const float z = (x - mu) / sg;
+        return -logf(sg) - 0.5f * kLog2Pi - 0.5f * z * z;
+    }
+    const float t0 = wrapf(x - mu);
     float s = 0.0f;
-    for (int m = 0; m < K; ++m) s += expf(terms[m] - best);
-    return best + logf(s);
+#pragma unroll
+    for (int n = -3; n <= 3; ++n) {
+        const float t = (t0 + 2.0f * kPiF * n) / sg;
+        s += expf(-0.5f * t * t);
+    }
+    return logf(s) - logf(sg) - 0.5f * kLog2Pi;
+}
+
+// log-sum-exp over the components, accumulated one component at a time
+struct Lse {
+    float best = -INFINITY, s = 0.0f;
+    __device__ void add(float t) {
+        if (t > best) {
+            s = s * expf(best - t) + 1.0f;
+            best = t;
+        } else {
+            s += expf(t - best);
+        }
+    }
+    __device__ float value() const { return best + logf(s); }
+};
+
+// the term of component mc of the log density of the (signed) displacement
+// under the scaled mixture: log w_mc + sum_d log N(delta_d; mu, sigma) (wave-
+// cooperative, the same value in every lane)
+__device__ float mix_term(const float* O, float lse, const float* delta, float sign, float scale, int N, int K, int D,
+                          int mc, int lane) {
+    float part = 0.0f;
+    for (int d = lane; d < D; d += 64) {
+        const float mu = scale * O[K + mc * D + d];
+        const float sg = scale * smax_of(d, N) * sigm(O[K + K * D + mc * D + d]);
+        part += log_coord(sign * delta[d], mu, sg, d >= N - 1);
+    }
+    return O[mc] - lse + wsum(part);
 }
 
 // the same over the coordinates of a subset S (2m - 1 values in delta)
-__device__ float log_mix_subset(const float* O, const int* S, const float* delta, float sign, float scale, int N,
-                                int K, int D, int m, int lane) {
-    Mix mw;
-    mix_weights(O, K, mw);
-    float best = -INFINITY, terms[kMaxK];
-    for (int mc = 0; mc < K; ++mc) {
-        float part = 0.0f;
-        for (int d = lane; d < 2 * m - 1; d += 64) {
-            const int ch = subset_channel(S, d, m, N);
-            const float mu = scale * O[K + mc * D + ch];
-            const float sg = scale * smax_of(ch, N) * sigm(O[K + K * D + mc * D + ch]);
-            const float x = sign * delta[d];
-            if (d < m - 1) {
-                const float z = (x - mu) / sg;
-                part += -logf(sg) - 0.5f * kLog2Pi - 0.5f * z * z;
-            } else {
-                const float t0 = wrapf(x - mu);
-                float sw = 0.0f;
-#pragma unroll
-                for (int n = -3; n <= 3; ++n) {
-                    const float t = (t0 + 2.0f * kPiF * n) / sg;
-                    sw += expf(-0.5f * t * t);
-                }
-                part += logf(sw) - logf(sg) - 0.5f * kLog2Pi;
-            }
-        }
-        terms[mc] = mw.lw[mc] + wsum(part);
-        best = fmaxf(best, terms[mc]);
+__device__ float mix_term_subset(const float* O, float lse, const int* S, const float* delta, float sign, float scale,
+                                 int N, int K, int D, int m, int mc, int lane) {
+    float part = 0.0f;
+    for (int d = lane; d < 2 * m - 1; d += 64) {
+        const int ch = subset_channel(S, d, m, N);
+        const float mu = scale * O[K + mc * D + ch];
+        const float sg = scale * smax_of(ch, N) * sigm(O[K + K * D + mc * D + ch]);
+        part += log_coord(sign * delta[d], mu, sg, d >= m - 1);
     }
-    float se = 0.0f;
-    for (int mc = 0; mc < K; ++mc) se += expf(terms[mc] - best);
-    return best + logf(se);
+    return O[mc] - lse + wsum(part);
+}
+
+// the log density from its component terms: waves w0, w0 + 1, ... of the
+// workgroup take components w0 + i, w0 + i + nw, ... (term(mc) is wave-
+// cooperative), the terms meet in LDS and are combined in component order.
+// Called by every thread; ends with a barrier; the value in every thread.
+template <typename Term>
+__device__ float log_mix_block(int K, Term term, float* sterm, int wave, int w0, int nw, int lane) {
+    if (wave >= w0 && wave < w0 + nw)
+        for (int mc = wave - w0; mc < K; mc += nw) {
+            const float t = term(mc);
+            if (lane == 0) sterm[mc] = t;
+        }
+    __syncthreads();
+    Lse acc;
+    for (int mc = 0; mc < K; ++mc) acc.add(sterm[mc]);
+    const float v = acc.value();
+    __syncthreads();  // sterm may be reused
+    return v;
+}
+
+// log of the uniform that decides a learned move: word 1 of the Philox block
+// after the move's Gaussians (counter word 3: 0 all-mode, 1 subset)
+__device__ inline double accept_log_uniform(uint64_t seed, int64_t move, int c, int nb, int subset) {
+    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, (uint64_t)subset, seed, kTagLearn);
+    return log(uniform01<double>(wu.v[1]));
 }
 
 // training head: mean NLL of the unwrapped mixture and its gradient w.r.t. the outputs
@@ -668,7 +771,7 @@ __device__ inline int64_t fragment_at(const MlpDev& M, int64_t p) {
 __device__ inline void store_bf16(const MlpDev& M, int64_t i, float w) {  // i over nets x NP
     const uint16_t b = f_to_bf16(w);
     M.wbf[i] = b;
-    if (M.In % 16 != 0 || M.H % 16 != 0) return;  // no fragment order for this shape (the fused path is off)
+    if (M.In % 32 != 0 || M.H % 32 != 0) return;  // no fragment order for this shape (the fused path is off)
     const int64_t net = i / M.NP, f = fragment_at(M, i - net * M.NP);
     if (f >= 0) M.wbt[net * M.NPt + f] = b;
 }
@@ -698,83 +801,114 @@ __global__ void k_sync_bf16(MlpDev M) {
 __device__ inline float move_gauss(uint64_t seed, int64_t move, int c, int d) {
     const Philox4 w = philox4x64((uint64_t)(d >> 1), (uint64_t)move, (uint64_t)c, 0, seed, kTagLearn);
     const int h = d & 1;
-    const double u1 = 1.0 - uniform01<double>(w.v[2 * h]);
-    const double u2 = uniform01<double>(w.v[2 * h + 1]);
+    const double u1 = 1.0 - uniform01<double>(word_of(w, 2 * h));
+    const double u2 = uniform01<double>(word_of(w, 2 * h + 1));
     return (float)(sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2));
 }
 
-__global__ __launch_bounds__(64) void k_propose(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+// The all-mode move's proposal.  Four waves share the serial work: wave 0
+// picks the component and the current chart coordinates while wave 1 draws
+// the Gaussians and wave 2 the acceptance uniform; every thread forms the
+// displacement; wave 0 builds the proposal; every wave then writes its
+// features and sums components of the forward log density.
+__global__ __launch_bounds__(256) void k_propose(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+    extern __shared__ float sO[];  // [Out] the item's network outputs, staged in one round of loads
     __shared__ float sdel[2 * kMaxModes];
-    __shared__ float slw[kMaxModes];
-    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    __shared__ float slw[kMaxModes / 2];
+    __shared__ float2 sp[kMaxModes / 2];  // the proposal
+    __shared__ float sterm[kMaxK];
+    __shared__ int s_mc, s_out;
+    __shared__ float s_dref;
+    const int net = blockIdx.y, b = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x, wave = tid >> 6, lane = tid & 63;
     const int N = M.N, K = M.K, D = M.D;
     const int64_t item = (int64_t)net * M.Bm + b;
     const int c = M.item_copy[item];
     const int64_t move = *M.moves_done - 1;
-    const float* O = M.Of + item * M.Out;
+    for (int i = tid; i < M.Out; i += nt) sO[i] = M.Of[item * M.Out + i];
+    __syncthreads();
+    const float* O = sO;
     const float* a = copy_amp(P, sh, N, c);
-    // component
-    Mix mw;
-    mix_weights(O, K, mw);
+    const float logN = logf((float)N);
     const int nb = (D + 1) / 2;
-    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
-    const double uc = uniform01<double>(wu.v[0]);
-    int m = K - 1;
-    double cum = 0.0;
-    for (int i = 0; i < K; ++i) {
-        cum += (double)expf(mw.lw[i]);
-        if (cum > uc) {
-            m = i;
-            break;
-        }
+    if (wave == 0) {  // the component, the current chart coordinates
+        const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, 0, sh.run_seed, kTagLearn);
+        const int mc = mix_component(O, K, uniform01<double>(wu.v[0]));
+        if (lane == 0) s_mc = mc;
+        for (int k = lane; k < N; k += 64) slw[k] = log_w(a, k, logN);
+    } else if (wave == 1) {  // the standard normals
+        for (int d = lane; d < D; d += 64) sdel[d] = move_gauss(sh.run_seed, move, c, d);
+    } else if (wave == 2 && lane == 0) {
+        M.lua[item] = accept_log_uniform(sh.run_seed, move, c, nb, 0);
     }
-    for (int d = lane; d < D; d += 64) {
-        const float mu = scale * O[K + m * D + d];
-        const float sg = scale * smax_of(d, N) * sigm(O[K + K * D + m * D + d]);
-        const float del = mu + sg * move_gauss(sh.run_seed, move, c, d);
+    __syncthreads();
+    const int mc = s_mc;
+    for (int d = tid; d < D; d += nt) {
+        const float mu = scale * O[K + mc * D + d];
+        const float sg = scale * smax_of(d, N) * sigm(O[K + K * D + mc * D + d]);
+        const float del = mu + sg * sdel[d];
         sdel[d] = del;
         M.delta[item * D + d] = del;
     }
-    const float logN = logf((float)N);
-    for (int k = lane; k < N; k += 64) slw[k] = log_w(a, k, logN);
     __syncthreads();
-    // new intensities from y' = y + dy (y'_{N-1} = 0), normalised on the simplex
-    const float last = slw[N - 1];
-    float mx = -INFINITY;
-    for (int k = lane; k < N; k += 64) mx = fmaxf(mx, k < N - 1 ? slw[k] - last + sdel[k] : 0.0f);
-    mx = wmax(mx);
-    float se = 0.0f;
-    for (int k = lane; k < N; k += 64) se += expf((k < N - 1 ? slw[k] - last + sdel[k] : 0.0f) - mx);
-    const float lse = mx + logf(wsum(se));
-    float dref = 0.0f;
+    if (wave == 0) {
+        // new intensities from y' = y + dy (y'_{N-1} = 0), normalised on the simplex
+        const float last = slw[N - 1];
+        float mx = -INFINITY;
+        for (int k = lane; k < N; k += 64) mx = fmaxf(mx, k < N - 1 ? slw[k] - last + sdel[k] : 0.0f);
+        mx = wmax(mx);
+        float se = 0.0f;
+        for (int k = lane; k < N; k += 64) se += expf((k < N - 1 ? slw[k] - last + sdel[k] : 0.0f) - mx);
+        const float lse = mx + logf(wsum(se));
+        float dref = 0.0f;
+        int bad = 0;
+        for (int k = lane; k < N; k += 64) {
+            const float lwn = (k < N - 1 ? slw[k] - last + sdel[k] : 0.0f) - lse;
+            dref += 0.5f * (lwn - slw[k]);
+            const float A = expf(0.25f * (logN + lwn));
+            const float x = a[2 * k], y = a[2 * k + 1];
+            const float ph = atan2f(y, x) + sdel[N - 1 + k];
+            float sn, cs;
+            sincosf(ph, &sn, &cs);
+            const float2 v = make_float2(A * cs, A * sn);
+            sp[k] = v;
+            // a move from a configuration off the alr chart (a zero amplitude), or
+            // to a proposal with an intensity that underflowed to zero, is rejected
+            const float u0 = x * x + y * y, u1 = v.x * v.x + v.y * v.y;
+            bad |= !(u0 > 0.0f) || !isfinite(x) || !isfinite(y) || !isfinite(u0);
+            bad |= !(u1 > 0.0f) || !isfinite(v.x) || !isfinite(v.y) || !isfinite(u1);
+        }
+        dref = wsum(dref);
+        const bool out = __any(bad);
+        if (lane == 0) {
+            s_out = out;
+            s_dref = out ? -INFINITY : dref;
+        }
+    }
+    __syncthreads();
+    // the proposal (the current configuration when rejected: the later stages see finite values only)
+    const bool out = s_out;
     float* ap = M.ap + item * 2 * N;
-    for (int k = lane; k < N; k += 64) {
-        const float lwn = (k < N - 1 ? slw[k] - last + sdel[k] : 0.0f) - lse;
-        dref += 0.5f * (lwn - slw[k]);
-        const float A = expf(0.25f * (logN + lwn));
-        const float ph = atan2f(a[2 * k + 1], a[2 * k]) + sdel[N - 1 + k];
-        float sn, cs;
-        sincosf(ph, &sn, &cs);
-        ap[2 * k] = A * cs;
-        ap[2 * k + 1] = A * sn;
+    for (int k = tid; k < N; k += nt) {
+        const float2 v = out ? make_float2(a[2 * k], a[2 * k + 1]) : sp[k];
+        if (out) sp[k] = v;
+        ap[2 * k] = v.x;
+        ap[2 * k + 1] = v.y;
     }
-    dref = wsum(dref);
-    __syncthreads();  // ap complete
-    // a move from a configuration off the alr chart (a zero amplitude), or to a
-    // proposal with an intensity that underflowed to zero, is rejected: its
-    // reference-density term is -inf, and the proposal is replaced by the
-    // current configuration so that the later stages see finite values only
-    const bool out = off_chart(a, N, lane) || off_chart(ap, N, lane);
-    if (out) {
-        for (int k = lane; k < 2 * N; k += 64) ap[k] = a[k];
-        dref = -INFINITY;
+    if (out) __syncthreads();
+    float* X = M.X + item * M.In;  // the network's input at the proposal
+    for (int k = tid; k < N; k += nt) {
+        float fr, fi;
+        feature_of(reinterpret_cast<const float*>(sp), k, fr, fi);
+        X[k] = fr;
+        X[N + k] = fi;
     }
-    __syncthreads();
-    write_features(ap, N, M.X + item * M.In, lane);  // the network's input at the proposal
-    const float lq = log_mix(O, sdel, 1.0f, scale, N, K, D, lane);
-    if (lane == 0) {
+    const float mlse = mix_lse(O, K);
+    const float lq = log_mix_block(K, [&](int m) { return mix_term(O, mlse, sdel, 1.0f, scale, N, K, D, m, lane); },
+                                   sterm, wave, 0, nt >> 6, lane);
+    if (tid == 0) {
         M.lqf[item] = lq;
-        M.dref[item] = dref;
+        M.dref[item] = s_dref;
     }
 }
 
@@ -856,234 +990,328 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
 __device__ inline float subset_gauss(uint64_t seed, int64_t move, int c, int d) {
     const Philox4 w = philox4x64((uint64_t)(d >> 1), (uint64_t)move, (uint64_t)c, 1, seed, kTagLearn);
     const int h = d & 1;
-    const double u1 = 1.0 - uniform01<double>(w.v[2 * h]);
-    const double u2 = uniform01<double>(w.v[2 * h + 1]);
+    const double u1 = 1.0 - uniform01<double>(word_of(w, 2 * h));
+    const double u2 = uniform01<double>(word_of(w, 2 * h + 1));
     return (float)(sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2));
 }
 
-// subset move, stage one: the subset, the component, the displacement in the
-// subset's chart, the proposal (other modes copied), the reference ratio, the
-// forward log density and the network's input at the proposal
-__global__ __launch_bounds__(64) void k_propose_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+// subset move: the proposal and its energy change, one workgroup per item.
+// The item's network outputs and configuration are staged in LDS first (one
+// round of loads instead of one per dependent read).  Wave 0 draws the
+// component and the displacement of the subset's chart coordinates and forms
+// the proposal (other modes copied), the reference ratio, the forward log
+// density and the network's input at the proposal; then every wave sums the
+// energy change from the subset's lists as the mode-by-mode sum
+// dE = sum_i -2 Re(conj(a'_i - a_i) F_i), F_i on a snapshot that already
+// holds the proposal for the modes before s_i (exact: every term holds a mode
+// at most once).
+template <int BLOCK, int UNITS>
+__global__ __launch_bounds__(BLOCK) void k_propose_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+    extern __shared__ float dyn[];  // [N] float2 snapshot, [N] float2 proposal, [Out] outputs
     __shared__ int perm[kMaxModes / 2];
     __shared__ int S[kMaxSubset];
     __shared__ float sdel[2 * kMaxSubset];
     __shared__ float slw[kMaxSubset];
-    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
+    __shared__ float2 snew[kMaxSubset];
+    __shared__ float red[16][2];
+    __shared__ int uoff[kMaxSubset + 1];
+    __shared__ uint32_t ustart[kMaxSubset];
+    __shared__ float sterm[kMaxK];
+    __shared__ int s_mc;
+    __shared__ float s_dref;
+    const int N = M.N, K = M.K, D = M.D, m = M.m;
+    float2* sa = reinterpret_cast<float2*>(dyn);
+    float2* sp = sa + N;
+    float* sO = dyn + 4 * N;
+    const int tid = threadIdx.x, nt = blockDim.x, wave = tid >> 6, lane = tid & 63;
+    const int net = blockIdx.y;
+    const int64_t item = (int64_t)net * M.Bm + blockIdx.x;
+    const int c = M.item_copy[item];
+    const int64_t move = *M.moves_done - 1;
+    const float* a = copy_amp(P, sh, N, c);
+    const float* O = M.Of + item * M.Out;
+    for (int k = tid; k < N; k += nt) sa[k] = sp[k] = make_float2(a[2 * k], a[2 * k + 1]);
+    for (int i = tid; i < M.Out; i += nt) sO[i] = O[i];
+    draw_subset(N, m, [&](int t) {
+        return word_of(philox4x64((uint64_t)(m + 1 + t / 4), (uint64_t)move, (uint64_t)c, 1, sh.run_seed, kTagLearn),
+                       t & 3);
+    }, perm, S, tid, nt);  // ends with a barrier: the staged values are visible too
+    const float logN = logf((float)N);
+    auto lw_of = [&](float2 v) { return 2.0f * logf(v.x * v.x + v.y * v.y) - logN; };  // log w_k
+    // wave 0: the component and the subset's chart coordinates; wave 1: the
+    // standard normals; wave 2: the acceptance uniform
+    if (wave == 0) {
+        const Philox4 wu = philox4x64((uint64_t)m, (uint64_t)move, (uint64_t)c, 1, sh.run_seed, kTagLearn);
+        const int mc = mix_component(sO, K, uniform01<double>(wu.v[0]));
+        if (lane == 0) s_mc = mc;
+        for (int i = lane; i < m; i += 64) {
+            slw[i] = lw_of(sa[S[i]]);
+            M.subset[item * kMaxSubset + i] = S[i];
+        }
+    } else if (wave == 1) {
+        for (int d = lane; d < 2 * m - 1; d += 64) sdel[d] = subset_gauss(sh.run_seed, move, c, d);
+    } else if (wave == 2 && lane == 0) {
+        M.lua[item] = accept_log_uniform(sh.run_seed, move, c, m, 1);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const int mc = s_mc;
+        for (int d = lane; d < 2 * m - 1; d += 64) {
+            const int ch = subset_channel(S, d, m, N);
+            const float mu = scale * sO[K + mc * D + ch];
+            const float sg = scale * smax_of(ch, N) * sigm(sO[K + K * D + mc * D + ch]);
+            const float del = mu + sg * sdel[d];
+            sdel[d] = del;
+            M.delta[item * D + d] = del;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // u' = u + du (u'_m = 0); the subset's total intensity is kept:
+        // log w'_i = v_i - logsumexp(v) + logsumexp(log w_S)
+        float mx = -INFINITY, mx0 = -INFINITY;
+        for (int i = lane; i < m; i += 64) {
+            mx = fmaxf(mx, i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f);
+            mx0 = fmaxf(mx0, slw[i]);
+        }
+        mx = wmax(mx);
+        mx0 = wmax(mx0);
+        float se = 0.0f, se0 = 0.0f;
+        for (int i = lane; i < m; i += 64) {
+            se += expf((i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f) - mx);
+            se0 += expf(slw[i] - mx0);
+        }
+        const float lse = mx + logf(wsum(se)), ltot = mx0 + logf(wsum(se0));
+        float dref = 0.0f;
+        int bad = 0;
+        for (int i = lane; i < m; i += 64) {
+            const float2 o = sa[S[i]];
+            const float lwn = (i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f) - lse + ltot;
+            dref += 0.5f * (lwn - slw[i]);
+            const float A = expf(0.25f * (logN + lwn));
+            const float ph = atan2f(o.y, o.x) + sdel[m - 1 + i];
+            float sn, cs;
+            sincosf(ph, &sn, &cs);
+            const float2 v = make_float2(A * cs, A * sn);
+            snew[i] = v;
+            // a move touching a zero amplitude of S (now or in the proposal) is rejected
+            const float u0 = o.x * o.x + o.y * o.y, u1 = v.x * v.x + v.y * v.y;
+            bad |= !(u0 > 0.0f) || !isfinite(o.x) || !isfinite(o.y) || !isfinite(u0);
+            bad |= !(u1 > 0.0f) || !isfinite(v.x) || !isfinite(v.y) || !isfinite(u1);
+        }
+        dref = wsum(dref);
+        if (__any(bad)) {
+            for (int i = lane; i < m; i += 64) snew[i] = sa[S[i]];
+            dref = -INFINITY;
+        }
+        for (int i = lane; i < m; i += 64) sp[S[i]] = snew[i];
+        if (lane == 0) s_dref = dref;
+    }
+    __syncthreads();
+    {  // the forward log density, components over the waves
+        const float mlse = mix_lse(sO, K);
+        const float lq = log_mix_block(
+            K, [&](int mc) { return mix_term_subset(sO, mlse, S, sdel, 1.0f, scale, N, K, D, m, mc, lane); }, sterm,
+            wave, 0, nt >> 6, lane);
+        if (tid == 0) {
+            M.lqf[item] = lq;
+            M.dref[item] = s_dref;
+        }
+    }
+    // the proposal, and its features for the GEMM forward
+    float* ap = M.ap + item * 2 * N;
+    float* X = M.X + item * M.In;
+    for (int k = tid; k < N; k += nt) {
+        const float2 v = sp[k];
+        ap[2 * k] = v.x;
+        ap[2 * k + 1] = v.y;
+        float fr, fi;
+        feature_of(reinterpret_cast<const float*>(sp), k, fr, fi);
+        X[k] = fr;
+        X[N + k] = fi;
+    }
+    if (s_dref == -INFINITY) {  // rejected: no energy change is needed
+        if (tid == 0) M.dE[item] = 0.0f;
+        return;
+    }
+    // The energy change in one pass over the subset's lists.  An entry of the
+    // list of s_i sees the proposal at the modes s_j, j < i, and the current
+    // configuration elsewhere (the snapshot of the mode-by-mode sum), so its
+    // term -2 Re(conj(a'_i - a_i) J conj(a_x) a_y a_z) needs no other entry:
+    // the lists are streamed together, several units per thread in flight.
+    // pos[k] = rank of mode k in S (m when k is not in S); units = chunks of 4
+    // entries (chunked lists) or groups of 4 entries (packed lists).
+    int* pos = perm;  // the shuffle is no longer needed
+    const SampleDev sd = P.samples[c / sh.copies_per_sample];
+    const bool chunked = sh.layout == kLayoutChunked;
+    const uint32_t* us = chunked ? P.chunk_start + sd.mode_base : P.mode_start + sd.mode_base;
+    const int ushift = chunked ? 0 : 2;  // packed lists: mode_start counts entries (a multiple of 4)
+    for (int k = tid; k < N; k += nt) pos[k] = m;
+    if (wave == 0) {  // unit offsets of the lists in S order: an inclusive scan over the wave
+        const int l = lane < m ? S[lane] : 0;
+        int len = lane < m ? (int)((us[l + 1] - us[l]) >> ushift) : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(len, o, 64);
+            if (lane >= o) len += v;
+        }
+        if (lane < m) {
+            uoff[lane + 1] = len;
+            ustart[lane] = us[l] >> ushift;
+        }
+        if (lane == 0) uoff[0] = 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += nt) pos[S[i]] = i;
+    __syncthreads();
+    auto val = [&](int k, int i) { return pos[k] < i ? sp[k] : sa[k]; };
+    const int total = uoff[m];
+    constexpr int kU = UNITS;  // units per thread in flight
+    float part = 0.0f;
+    int i = 0;
+    for (int g0 = tid; g0 < total; g0 += kU * nt) {
+        int li[kU];
+        uint32_t qi[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int g = g0 + u * nt;
+            li[u] = -1;
+            if (g < total) {
+                while (g >= uoff[i + 1]) ++i;
+                li[u] = i;
+                qi[u] = ustart[i] + (uint32_t)(g - uoff[i]);
+            }
+        }
+        if (chunked) {
+            uint32_t xv[kU];
+            uint2 yzv[kU];
+            float4 jv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (li[u] >= 0) {
+                    xv[u] = P.cx[qi[u]];
+                    yzv[u] = P.cyz[qi[u]];
+                    jv[u] = reinterpret_cast<const float4*>(P.cJ)[qi[u]];
+                }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (li[u] < 0) continue;
+                const int ii = li[u];
+                const float2 ax = val(xv[u], ii);
+                const uint32_t v[4] = {yzv[u].x & 0xffffu, yzv[u].x >> 16, yzv[u].y & 0xffffu, yzv[u].y >> 16};
+                const float jj[4] = {jv[u].x, jv[u].y, jv[u].z, jv[u].w};
+                float gr = 0.0f, gi = 0.0f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float2 ay = val(v[e] & 0xffu, ii), az = val((v[e] >> 8) & 0xffu, ii);
+                    gr += jj[e] * (ay.x * az.x - ay.y * az.y);
+                    gi += jj[e] * (ay.x * az.y + ay.y * az.x);
+                }
+                const float fr = ax.x * gr + ax.y * gi, fi = ax.x * gi - ax.y * gr;
+                const int l = S[ii];
+                part += -2.0f * ((snew[ii].x - sa[l].x) * fr + (snew[ii].y - sa[l].y) * fi);
+            }
+        } else {
+            uint4 iv[kU];
+            float4 jv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (li[u] >= 0) {
+                    iv[u] = reinterpret_cast<const uint4*>(P.idx)[qi[u]];
+                    jv[u] = reinterpret_cast<const float4*>(P.J)[qi[u]];
+                }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (li[u] < 0) continue;
+                const int ii = li[u];
+                const uint32_t ev[4] = {iv[u].x, iv[u].y, iv[u].z, iv[u].w};
+                const float jj[4] = {jv[u].x, jv[u].y, jv[u].z, jv[u].w};
+                float fr = 0.0f, fi = 0.0f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float2 ax = val(ev[e] & 1023u, ii), ay = val((ev[e] >> 10) & 1023u, ii),
+                                 az = val(ev[e] >> 20, ii);
+                    const float pr = ax.x * ay.x + ax.y * ay.y, pi = ax.x * ay.y - ax.y * ay.x;
+                    fr += jj[e] * (pr * az.x - pi * az.y);
+                    fi += jj[e] * (pr * az.y + pi * az.x);
+                }
+                const int l = S[ii];
+                part += -2.0f * ((snew[ii].x - sa[l].x) * fr + (snew[ii].y - sa[l].y) * fi);
+            }
+        }
+    }
+    part = wsum(part);
+    if (lane == 0) red[wave][0] = part;
+    __syncthreads();
+    if (tid == 0) {
+        float dE = 0.0f;
+        for (int w = 0; w < (nt >> 6); ++w) dE += red[w][0];
+        M.dE[item] = dE;
+    }
+}
+
+// The loads of the item's data are issued together at the start (one round
+// trip, then one for the inverse temperature and the running energy), the
+// proposal row included: it is stored into the configuration only on
+// acceptance.  The reverse log density's components are summed on the four
+// waves; the uniform that decides was drawn with the proposal.
+constexpr int kAcceptThreads = 256;
+constexpr int kApPerThread = kMaxModes / kAcceptThreads;  // floats of the proposal row per thread (2N <= kMaxModes)
+
+__global__ __launch_bounds__(kAcceptThreads) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
+    extern __shared__ float sO[];  // [Out] the network's outputs at the proposal
+    __shared__ float sdel[2 * kMaxModes];
+    __shared__ int S[kMaxSubset];
+    __shared__ float sterm[kMaxK];
+    __shared__ int s_acc;
+    const int net = blockIdx.y, b = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int N = M.N, K = M.K, D = M.D, m = M.m;
     const int64_t item = (int64_t)net * M.Bm + b;
     const int c = M.item_copy[item];
-    const int64_t move = *M.moves_done - 1;
-    const float* O = M.Of + item * M.Out;
-    const float* a = copy_amp(P, sh, N, c);
-    Mix mw;
-    mix_weights(O, K, mw);
-    const Philox4 wu = philox4x64((uint64_t)m, (uint64_t)move, (uint64_t)c, 1, sh.run_seed, kTagLearn);
-    const double uc = uniform01<double>(wu.v[0]);
-    int mc = K - 1;
-    double cum = 0.0;
-    for (int i = 0; i < K; ++i) {
-        cum += (double)expf(mw.lw[i]);
-        if (cum > uc) {
-            mc = i;
-            break;
-        }
-    }
-    draw_subset(N, m, [&](int t) {
-        return philox4x64((uint64_t)(m + 1 + t / 4), (uint64_t)move, (uint64_t)c, 1, sh.run_seed, kTagLearn).v[t & 3];
-    }, perm, S, lane);
-    for (int d = lane; d < 2 * m - 1; d += 64) {
-        const int ch = subset_channel(S, d, m, N);
-        const float mu = scale * O[K + mc * D + ch];
-        const float sg = scale * smax_of(ch, N) * sigm(O[K + K * D + mc * D + ch]);
-        const float del = mu + sg * subset_gauss(sh.run_seed, move, c, d);
-        sdel[d] = del;
-        M.delta[item * D + d] = del;
-    }
-    const float logN = logf((float)N);
-    for (int i = lane; i < m; i += 64) {
-        slw[i] = log_w(a, S[i], logN);
-        M.subset[item * kMaxSubset + i] = S[i];
-    }
-    __syncthreads();
-    // u' = u + du (u'_m = 0); the subset's total intensity is kept:
-    // log w'_i = v_i - logsumexp(v) + logsumexp(log w_S)
-    float mx = -INFINITY, mx0 = -INFINITY;
-    for (int i = lane; i < m; i += 64) {
-        mx = fmaxf(mx, i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f);
-        mx0 = fmaxf(mx0, slw[i]);
-    }
-    mx = wmax(mx);
-    mx0 = wmax(mx0);
-    float se = 0.0f, se0 = 0.0f;
-    for (int i = lane; i < m; i += 64) {
-        se += expf((i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f) - mx);
-        se0 += expf(slw[i] - mx0);
-    }
-    const float lse = mx + logf(wsum(se)), ltot = mx0 + logf(wsum(se0));
-    float* ap = M.ap + item * 2 * N;
-    for (int k = lane; k < 2 * N; k += 64) ap[k] = a[k];
-    __syncthreads();
-    float dref = 0.0f;
-    for (int i = lane; i < m; i += 64) {
-        const int k = S[i];
-        const float lwn = (i < m - 1 ? slw[i] - slw[m - 1] + sdel[i] : 0.0f) - lse + ltot;
-        dref += 0.5f * (lwn - slw[i]);
-        const float A = expf(0.25f * (logN + lwn));
-        const float ph = atan2f(a[2 * k + 1], a[2 * k]) + sdel[m - 1 + i];
-        float sn, cs;
-        sincosf(ph, &sn, &cs);
-        ap[2 * k] = A * cs;
-        ap[2 * k + 1] = A * sn;
-    }
-    dref = wsum(dref);
-    __syncthreads();
-    // a move touching a zero amplitude of S (now or in the proposal) is rejected
-    const bool out = subset_off_chart(a, S, m, lane) || subset_off_chart(ap, S, m, lane);
-    if (out) {
-        for (int i = lane; i < m; i += 64) {
-            ap[2 * S[i]] = a[2 * S[i]];
-            ap[2 * S[i] + 1] = a[2 * S[i] + 1];
-        }
-        dref = -INFINITY;
-    }
-    __syncthreads();
-    write_features(ap, N, M.X + item * M.In, lane);
-    const float lq = log_mix_subset(O, S, sdel, 1.0f, scale, N, K, D, m, lane);
-    if (lane == 0) {
-        M.lqf[item] = lq;
-        M.dref[item] = dref;
-    }
-}
-
-// field F_l = sum over l's list of J conj(a_x) a_y a_z from amplitudes a in
-// LDS; thread t of nt takes every nt-th chunk (chunked lists) or group of 4
-// entries (packed lists)
-__device__ inline void list_field(const DevPtrs<float>& P, const SampleDev& sd, int layout, int l, const float2* a,
-                                  int t, int nt, float& fr, float& fi) {
-    if (layout == kLayoutChunked) {
-        const uint32_t* cs = P.chunk_start + sd.mode_base;
-        const float4* Jv = reinterpret_cast<const float4*>(P.cJ);
-        for (uint32_t q = cs[l] + t; q < cs[l + 1]; q += nt) {
-            const float2 ax = a[P.cx[q]];
-            const uint2 yz = P.cyz[q];
-            const float4 j = Jv[q];
-            const uint32_t v[4] = {yz.x & 0xffffu, yz.x >> 16, yz.y & 0xffffu, yz.y >> 16};
-            const float jj[4] = {j.x, j.y, j.z, j.w};
-            float gr = 0.0f, gi = 0.0f;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float2 ay = a[v[i] & 0xffu], az = a[(v[i] >> 8) & 0xffu];
-                gr += jj[i] * (ay.x * az.x - ay.y * az.y);
-                gi += jj[i] * (ay.x * az.y + ay.y * az.x);
-            }
-            fr += ax.x * gr + ax.y * gi;
-            fi += ax.x * gi - ax.y * gr;
-        }
-    } else {
-        const uint32_t* ms = P.mode_start + sd.mode_base;
-        for (uint32_t q = ms[l] + t; q < ms[l + 1]; q += nt) {
-            const uint32_t e = P.idx[q];
-            const float2 ax = a[e & 1023u], ay = a[(e >> 10) & 1023u], az = a[e >> 20];
-            const float pr = ax.x * ay.x + ax.y * ay.y, pi = ax.x * ay.y - ax.y * ay.x;
-            fr += P.J[q] * (pr * az.x - pi * az.y);
-            fi += P.J[q] * (pr * az.y + pi * az.x);
-        }
-    }
-}
-
-// subset move, stage two: the energy change, mode by mode on a snapshot that
-// already holds the proposal for the modes before: dE = sum_i -2 Re(conj(a'_i - a_i) F_i)
-// (exact: every term holds a mode at most once).  One workgroup of up to 1024
-// threads per item: the items are few, and each list is streamed by the whole
-// workgroup before the next can start.
-__global__ __launch_bounds__(1024) void k_energy_subset(MlpDev M, DevPtrs<float> P, ShapeInfo sh) {
-    extern __shared__ float2 sa[];  // [N] the snapshot
-    __shared__ float red[16][2];
-    const int64_t item = blockIdx.x;
-    const int N = M.N, m = M.m;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (M.dref[item] == -INFINITY) {  // rejected in stage one
-        if (threadIdx.x == 0) M.dE[item] = 0.0f;
-        return;
-    }
-    const int c = M.item_copy[item];
-    const SampleDev sd = P.samples[c / sh.copies_per_sample];
-    const float* a = copy_amp(P, sh, N, c);
-    const float* ap = M.ap + item * 2 * N;
-    const int* S = M.subset + item * kMaxSubset;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) sa[k] = make_float2(a[2 * k], a[2 * k + 1]);
-    __syncthreads();
-    float dE = 0.0f;
-    for (int i = 0; i < m; ++i) {
-        const int l = S[i];
-        float fr = 0.0f, fi = 0.0f;
-        list_field(P, sd, sh.layout, l, sa, threadIdx.x, blockDim.x, fr, fi);
-        fr = wsum(fr);
-        fi = wsum(fi);
-        if (lane == 0) {
-            red[wave][0] = fr;
-            red[wave][1] = fi;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float Fr = 0.0f, Fi = 0.0f;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-                Fr += red[w][0];
-                Fi += red[w][1];
-            }
-            const float2 o = sa[l];
-            const float nr = ap[2 * l], ni = ap[2 * l + 1];
-            dE += -2.0f * ((nr - o.x) * Fr + (ni - o.y) * Fi);
-            sa[l] = make_float2(nr, ni);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) M.dE[item] = dE;
-}
-
-__global__ __launch_bounds__(64) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
-    __shared__ float sdel[2 * kMaxModes];
-    const int net = blockIdx.y, b = blockIdx.x, lane = threadIdx.x;
-    const int N = M.N, K = M.K, D = M.D;
-    const int64_t item = (int64_t)net * M.Bm + b;
-    const int c = M.item_copy[item];
-    const int64_t move = *M.moves_done - 1;
-    __shared__ int S[kMaxSubset];
-    const int m = M.m;
+    const int slot = M.temp_index[net];
+    const float dref = M.dref[item], lqf = M.lqf[item];
+    const double lua = M.lua[item];
+    float dE = m > 0 ? M.dE[item] : 0.0f;
     const int nd = m > 0 ? 2 * m - 1 : D;
-    for (int d = lane; d < nd; d += 64) sdel[d] = M.delta[item * D + d];
-    for (int i = lane; i < m; i += 64) S[i] = M.subset[item * kMaxSubset + i];
-    __syncthreads();
-    float lqr, dE = 0.0f;
-    if (m > 0) {
-        lqr = log_mix_subset(M.Or + item * M.Out, S, sdel, -1.0f, scale, N, K, D, m, lane);
-        dE = M.dE[item];
-    } else {
-        lqr = log_mix(M.Or + item * M.Out, sdel, -1.0f, scale, N, K, D, lane);
+    for (int d = tid; d < nd; d += kAcceptThreads) sdel[d] = M.delta[item * D + d];
+    for (int i = tid; i < m; i += kAcceptThreads) S[i] = M.subset[item * kMaxSubset + i];
+    for (int i = tid; i < M.Out; i += kAcceptThreads) sO[i] = M.Or[item * M.Out + i];
+    const float* ap = M.ap + item * 2 * N;
+    float apv[kApPerThread];
+#pragma unroll
+    for (int r = 0; r < kApPerThread; ++r)
+        if (tid + kAcceptThreads * r < 2 * N) apv[r] = ap[tid + kAcceptThreads * r];
+    if (m == 0)
         for (int p = 0; p < kEnergyParts; ++p) dE += M.dEp[item * kEnergyParts + p];  // the parts, added in order
-    }
-    const float beta = P.beta[M.temp_index[net]];
-    const float dref = M.dref[item];
-    const float la = dref == -INFINITY ? -INFINITY : -beta * dE + dref + lqr - M.lqf[item];
-    // the acceptance uniform: word 1 of the block after the Gaussians (counter word 3: 0 all-mode, 1 subset)
-    const int nb = m > 0 ? m : (D + 1) / 2;
-    const Philox4 wu = philox4x64((uint64_t)nb, (uint64_t)move, (uint64_t)c, m > 0 ? 1 : 0, sh.run_seed, kTagLearn);
-    const double ua = uniform01<double>(wu.v[1]);
-    const bool accept = log(ua) < (double)la;
-    if (accept) {
-        float* a = P.amp + 2 * (int64_t)c * N;
-        const float* ap = M.ap + item * 2 * N;
-        for (int k = lane; k < 2 * N; k += 64) a[k] = ap[k];
-    }
-    if (lane == 0) {
+    const float beta = P.beta[slot];
+    const float E0 = P.E[c];
+    __syncthreads();
+    const float mlse = mix_lse(sO, K);
+    const float lqr =
+        m > 0 ? log_mix_block(
+                    K, [&](int mc) { return mix_term_subset(sO, mlse, S, sdel, -1.0f, scale, N, K, D, m, mc, lane); },
+                    sterm, wave, 0, kAcceptThreads / 64, lane)
+              : log_mix_block(K, [&](int mc) { return mix_term(sO, mlse, sdel, -1.0f, scale, N, K, D, mc, lane); },
+                              sterm, wave, 0, kAcceptThreads / 64, lane);
+    const float la = dref == -INFINITY ? -INFINITY : -beta * dE + dref + lqr - lqf;
+    if (tid == 0) {
+        const bool accept = lua < (double)la;
+        s_acc = accept;
         M.la[item] = la;
         M.dE[item] = dE;
         if (accept) {
-            P.E[c] += dE;
+            P.E[c] = E0 + dE;
             atomicAdd(&M.acc[net], 1ull);
         }
         atomicAdd(&M.tries[net], 1ull);
+    }
+    __syncthreads();
+    if (s_acc) {
+        float* a = P.amp + 2 * (int64_t)c * N;
+#pragma unroll
+        for (int r = 0; r < kApPerThread; ++r)
+            if (tid + kAcceptThreads * r < 2 * N) a[tid + kAcceptThreads * r] = apv[r];
     }
 }
 
@@ -1107,25 +1335,35 @@ __global__ __launch_bounds__(64) void k_harvest(MlpDev M, DevPtrs<float> P, Shap
 
 }  // namespace
 
-hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
-    hipLaunchKernelGGL(k_feat_current, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh);
-    return hipGetLastError();
-}
-
 hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int use_first, hipStream_t st) {
     hipLaunchKernelGGL(k_feat_train, dim3(M.Bt, M.nets), dim3(64), 0, st, M, seed, step, use_first);
     return hipGetLastError();
 }
 
-hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st) {
-    const int tiles = (M.Out + 255) / 256;
-    if (!train && M.Bm <= kFwdRows && M.H % (16 * kFwdSteps) == 0 && M.In % (16 * kFwdSteps) == 0 &&
-        tiles <= kFwdMaxTiles &&
-        forward_small_lds(M.H) <= 64 * 1024) {
-        hipLaunchKernelGGL(k_forward_small, dim3(tiles, M.nets), dim3(256), forward_small_lds(M.H), st, M, M.X,
-                           into_reverse ? M.Or : M.Of);
+bool mlp_fused_forward(const MlpDev& M) { return forward_small_fits(M); }
+
+hipError_t mlp_forward_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
+    if (forward_small_fits(M)) {
+        hipLaunchKernelGGL(k_forward_small, dim3((M.Out + 255) / 256, M.nets), dim3(64 * kFwdWaves),
+                           forward_small_lds(M.In, M.H), st, M, P, sh, (int)kFwdCurrent, M.Of);
         return hipGetLastError();
     }
+    hipLaunchKernelGGL(k_feat_current, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : mlp_forward(M, 0, 0, st);
+}
+
+hipError_t mlp_forward_proposal(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float* O,
+                                hipStream_t st) {
+    if (forward_small_fits(M)) {
+        hipLaunchKernelGGL(k_forward_small, dim3((M.Out + 255) / 256, M.nets), dim3(64 * kFwdWaves),
+                           forward_small_lds(M.In, M.H), st, M, P, sh, (int)kFwdProposal, O);
+        return hipGetLastError();
+    }
+    return mlp_forward(M, 0, O == M.Or ? 1 : 0, st);  // features in M.X (written with the proposals)
+}
+
+hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st) {
     const int B = train ? M.Bt : M.Bm;
     const float* X = train ? M.tX : M.X;
     float* P1 = train ? M.tP1 : M.P1;
@@ -1205,7 +1443,7 @@ hipError_t mlp_sync_bf16(const MlpDev& M, hipStream_t st) {
 }
 
 hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_propose, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
+    hipLaunchKernelGGL(k_propose, dim3(M.Bm, M.nets), dim3(256), (size_t)M.Out * sizeof(float), st, M, P, sh, scale);
     return hipGetLastError();
 }
 
@@ -1225,20 +1463,21 @@ hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const Sha
 
 hipError_t mlp_propose_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_propose_subset, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
-    return hipGetLastError();
-}
-
-hipError_t mlp_energy_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st) {
     // threads per item grow with the list length (N = 256: 1024 threads, ~5 chunks each per list)
-    const int block = M.N >= 192 ? 1024 : (M.N >= 96 ? 512 : 256);
-    hipLaunchKernelGGL(k_energy_subset, dim3((unsigned)(M.Bm * M.nets)), dim3(block), (size_t)M.N * sizeof(float2), st,
-                       M, P, sh);
+    const size_t lds = (size_t)M.N * 2 * sizeof(float2) + (size_t)M.Out * sizeof(float);
+    const dim3 grid(M.Bm, M.nets);
+    if (M.N >= 192)
+        hipLaunchKernelGGL((k_propose_subset<1024, 4>), grid, dim3(1024), lds, st, M, P, sh, scale);
+    else if (M.N >= 96)
+        hipLaunchKernelGGL((k_propose_subset<512, 8>), grid, dim3(512), lds, st, M, P, sh, scale);
+    else
+        hipLaunchKernelGGL((k_propose_subset<256, 8>), grid, dim3(256), lds, st, M, P, sh, scale);
     return hipGetLastError();
 }
 
 hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_accept, dim3(M.Bm, M.nets), dim3(64), 0, st, M, P, sh, scale);
+    hipLaunchKernelGGL(k_accept, dim3(M.Bm, M.nets), dim3(kAcceptThreads), (size_t)M.Out * sizeof(float), st, M, P, sh,
+                       scale);
     return hipGetLastError();
 }
 

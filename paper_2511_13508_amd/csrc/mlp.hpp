@@ -29,7 +29,7 @@ struct MlpDev {
     float* master;   // [nets][NP]
     uint16_t* wbf;   // [nets][NP] bfloat16 copies
     uint16_t* wbt;   // [nets][NPt] bfloat16 weights in MFMA fragment order (see frag_at), zero padded
-    int64_t NPt;     // per net: In H + H H + H ceil(Out / 16) 16 elements (W1, W2, W3 with padded columns)
+    int64_t NPt;     // per net: In H + H H + H ceil(Out / 64) 64 elements (W1, W2, W3 with padded columns)
     float* grad;     // [nets][NP]
     float* am;       // Adam first moments
     float* av;       // Adam second moments
@@ -48,6 +48,7 @@ struct MlpDev {
     float* dE;       // [nets][Bm] energy change
     float* dEp;      // [nets][Bm][kEnergyParts] partial energy changes (term ranges)
     float* la;       // [nets][Bm] log acceptance ratio
+    double* lua;     // [nets][Bm] log of the uniform that decides the move (drawn with the proposal)
     int32_t* item_copy;  // [nets][Bm]
     int32_t* subset;     // [nets][Bm][kMaxSubset] the subset of the last move, ascending (subset move)
     // training
@@ -73,19 +74,27 @@ struct MlpDev {
 };
 
 // all launchers enqueue on st and cover every net in one launch (grid z = net)
-hipError_t mlp_features_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
 hipError_t mlp_features_train(const MlpDev& M, uint64_t seed, int64_t step, int use_first, hipStream_t st);
-// forward of every net: inference (train = 0, from M.X into Of or Or) or training (from tX into tO)
+// forward of every net through the GEMMs: inference (train = 0, from M.X into Of or Or) or training
+// (from tX into tO)
 hipError_t mlp_forward(const MlpDev& M, int train, int into_reverse, hipStream_t st);
+// true when inference forwards take the one-launch kernel (batch <= 16 rows, In and H multiples of 128)
+bool mlp_fused_forward(const MlpDev& M);
+// inference forward at the copies of every net's temperature slot into Of; also records item_copy and
+// starts the round (moves_done += 1)
+hipError_t mlp_forward_current(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
+// inference forward at the configurations in M.ap into O (Of or Or); the GEMM path reads their features
+// from M.X, which the proposal stage writes
+hipError_t mlp_forward_proposal(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float* O,
+                                hipStream_t st);
 hipError_t mlp_backward(const MlpDev& M, hipStream_t st);
 hipError_t mlp_adam(const MlpDev& M, float lr, int64_t t, hipStream_t st);
 hipError_t mlp_sync_bf16(const MlpDev& M, hipStream_t st);
 hipError_t mlp_propose(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
 hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
-// subset move: proposal, energy change from the subset's lists, acceptance
+// subset move: the proposal and its energy change from the subset's lists (one launch)
 hipError_t mlp_propose_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale,
                               hipStream_t st);
-hipError_t mlp_energy_subset(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, hipStream_t st);
 hipError_t mlp_accept(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, float scale, hipStream_t st);
 hipError_t mlp_harvest(const MlpDev& M, const DevPtrs<float>& P, const ShapeInfo& sh, int which, int slot0,
                        hipStream_t st);

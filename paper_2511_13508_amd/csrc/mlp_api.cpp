@@ -55,7 +55,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
         const size_t o = take(off, n * P * 2);
         m.wbf = base ? (uint16_t*)(base + o) : nullptr;
     }
-    m.NPt = ((int64_t)m.In * m.H + (int64_t)m.H * m.H + (int64_t)m.H * ((m.Out + 15) / 16 * 16) + 3) & ~(int64_t)3;
+    m.NPt = ((int64_t)m.In * m.H + (int64_t)m.H * m.H + (int64_t)m.H * ((m.Out + 63) / 64 * 64) + 7) & ~(int64_t)7;
     {
         const size_t o = take(off, n * (size_t)m.NPt * 2);
         m.wbt = base ? (uint16_t*)(base + o) : nullptr;
@@ -77,6 +77,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.dE = f(n * Bm);
     m.dEp = f(n * Bm * kEnergyParts);
     m.la = f(n * Bm);
+    m.lua = (double*)f(2 * n * Bm);
     m.item_copy = (int32_t*)f(n * Bm);
     m.subset = (int32_t*)f(n * Bm * kMaxSubset);
     m.tX = f(n * Bt * m.In);
@@ -167,16 +168,14 @@ int minibatch_loss(rlpt_ctx* c, std::vector<double>* loss, std::vector<int>* use
 int mlp_enqueue_round(rlpt_ctx* c) {
     const MlpDev& M = c->mlp;
     const float s = (float)c->mlp_scale;
-    HIP_TRY2(mlp_features_current(M, c->pf, c->sh, c->stream), "learned features");
-    HIP_TRY2(mlp_forward(M, 0, 0, c->stream), "learned forward");
+    HIP_TRY2(mlp_forward_current(M, c->pf, c->sh, c->stream), "learned forward");
     if (M.m > 0) {
         HIP_TRY2(mlp_propose_subset(M, c->pf, c->sh, s, c->stream), "learned propose");
-        HIP_TRY2(mlp_energy_subset(M, c->pf, c->sh, c->stream), "learned energy");
     } else {
         HIP_TRY2(mlp_propose(M, c->pf, c->sh, s, c->stream), "learned propose");
         HIP_TRY2(mlp_energy_change(M, c->pf, c->sh, c->stream), "learned energy");
     }
-    HIP_TRY2(mlp_forward(M, 0, 1, c->stream), "learned forward");
+    HIP_TRY2(mlp_forward_proposal(M, c->pf, c->sh, M.Or, c->stream), "learned forward");
     HIP_TRY2(mlp_accept(M, c->pf, c->sh, s, c->stream), "learned accept");
     if (c->sh.cached) HIP_TRY2(launch_fields_all(c->cfg.precision, c->ptrs(), c->sh, c->n_copies, c->stream), "fields");
     return RLPT_OK;
@@ -398,8 +397,8 @@ int rlpt_mlp_infer(rlpt_ctx* c, int32_t net, int32_t n, const double* states, do
     HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
     HIP_TRY2(hipMemcpy(M.ap + (size_t)net * M.Bm * 2 * M.N, buf.data(), buf.size() * 4, hipMemcpyHostToDevice),
              "upload states");
-    HIP_TRY2(mlp_features_from_proposals(M, net, n, c->stream), "features");
-    HIP_TRY2(mlp_forward(M, 0, 0, c->stream), "forward");
+    if (!mlp_fused_forward(M)) HIP_TRY2(mlp_features_from_proposals(M, net, n, c->stream), "features");
+    HIP_TRY2(mlp_forward_proposal(M, c->pf, c->sh, M.Of, c->stream), "forward");
     HIP_TRY2(hipStreamSynchronize(c->stream), "stream synchronize");
     std::vector<float> o((size_t)n * M.Out);
     HIP_TRY2(hipMemcpy(o.data(), M.Of + (size_t)net * M.Bm * M.Out, o.size() * 4, hipMemcpyDeviceToHost), "read");

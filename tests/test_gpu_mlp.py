@@ -325,22 +325,23 @@ def _infer_ctx(N, S, reps, H, K, batch, seed_graph=0):
                    temps=synth.geometric_temps(0.7, 0.9, T))
 
 
-@pytest.mark.parametrize("S,reps", [(8, 2), (12, 2)])
-def test_inference_forward_at_configured_size(S, reps):
-    """The learned-proposal configuration's network (N = 64: 128 -> 256 -> 256
-    -> 4-component mixture, 1020 outputs).  With samples x replicas = 16 the
-    inference forward is the one-launch fused kernel, otherwise three GEMMs:
-    outputs against the FP64 oracle on the same bfloat16 operands, and bitwise
-    against the training-path GEMMs on the same configurations; again after
-    new parameters are set and after an Adam step (the fragment-order weight
-    copy must follow both)."""
-    N, H, K = 64, 256, 4
+@pytest.mark.parametrize("N,S,reps", [(64, 8, 2), (64, 12, 2), (256, 2, 8)])
+def test_inference_forward_at_configured_size(N, S, reps):
+    """The learned-proposal configurations' networks (2N -> 256 -> 256 ->
+    4-component mixture: 1020 outputs at N = 64, 4092 at N = 256).  With
+    samples x replicas = 16 the inference forward is the one-launch fused
+    kernel (features formed in the kernel), otherwise the feature kernel and
+    three GEMMs: outputs against the FP64 oracle on the same bfloat16
+    operands, and bitwise against the training-path GEMMs on the same
+    configurations; again after new parameters are set and after an Adam step
+    (the fragment-order weight copy must follow both)."""
+    H, K = 256, 4
     Bm = S * reps
     ctx = _infer_ctx(N, S, reps, H, K, batch=Bm)
     ctx.init(2)
     ctx.mlp_setup([0, 1], seed=7)
     NP, Out = ctx.mlp_sizes()
-    assert Out == 1020
+    assert Out == K * (4 * N - 1)
     states = synth.random_constrained_state(N, 60, Bm)
     b32, a32 = _store_pairs(ctx, 1, states, synth.random_constrained_state(N, 61, Bm))
 
