@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 SEED_BASE = 2511135080 + 400  # disorder seed of sample mu: SEED_BASE + mu
 HBM_PEAK_GBS = 8000.0
+LDS_PEAK_GBS = 128 * 256 * 2.4  # 128 B per clock per CU, 256 CUs, 2.4 GHz
 METRIC = "mode-updates/s + τ_int-corrected sweeps/s (learned vs plain PT), N=256, 1 GPU"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_n256_traffic.json")
 BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_traffic.json")
@@ -678,6 +679,18 @@ def n64_protocol(args, rlpt, torch, out, cv_per_mode, sweeps=32768, ladder_sweep
         f"{r_ad.min():.2f}-{r_ad.max():.2f} (geometric {r_geo.min():.2f}-{r_geo.max():.2f})")
 
 
+def graph_sweeps(ctx, n, tag, piece=10000):
+    """n sweeps (a multiple of 100) in 100-sweep HIP-graph segments, a progress line after each piece"""
+    done = 0
+    while done < n:
+        k = min(piece, n - done)
+        ctx.run_graph(100, k // 100)
+        done += k
+        if n > piece:
+            ctx.check()
+            log(f"{tag}: {done}/{n} sweeps")
+
+
 def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweeps=20000, warm=2000,
                 harvest_rounds=6250, train_steps=1000, reeq=5000, at="peak", train=True):
     """The learned-proposal configuration: N = 64, 8 samples x 24 temperatures
@@ -726,7 +739,7 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         ctx.sweep(start - ctx.counters()[0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.run_graph(100, sweeps // 100)  # 100-sweep segments replayed as HIP graphs
+        graph_sweeps(ctx, sweeps, "learned N=64: measured")  # 100-sweep segments replayed as HIP graphs
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ctx.check()
@@ -742,7 +755,7 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
                            resync_interval=100, measure_start=warm, measure_interval=1, n_bins=100)
         ctx.init(3)
         ctx.run_graph(100, warm // 100)
-        ctx.run_graph(100, sweeps // 100)
+        graph_sweeps(ctx, sweeps, "learned N=64: C_V peak run")
         ctx.check()
         cv = rlpt.summarize(ctx.observables(), N, temps)["cv"]
         ctx.close()
@@ -913,6 +926,11 @@ def main():
     ap.add_argument("--learn-temps", type=lambda v: [int(x) for x in v.split(",")] if v else [],
                     default=[25, 26, 27, 28], help="temperature indices with learned global moves")
     ap.add_argument("--learn-scale", type=float, default=0.05)
+    ap.add_argument("--learn-rounds", type=int, default=1, help="all-mode learned rounds per sweep at N=256")
+    ap.add_argument("--untrained", action="store_true",
+                    help="N=256 learned runs with untrained networks (no harvest, no training)")
+    ap.add_argument("--only-learned-all-256", action="store_true",
+                    help="n256 workload: only the plain tau run and the all-mode learned comparison")
     ap.add_argument("--subset-frac", type=int, default=8, help="subset move: m = N / subset_frac modes per move")
     ap.add_argument("--subset-scale", type=float, default=0.5, help="subset move: step scale")
     ap.add_argument("--subset-rounds", type=int, default=1, help="subset move: learned rounds per sweep at N=256")
@@ -940,7 +958,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales the rocprofv3 byte counters)")
     args = ap.parse_args()
-    if args.only_learned_256:
+    if args.only_learned_256 or args.only_learned_all_256:
         args.no_cached = args.no_n64 = args.no_batched = args.no_cpu_baseline = True
     args.sweeps = args.steps * args.sweeps_per_step
     args.warm_sweeps = args.warmup * args.sweeps_per_step
@@ -1143,11 +1161,21 @@ def main():
                              "replicas, same window", "estimator": "Sokal window c=6, per disorder sample",
                "plain": tau_plain}
         # ------------------------------------------------------------ shared pair schedule
-        if not args.shared_pairs and not args.only_learned_256:
+        if not args.shared_pairs and not args.only_learned_256 and not args.only_learned_all_256:
             ctx = rlpt.Context(graphs, temps, shared_pairs=1, **common)
-            el2, _, _ = timed(ctx, "shared pairs")
+            el2, kms2, launches2 = timed(ctx, "shared pairs")
             tau["shared_pairs"], tE2, _ = tau_block(ctx, args.sweeps / el2, t_learn, args.tau_sweeps, "shared pairs")
             tau["shared_pairs"]["mode_updates_per_s"] = N * n_copies * args.sweeps / el2
+            if chunked:
+                # the copies of a sample share their lists through L2, so the binding roof is the LDS
+                # gathers: per chunk of 4 entries one partner and 8 pair amplitudes, 9 x 8 B = 18 B per
+                # entry; LDS peak = 128 B per clock per CU x 256 CUs x 2.4 GHz
+                t2 = kms2 / launches2 * 1e-3
+                lds_gbs = entries_per_launch * 18.0 / t2 / 1e9
+                tau["shared_pairs"]["roofline"] = {
+                    "bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                    "frac": lds_gbs / LDS_PEAK_GBS, "bytes_per_entry": 18.0, "ms_per_launch": kms2 / launches2,
+                    "list_GBps_algorithmic": entries_per_launch * per_entry / t2 / 1e9}
             tau["shared_vs_plain_eff"] = eff_ratio(tE2, tau_plain_E, args.sweeps / el2, sweeps_per_s)
             ctx.close()
         # ------------------------------------------------------------ learned global moves
@@ -1159,21 +1187,23 @@ def main():
             ctx.init(1)
             ctx.sweep(args.warm_sweeps)
             ctx.mlp_setup(t_learn, seed=1)
-            log(f"{tag}: harvest and train")
             t0 = time.perf_counter()
-            ctx.mlp_harvest(rounds=args.harvest_rounds, lag=2)
             losses, train_error = [], None
-            try:
-                losses.append(ctx.mlp_train(1, 1e-3))
-                losses.append(ctx.mlp_train(args.train_steps, 1e-3))
-            except rlpt.RlptError as e:
-                train_error = str(e)
-                log(f"{tag}: training failed: {e}")
+            if not args.untrained:
+                log(f"{tag}: harvest and train")
+                ctx.mlp_harvest(rounds=args.harvest_rounds, lag=2)
+                try:
+                    losses.append(ctx.mlp_train(1, 1e-3))
+                    losses.append(ctx.mlp_train(args.train_steps, 1e-3))
+                except rlpt.RlptError as e:
+                    train_error = str(e)
+                    log(f"{tag}: training failed: {e}")
             t_train = time.perf_counter() - t0
             if train_error is None:
                 ctx.mlp_enable(rounds, scale)
             # the harvest ran without swaps: re-equilibrate with swaps and learned rounds before the window
-            ctx.sweep(args.reeq)
+            if not args.untrained:
+                ctx.sweep(args.reeq)
             done = ctx.counters()[0]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -1195,7 +1225,9 @@ def main():
             dead = dead_networks(acc_rate, np.array(losses) if losses else None)
             if train_error:
                 dead.append({"network": "all", "failed": train_error})
-            res = {"move": f"subset of {subset} modes" if subset else "all modes", "temperatures":
+            res = {"move": f"subset of {subset} modes" if subset else "all modes",
+                   "networks": "untrained (outputs near 0: an isotropic small-step mixture)" if args.untrained
+                   else "trained on harvested pairs", "temperatures":
                    [float(temps[t]) for t in t_learn], "tau_int_E": tau_stats(tEl), "tau_int_q": tau_stats(tql),
                    "sweeps_per_s": sps3, "series_points": m - lo, "move_acceptance": acc_rate.round(4).tolist(),
                    "step_scale": scale, "rounds_per_sweep": rounds,
@@ -1212,8 +1244,9 @@ def main():
             return res, ratio
 
         if t_learn and not args.only_learned_256:
-            tau["learned"], tau["learned_vs_plain_eff"] = learned_256(0, args.learn_scale, "learned")
-        if t_learn:
+            tau["learned"], tau["learned_vs_plain_eff"] = learned_256(0, args.learn_scale, "learned",
+                                                                      args.learn_rounds)
+        if t_learn and not args.only_learned_all_256:
             m_sub = max(2, N // args.subset_frac)
             tau["learned_subset"], tau["learned_subset_vs_plain_eff"] = learned_256(m_sub, args.subset_scale,
                                                                                    "learned subset",
