@@ -1156,6 +1156,11 @@ def main():
         rlpt.tune_clear()  # the autotuner's registry would otherwise choose the later contexts' tiles
     if args.tau_sweeps > 0 and args.learn_temps and not args.no_n64:
         learned_n64(args, rlpt, torch, out)
+        # the same comparison at the four coldest temperatures with untrained networks (isotropic small
+        # steps), over 10^5 measured sweeps: where the pair moves freeze, global chart moves pay
+        cold = {}
+        learned_n64(args, rlpt, torch, cold, sweeps=100000, at="cold", train=False)
+        out["learned_n64_cold_untrained"] = cold["learned_n64"]
     if args.tau_sweeps > 0:
         tau = {"observable": "E (energy of ladder 0 at each temperature); tau_int_q: overlap q of the two "
                              "replicas, same window", "estimator": "Sokal window c=6, per disorder sample",
