@@ -735,7 +735,7 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
                 info = {"train_error": str(e)}
                 log(f"learned N=64: training failed: {e}")
         if learned and "train_error" not in info:
-            ctx.mlp_enable(1, scale)
+            ctx.mlp_enable(args.n64_rounds, scale)
         ctx.sweep(start - ctx.counters()[0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -819,7 +819,8 @@ def learned_n64(args, rlpt, torch, out, N=64, S=8, T=24, reps=2, n_nets=4, sweep
         rE["status"] = rq["status"] = ["failed: " + info["train_error"]] * len(t_learn)
     out["learned_n64"] = {
         "config": f"N={N}, {S} samples x {T} temperatures [0.3, 1.5] x {reps} replicas, FP32; learned rounds "
-                  f"(1 per sweep, step scale {args.learn_scale}, {'trained' if train else 'untrained'} networks) at "
+                  f"({args.n64_rounds} per sweep, step scale {args.learn_scale}, {'trained' if train else 'untrained'} "
+                  f"networks) at "
                   f"the {len(t_learn)} {'coldest temperatures' if at == 'cold' else 'temperatures around the C_V peak'}"
                   f"; both runs: {warm} warm-up, {harvest_rounds * 2} harvest (no swaps), {reeq} more sweeps, "
                   f"then {sweeps} measured sweeps",
@@ -953,6 +954,7 @@ def main():
                     help="learned64 workload: networks around the C_V peak or on the four coldest temperatures")
     ap.add_argument("--n64-untrained", action="store_true",
                     help="learned64 workload: learned rounds with untrained networks")
+    ap.add_argument("--n64-rounds", type=int, default=1, help="N=64 learned comparison: learned rounds per sweep")
     ap.add_argument("--batched-launches-only", action="store_true",
                     help="batched workload: only 20 sweeps of the mixed launch with built-in tiles (for counters)")
     ap.add_argument("--copy-calibration", action="store_true",

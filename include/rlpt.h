@@ -432,8 +432,10 @@ int rlpt_mlp_train(rlpt_ctx* ctx, int32_t steps, double lr, double* mean_loss);
 int rlpt_mlp_forward(rlpt_ctx* ctx, int32_t net, int32_t n, double* out);
 int rlpt_mlp_loss_grad(rlpt_ctx* ctx, int32_t net, double* loss, float* grad);
 /* Test hook: the inference forward that learned rounds run (one fused launch
- * when samples x replicas <= 16 and 2N, mlp_hidden are multiples of 128, the
- * three GEMMs otherwise) of network `net` on n <= samples x replicas caller
+ * that also forms the features when samples x replicas <= 16, 2N and
+ * mlp_hidden are multiples of 128 and the outputs fit 16 tiles of 256 columns;
+ * the feature kernel and three GEMMs otherwise) of network `net` on
+ * n <= samples x replicas caller
  * configurations states[n][N] (interleaved complex doubles, converted to
  * FP32); out[n][outputs].  Uses the network's inference buffers (outputs at
  * the current configurations of the last learned round are overwritten).
