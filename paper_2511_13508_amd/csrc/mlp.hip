@@ -319,7 +319,6 @@ __global__ __launch_bounds__(1024) void k_forward_small(MlpDev M, DevPtrs<float>
     // features: their loads are in flight while the features are formed
     bf16x8 w1[kFwdPairs / 2];
     if (16 * wave < H) fwd_load<kFwdPairs / 2>(WF, 0, In, wave, 0, lane, w1);
-    asm volatile("" ::: "memory");  // keep the loads ahead of the feature loop
     // the input tile: features of each row's configuration rounded to bfloat16, zero rows beyond the batch
     const int slot = M.temp_index[net];
     for (int i = threadIdx.x; i < kFwdRows * N; i += blockDim.x) {
