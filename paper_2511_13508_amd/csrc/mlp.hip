@@ -915,7 +915,7 @@ __global__ __launch_bounds__(256) void k_propose(MlpDev M, DevPtrs<float> P, Sha
 // one sample (every network's temperature x replicas) share that sample's
 // list: a workgroup holds up to kEnergyItems of them (current and proposed
 // amplitudes in LDS) and streams a contiguous range of terms once for all of
-// them; kEnergyParts workgroups per item group fill the chip, and the parts
+// them; M.eparts workgroups per item group fill the chip, and the parts
 // are added in a fixed order by the accept stage.
 constexpr int kEnergyItems = 8;
 
@@ -924,9 +924,10 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
     extern __shared__ float2 samp[];  // [ni][2][N]: current, proposed
     __shared__ float red[4][kEnergyItems];
     const int N = M.N;
-    const int part = blockIdx.x % kEnergyParts;
-    const int grp = (blockIdx.x / kEnergyParts) % groups;
-    const int mu = blockIdx.x / (kEnergyParts * groups);
+    const int parts = M.eparts;
+    const int part = blockIdx.x % parts;
+    const int grp = (blockIdx.x / parts) % groups;
+    const int mu = blockIdx.x / (parts * groups);
     const int per_sample = M.nets * sh.n_reps;
     const int j0 = grp * gsize;
     const int ni = per_sample - j0 < gsize ? per_sample - j0 : gsize;
@@ -949,7 +950,7 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
     const SampleDev sd = P.samples[mu];
     const ushort4* Q = P.quads + sd.quad_base;
     const double* Jq = P.Jq + sd.quad_base;
-    const int64_t q0 = sd.n_quads * part / kEnergyParts, q1 = sd.n_quads * (part + 1) / kEnergyParts;
+    const int64_t q0 = sd.n_quads * part / parts, q1 = sd.n_quads * (part + 1) / parts;
     float acc[kEnergyItems];
 #pragma unroll
     for (int i = 0; i < kEnergyItems; ++i) acc[i] = 0.0f;
@@ -981,7 +982,7 @@ __global__ __launch_bounds__(256) void k_energy_change(MlpDev M, DevPtrs<float> 
     __syncthreads();
     if (threadIdx.x < ni) {
         const int i = threadIdx.x;
-        M.dEp[item_of(i) * kEnergyParts + part] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        M.dEp[item_of(i) * kMaxEnergyParts + part] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
     }
 }
 
@@ -1255,6 +1256,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_subset(MlpDev M, DevPtrs<floa
 // acceptance.  The reverse log density's components are summed on the four
 // waves; the uniform that decides was drawn with the proposal.
 constexpr int kAcceptThreads = 256;
+static_assert(kAcceptThreads >= kMaxEnergyParts, "one energy part per accept thread");
 constexpr int kApPerThread = kMaxModes / kAcceptThreads;  // floats of the proposal row per thread (2N <= kMaxModes)
 
 __global__ __launch_bounds__(kAcceptThreads) void k_accept(MlpDev M, DevPtrs<float> P, ShapeInfo sh, float scale) {
@@ -1271,7 +1273,9 @@ __global__ __launch_bounds__(kAcceptThreads) void k_accept(MlpDev M, DevPtrs<flo
     const int slot = M.temp_index[net];
     const float dref = M.dref[item], lqf = M.lqf[item];
     const double lua = M.lua[item];
-    float dE = m > 0 ? M.dE[item] : 0.0f;
+    __shared__ float s_part[kAcceptThreads / 64];
+    // the all-mode move's energy change: its term-range parts, one per thread, summed in a fixed order
+    float dE = m > 0 ? M.dE[item] : (tid < M.eparts ? M.dEp[item * kMaxEnergyParts + tid] : 0.0f);
     const int nd = m > 0 ? 2 * m - 1 : D;
     for (int d = tid; d < nd; d += kAcceptThreads) sdel[d] = M.delta[item * D + d];
     for (int i = tid; i < m; i += kAcceptThreads) S[i] = M.subset[item * kMaxSubset + i];
@@ -1281,11 +1285,17 @@ __global__ __launch_bounds__(kAcceptThreads) void k_accept(MlpDev M, DevPtrs<flo
 #pragma unroll
     for (int r = 0; r < kApPerThread; ++r)
         if (tid + kAcceptThreads * r < 2 * N) apv[r] = ap[tid + kAcceptThreads * r];
-    if (m == 0)
-        for (int p = 0; p < kEnergyParts; ++p) dE += M.dEp[item * kEnergyParts + p];  // the parts, added in order
     const float beta = P.beta[slot];
     const float E0 = P.E[c];
+    if (m == 0) {
+        dE = wsum(dE);
+        if (lane == 0) s_part[wave] = dE;
+    }
     __syncthreads();
+    if (m == 0) {
+        dE = 0.0f;
+        for (int w = 0; w < kAcceptThreads / 64; ++w) dE += s_part[w];
+    }
     const float mlse = mix_lse(sO, K);
     const float lqr =
         m > 0 ? log_mix_block(
@@ -1455,7 +1465,7 @@ hipError_t mlp_energy_change(const MlpDev& M, const DevPtrs<float>& P, const Sha
     const int groups = (per_sample + gsize - 1) / gsize;
     const int samples = M.Bm / sh.n_reps;
     const size_t lds = (size_t)gsize * 2 * M.N * sizeof(float2);
-    hipLaunchKernelGGL(k_energy_change, dim3((unsigned)(samples * groups * kEnergyParts)), dim3(256), lds, st, M, P,
+    hipLaunchKernelGGL(k_energy_change, dim3((unsigned)(samples * groups * M.eparts)), dim3(256), lds, st, M, P,
                        sh, groups, gsize);
     return hipGetLastError();
 }

@@ -15,7 +15,7 @@
 
 namespace rlpt {
 
-constexpr int kEnergyParts = 32;  // workgroups sharing one learned move's energy change
+constexpr int kMaxEnergyParts = 128;  // most workgroups sharing one learned move's energy change
 constexpr int kMaxSubset = 64;    // largest subset of the subset move
 
 struct MlpDev {
@@ -23,6 +23,7 @@ struct MlpDev {
     int32_t Bm;      // inference items per net (samples x replicas)
     int32_t m;       // subset move: modes per move (0: the all-mode move)
     int32_t Bt;      // training minibatch
+    int32_t eparts;  // workgroups (term ranges) per item group of the all-mode energy change
     int32_t cap;     // stored training pairs per net
     int64_t NP;      // parameters per net
     int64_t oW1, ob1, oW2, ob2, oW3, ob3;  // offsets inside a parameter vector
@@ -46,7 +47,7 @@ struct MlpDev {
     float* lqf;      // [nets][Bm] forward log density
     float* dref;     // [nets][Bm] log reference-density ratio
     float* dE;       // [nets][Bm] energy change
-    float* dEp;      // [nets][Bm][kEnergyParts] partial energy changes (term ranges)
+    float* dEp;      // [nets][Bm][kMaxEnergyParts] partial energy changes (term ranges)
     float* la;       // [nets][Bm] log acceptance ratio
     double* lua;     // [nets][Bm] log of the uniform that decides the move (drawn with the proposal)
     int32_t* item_copy;  // [nets][Bm]

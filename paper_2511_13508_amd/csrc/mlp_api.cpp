@@ -40,6 +40,9 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.Bm = S * cfg.n_reps;
     m.m = cfg.mlp_subset;
     m.Bt = cfg.mlp_batch;
+    // term ranges per item group: enough workgroups to fill the chip several times over at N = 256
+    // (each streams its range once for the group's items), fewer where the lists are short
+    m.eparts = N >= 192 ? kMaxEnergyParts : 32;
     m.cap = cfg.mlp_capacity;
     m.oW1 = 0;
     m.ob1 = m.oW1 + (int64_t)m.In * m.H;
@@ -75,7 +78,7 @@ size_t mlp_layout(const rlpt_config& cfg, int N, int S, MlpDev* M, unsigned char
     m.lqf = f(n * Bm);
     m.dref = f(n * Bm);
     m.dE = f(n * Bm);
-    m.dEp = f(n * Bm * kEnergyParts);
+    m.dEp = f(n * Bm * kMaxEnergyParts);
     m.la = f(n * Bm);
     m.lua = (double*)f(2 * n * Bm);
     m.item_copy = (int32_t*)f(n * Bm);
