@@ -398,12 +398,14 @@ def test_gradients_at_configured_size(N):
         assert np.dot(x, y) / (np.linalg.norm(x) * np.linalg.norm(y)) >= 0.999, k
 
 
-def test_learned_move_matches_oracle_at_configured_size(oracle):
-    """A learned round of the N = 64 configuration's networks (H = 256, K = 4;
-    8 samples x 2 replicas = 16 items: the fused inference forward) against
-    the oracle on the same draws: proposals, log acceptance ratios and the
-    decisions taken away from the boundary."""
-    N, S, T, reps, H, K = 64, 8, 4, 2, 256, 4
+@pytest.mark.parametrize("N,S,T,reps", [(64, 8, 4, 2), (256, 2, 4, 8)])
+def test_learned_move_matches_oracle_at_configured_size(oracle, N, S, T, reps):
+    """A learned round of the configured networks (H = 256, K = 4; samples x
+    replicas = 16 items: the fused inference forward; at N = 256 the energy
+    change runs over 128 term slices per sample) against the oracle on the
+    same draws: proposals, log acceptance ratios and the decisions taken away
+    from the boundary."""
+    H, K = 256, 4
     temps = synth.geometric_temps(0.7, 1.0, T)
     graphs = [rlpt.Graph(N, SEED3 + 400 + i) for i in range(S)]
     ctx = mlp_ctx(N, S, T, reps, H, K, batch=16, nets=2, graphs=graphs, temps=temps)
