@@ -12,14 +12,18 @@ resident in HBM when timing starts.
 
 Prints one JSON line.  ``value`` = mode-updates/s (N mode-updates per copy
 per sweep) over the timed steps.  ``roofline`` describes the sweep kernel:
-algorithmic bytes per launch (every list entry a step streams: 6.25 B in
-the chunked layout, 25 B per chunk of 4 entries sharing their partner mode;
-8 B in the packed one) over its mean duration measured with HIP events on
-the context's stream, against the measured ceiling of the memory hierarchy
-for the same list stream (rlpt_stream_lists: the sweep's grid and reads with
-no arithmetic), beside the published 8 TB/s HBM peak.  ``cpu_baseline``
-times the CPU FP64 oracle on a bounded slice of the same workload (sample 0,
-all 80 copies, whole sweeps for ~10 s).
+``achieved`` = algorithmic bytes per launch (every list entry a step
+streams: 6.25 B in the chunked layout, 25 B per chunk of 4 entries sharing
+their partner mode; 8 B in the packed one) over its mean duration measured
+with HIP events on the context's stream; ``traffic`` = the fabric bytes per
+launch from the committed rocprofv3 counters of this kernel source;
+``frac`` = traffic per second over the published 8 TB/s HBM peak, and
+``peak`` = that peak scaled by algorithmic / fabric bytes, so that
+achieved / peak = frac (fabric bytes include Infinity-Cache hits: the HBM
+share is at most frac).  The list-stream probe (rlpt_stream_lists: the
+sweep's grid and reads with no arithmetic) is timed beside it.
+``cpu_baseline`` times the CPU FP64 oracle on a bounded slice of the same
+workload (sample 0, all 80 copies, whole sweeps for ~10 s).
 """
 from __future__ import annotations
 
