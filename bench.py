@@ -932,6 +932,7 @@ def main():
                     default=[25, 26, 27, 28], help="temperature indices with learned global moves")
     ap.add_argument("--learn-scale", type=float, default=0.05)
     ap.add_argument("--learn-rounds", type=int, default=1, help="all-mode learned rounds per sweep at N=256")
+    ap.add_argument("--run-seed", type=int, default=1, help="N=256 runs: the seed of the initial draw and the moves")
     ap.add_argument("--untrained", action="store_true",
                     help="N=256 learned runs with untrained networks (no harvest, no training)")
     ap.add_argument("--only-learned-all-256", action="store_true",
@@ -1015,7 +1016,7 @@ def main():
 
     def timed(ctx, tag):
         """warm-up, then the timed steps with sweep-kernel events; returns (s, kernel ms, launches)"""
-        ctx.init(1)
+        ctx.init(args.run_seed)
         log(f"{tag}: warmup {args.warmup} steps ({args.warm_sweeps} sweeps)")
         ctx.sweep(args.warm_sweeps)
         ctx.check()
@@ -1195,7 +1196,7 @@ def main():
             ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, mlp_nets=len(t_learn),
                                mlp_hidden=256, mlp_components=4, mlp_capacity=8192, mlp_batch=512,
                                mlp_subset=subset, **lcommon)
-            ctx.init(1)
+            ctx.init(args.run_seed)
             ctx.sweep(args.warm_sweeps)
             ctx.mlp_setup(t_learn, seed=1)
             t0 = time.perf_counter()
