@@ -12,7 +12,9 @@ z-score of the mean over samples of the paired difference (both runs see the
 same disorder; jackknife error over samples), the fraction of cells within
 2 sigma, the largest z, and sum z^2 beside its expectation (S - 1)/(S - 3) per
 cell for a t law with S - 1 degrees of freedom (cells at neighbouring
-temperatures are correlated through the swaps, so this is a rough check).
+temperatures are correlated through the swaps, so this is a rough check),
+and the collected tests' t-law rule (count within 2 sigma, mean z^2, largest
+z against their thresholds).
 It also times the oracle: the whole run of the N = 64 configuration, and the
 N = 16 FP64 configuration (1 sample x 8 temperatures x 2 replicas, 2000
 sweeps) in full.
@@ -34,7 +36,7 @@ if ROOT not in sys.path:
 
 from oracle import oracle as O  # noqa: E402
 from paper_2511_13508_amd import rlpt  # noqa: E402
-from tests.test_gpu_parity import jackknife, oracle_stack, per_sample_obs  # noqa: E402
+from tests.test_gpu_parity import jackknife, oracle_stack, per_sample_obs, same_law_report  # noqa: E402
 
 N, S, T, REPS = 64, 8, 24, 2
 SEED = 2511135080 + 500  # disorder seed of sample mu in the N = 64 configuration: SEED + mu
@@ -97,7 +99,11 @@ def main():
                                  "mode_updates_per_s": S * T * REPS * N * sweeps / o_sec,
                                  "n16_fp64_full_run_seconds": o16_sec},
                       "gpu_vs_oracle": summary(z_scores(g1, o), temps),
-                      "gpu_vs_gpu_other_seed": summary(z_scores(g1, g2), temps)}), flush=True)
+                      "gpu_vs_gpu_other_seed": summary(z_scores(g1, g2), temps),
+                      "t_law_rule": {name: {k: v for k, v in same_law_report(a, b, ("E", "C_V", "q2", "Y2")).items()
+                                            if k != "z"}
+                                     for name, (a, b) in (("gpu_vs_oracle", (g1, o)), ("gpu_vs_gpu", (g1, g2)))}}),
+          flush=True)
 
 
 if __name__ == "__main__":
