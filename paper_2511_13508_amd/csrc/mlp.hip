@@ -574,6 +574,7 @@ __device__ inline float log_coord(float x, float mu, float sg, bool phase) {
 struct Lse {
     float best = -INFINITY, s = 0.0f;
     __device__ void add(float t) {
+        if (t == -INFINITY) return;  // a component of zero density adds nothing (all of them: the value is -inf)
         if (t > best) {
             s = s * expf(best - t) + 1.0f;
             best = t;
