@@ -883,6 +883,32 @@ def eff_ratio(tau_a, tau_b, sps_a, sps_b):
                                         "band = exp(+-1 standard error)"}
 
 
+def window_means(o, t_idx, lo, m):
+    """per-sample means over the series window [lo, m) at the temperature
+    indices t_idx, arrays [len(t_idx)][samples]: E, q^2, and E over the
+    window's first and second halves (a drift between them means the run is
+    still relaxing)"""
+    e = o["series_e"][:, t_idx, lo:m].astype(np.float64)
+    q = o["series_q"][:, t_idx, lo:m].astype(np.float64)
+    h = (m - lo) // 2
+    return {"E": e.mean(axis=2).T, "q2": (q * q).mean(axis=2).T, "E_first": e[:, :, :h].mean(axis=2).T,
+            "E_second": e[:, :, h:].mean(axis=2).T}
+
+
+def paired_agreement(a, b):
+    """a - b per temperature (rows), paired by disorder sample (columns): the
+    mean difference, its jackknife error over the samples (for a mean, the
+    standard error), z = |mean| / error and the fraction of rows with z <= 2"""
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    n = d.shape[1]
+    loo = (d.sum(axis=1, keepdims=True) - d) / (n - 1)
+    err = np.sqrt((n - 1) / n * ((loo - loo.mean(axis=1, keepdims=True)) ** 2).sum(axis=1))
+    mean = d.mean(axis=1)
+    z = np.abs(mean) / np.maximum(err, 1e-300)
+    return {"diff": np.round(mean, 4).tolist(), "err": np.round(err, 4).tolist(), "z": np.round(z, 2).tolist(),
+            "within_2sigma": float(np.mean(z <= 2))}
+
+
 def dead_networks(acceptance, losses):
     """Networks that accepted no learned move or trained to a non-finite loss"""
     bad = []
@@ -1047,7 +1073,8 @@ def main():
     def tau_block(ctx, sweeps_per_s, t_idx, extra_sweeps, tag):
         """continue extra_sweeps sweeps, then tau_int of E and q at the
         temperature indices t_idx from the series (first quarter discarded),
-        per sample; returns (summary, tau_E per sample, tau_q per sample)"""
+        per sample; returns (summary, tau_E per sample, the window means of
+        E and q^2 per sample)"""
         if extra_sweeps > 0:
             long_run(ctx, extra_sweeps, tag)
         o = ctx.observables()
@@ -1059,7 +1086,7 @@ def main():
         return ({"temperatures": [float(temps[t]) for t in t_idx], "tau_int_E": tau_stats(tE),
                  "tau_int_q": tau_stats(tq), "sweeps_per_s": sweeps_per_s,
                  "eff_sweeps_per_s_E": (sweeps_per_s / (2 * np.median(tE, axis=1))).round(3).tolist(),
-                 "series_points": m - lo}, tE, tq)
+                 "series_points": m - lo}, tE, window_means(o, t_idx, lo, m))
 
     # ---------------------------------------------------------------- headline: per-copy pairs
     ctx = rlpt.Context(graphs, temps, shared_pairs=args.shared_pairs, **common)
@@ -1120,10 +1147,10 @@ def main():
         roof.update({"peak": HBM_PEAK_GBS, "frac": achieved / HBM_PEAK_GBS, "peak_kind": "published HBM peak"})
     sweeps_per_s = args.sweeps / el
     t_learn = [t for t in args.learn_temps if t < T]
-    tau_plain = tau_plain_E = None
+    tau_plain = tau_plain_E = tau_plain_w = None
     if args.tau_sweeps > 0:
         log(f"plain: {args.tau_sweeps} more sweeps for tau_int")
-        tau_plain, tau_plain_E, _ = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps, "plain")
+        tau_plain, tau_plain_E, tau_plain_w = tau_block(ctx, sweeps_per_s, t_learn, args.tau_sweeps, "plain")
     out = {
         "metric": METRIC,
         "value": value,
@@ -1231,6 +1258,7 @@ def main():
             lo = max(done - args.warm_sweeps, 0) + (m - max(done - args.warm_sweeps, 0)) // 4
             tEl = tau_per_sample(o["series_e"], t_learn, lo, m)
             tql = tau_per_sample(o["series_q"], t_learn, lo, m)
+            wl = window_means(o, t_learn, lo, m)
             acc, tries = ctx.mlp_stats()
             acc_rate = acc / np.maximum(tries, 1)
             sps3 = args.sweeps / el3
@@ -1244,7 +1272,14 @@ def main():
                    "sweeps_per_s": sps3, "series_points": m - lo, "move_acceptance": acc_rate.round(4).tolist(),
                    "step_scale": scale, "rounds_per_sweep": rounds,
                    "train_loss_first_last": [np.round(x, 2).tolist() for x in losses],
-                   "harvest_and_train_s": t_train, "failed_networks": dead}
+                   "harvest_and_train_s": t_train, "failed_networks": dead,
+                   "agreement_with_plain": {
+                       "E": paired_agreement(wl["E"], tau_plain_w["E"]),
+                       "q2": paired_agreement(wl["q2"], tau_plain_w["q2"]),
+                       "E_drift_plain": paired_agreement(tau_plain_w["E_second"], tau_plain_w["E_first"]),
+                       "E_drift_learned": paired_agreement(wl["E_second"], wl["E_first"]),
+                       "test": "window means of E and of q^2 per sample, learned - plain, paired jackknife over "
+                               "the disorder samples; E_drift: second half of a run's window - first half"}}
             ctx.close()
             ratio = eff_ratio(tEl, tau_plain_E, sps3, sweeps_per_s)
             for d in dead:
@@ -1252,7 +1287,11 @@ def main():
                     ratio["status"][d["network"]] = "failed: " + d["failed"]
                 else:
                     ratio["status"] = ["failed: " + d["failed"]] * len(ratio["status"])
-            log(f"{tag}: eff ratio {ratio['ratio']} {ratio['status']}")
+            log(f"{tag}: eff ratio {ratio['ratio']} {ratio['status']}; E within 2 sigma of plain "
+                f"{res['agreement_with_plain']['E']['within_2sigma']:.2f}, q^2 "
+                f"{res['agreement_with_plain']['q2']['within_2sigma']:.2f}; E drift over the window plain "
+                f"{res['agreement_with_plain']['E_drift_plain']['diff']}, learned "
+                f"{res['agreement_with_plain']['E_drift_learned']['diff']}")
             return res, ratio
 
         if t_learn and not args.only_learned_256:

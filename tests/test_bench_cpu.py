@@ -47,3 +47,43 @@ def test_dead_networks_flags_no_acceptance_and_nonfinite_losses():
     assert bad == [{"network": 1, "failed": "accepted no learned move"},
                    {"network": 2, "failed": "non-finite training loss"}]
     assert bench.dead_networks([0.1, 0.2], None) == []
+
+
+def test_paired_agreement_error_is_the_standard_error_of_the_paired_mean():
+    """the jackknife error of a mean over samples equals its standard error"""
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=(4, 8))
+    a = b + rng.normal(0.3, 1.0, size=(4, 8))
+    r = bench.paired_agreement(a, b)
+    d = a - b
+    np.testing.assert_allclose(r["diff"], d.mean(axis=1), atol=1e-4)
+    np.testing.assert_allclose(r["err"], d.std(axis=1, ddof=1) / np.sqrt(8), atol=1e-4)
+    z = np.abs(d.mean(axis=1)) / (d.std(axis=1, ddof=1) / np.sqrt(8))
+    np.testing.assert_allclose(r["z"], z, atol=1e-2)
+    assert r["within_2sigma"] == pytest.approx(np.mean(z <= 2))
+
+
+def test_paired_agreement_sees_a_shift_that_the_sample_spread_hides():
+    """pairing removes what the runs share: a small shift common to all samples
+    stands out although the samples themselves differ far more"""
+    rng = np.random.default_rng(6)
+    b = rng.normal(0.0, 10.0, size=(3, 8))
+    r0 = bench.paired_agreement(b + rng.normal(0.0, 0.01, size=(3, 8)), b)
+    r1 = bench.paired_agreement(b + 0.1 + rng.normal(0.0, 0.01, size=(3, 8)), b)
+    assert r0["within_2sigma"] == 1.0
+    assert r1["within_2sigma"] == 0.0
+
+
+def test_window_means_are_per_sample_means_over_the_window():
+    rng = np.random.default_rng(7)
+    o = {"series_e": rng.normal(size=(8, 6, 50)).astype(np.float32),
+         "series_q": rng.uniform(-1, 1, size=(8, 6, 50)).astype(np.float32)}
+    w = bench.window_means(o, [1, 4], 10, 40)
+    assert w["E"].shape == w["q2"].shape == w["E_first"].shape == w["E_second"].shape == (2, 8)
+    for i, t in enumerate([1, 4]):
+        for mu in range(8):
+            e = o["series_e"][mu, t].astype(np.float64)
+            assert w["E"][i, mu] == pytest.approx(float(np.mean(e[10:40])))
+            assert w["E_first"][i, mu] == pytest.approx(float(np.mean(e[10:25])))
+            assert w["E_second"][i, mu] == pytest.approx(float(np.mean(e[25:40])))
+            assert w["q2"][i, mu] == pytest.approx(float(np.mean(o["series_q"][mu, t, 10:40].astype(np.float64) ** 2)))
