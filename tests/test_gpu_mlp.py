@@ -507,6 +507,68 @@ def test_subset_move_matches_oracle(oracle, N, S, T, reps, H, K, m, layout):
     assert np.all(tries == S * reps)
 
 
+@pytest.mark.parametrize("m", [0, 64])
+def test_learned_moves_at_the_largest_sizes(oracle, m):
+    """The largest learned configuration the library accepts: N = 512 (a sparse
+    graph of mean degree 16, packed lists), K = 8 components (the network's
+    outputs, 16,376 floats, staged in LDS by the proposal and accept stages)
+    and, for the subset move, the largest subset m = 64; one round against the
+    oracle on the same draws."""
+    N, S, T, reps, H, K, z = 512, 1, 3, 2, 128, 8, 16
+    temps = synth.geometric_temps(0.6, 1.2, T)
+    graphs = [rlpt.Graph(N, SEED3 + 700, mean_degree=z)]
+    ctx = make_ctx(graphs, temps, n_temps=T, n_reps=reps, precision=rlpt.FP32, mlp_nets=2, mlp_hidden=H,
+                   mlp_components=K, mlp_capacity=64, mlp_batch=16, mlp_subset=m, resync_interval=0, drift_tol=0.0)
+    ctx.init(8)
+    ctx.mlp_setup([1, 2], seed=4)
+    NP, Out = ctx.mlp_sizes()
+    assert Out == K * (2 * (2 * N - 1) + 1)
+    raw = [synth.random_mlp_params(2 * N, H, Out, seed=190 + n, out_scale=0.05) for n in range(2)]
+    for n in range(2):
+        if m == 0:  # small output biases: over 1023 coordinates larger means would reject every move
+            raw[n][-Out:] *= 0.02
+        ctx.mlp_set_params(n, raw[n])
+    state = synth.random_constrained_state(N, 191, S * T * reps)
+    ctx.set_state(state)
+    s32 = state.astype(np.complex64).astype(np.complex128)
+    scale = 0.05 if m == 0 else 0.1
+    ctx.mlp_move(scale)
+    after = ctx.get_state().reshape(S * T * reps, N)
+    og = oracle.Graph(N, SEED3 + 700, mean_degree=z)
+    decided = 0
+    for n, t in enumerate([1, 2]):
+        params = M.rounded(unflatten(raw[n], N, H, K))
+        la, copies, prop = ctx.mlp_last_move(n)
+        for b in range(S * reps):
+            c = b * T + t
+            assert copies[b] == c
+            E0 = oracle.energy(og, s32[c])
+            if m == 0:
+                g, uc, ua = M.draws(8, 0, c, 2 * N - 1)
+                dH = lambda an: np.array([oracle.energy(og, x) for x in an]) - E0  # noqa
+                an, la_ref, parts = M.move_log_alpha(params, s32[c][None], dH, 1.0 / temps[t], N, K, scale, g[None],
+                                                     np.array([uc]))
+                an, la_ref = an[0], la_ref[0]
+                parts = {k: v[0] for k, v in parts.items()}
+            else:
+                Ss, g, uc, ua = M.subset_draws(8, 0, c, N, m)
+                dH = lambda an: oracle.energy(og, an) - E0  # noqa
+                an, la_ref, parts = M.subset_move_log_alpha(params, s32[c], Ss, dH, 1.0 / temps[t], N, K, scale, g,
+                                                            uc)
+                rest = np.setdiff1d(np.arange(N), Ss)
+                assert np.array_equal(prop[b][rest], s32[c][rest]), (n, b)
+            np.testing.assert_allclose(prop[b], an, rtol=0, atol=5e-4)
+            mag = abs(parts["lq_f"]) + abs(parts["lq_r"]) + abs(parts["dlogref"]) + abs(parts["dH"]) / temps[t]
+            assert la[b] == pytest.approx(la_ref, abs=5e-3 + 2e-5 * mag), (n, b)
+            if abs(math.log(ua) - la_ref) > 2e-2 + 4e-5 * mag:
+                accepted = math.log(ua) < la_ref
+                np.testing.assert_allclose(after[c], an if accepted else s32[c], rtol=0, atol=5e-4)
+                decided += 1
+    assert decided >= 2
+    acc, tries = ctx.mlp_stats()
+    assert np.all(tries == S * reps)
+
+
 @pytest.mark.parametrize("N,H,K,B,m", [(16, 48, 3, 16, 5), (64, 256, 4, 512, 8)])
 def test_subset_gradients_match_oracle(N, H, K, B, m):
     """Training loss and gradients of the subset move (each minibatch item in
