@@ -87,3 +87,54 @@ def test_window_means_are_per_sample_means_over_the_window():
             assert w["E_first"][i, mu] == pytest.approx(float(np.mean(e[10:25])))
             assert w["E_second"][i, mu] == pytest.approx(float(np.mean(e[25:40])))
             assert w["q2"][i, mu] == pytest.approx(float(np.mean(o["series_q"][mu, t, 10:40].astype(np.float64) ** 2)))
+
+
+def _csv(path, header, rows):
+    import csv
+    import os
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_fabric_traffic_is_the_counters_scaled_by_the_copy_calibration(tmp_path, monkeypatch):
+    """The roofline's traffic: FETCH_SIZE and WRITE_SIZE of the sweep kernel (KiB
+    per dispatch), each scaled by the bytes a 512 MiB device copy moves over
+    what the same counter reads for it; constructed rocprofv3 CSVs."""
+    import json
+    import os
+    root = tmp_path / "repo"
+    d = root / "gpurun_out" / "prof"
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(root / "profiles" / "traffic.json"))
+    monkeypatch.setattr(bench, "BATCHED_TRAFFIC_FILE", str(root / "profiles" / "batched.json"))
+    sweep = "void rlpt::(anonymous namespace)::k_sweep<float, 256, 2, 0, false>(x)"
+    probe = "void rlpt::(anonymous namespace)::k_stream_lists<256>(x)"
+    copy = "__amd_rocclr_copyBuffer"
+    _csv(str(d / "kt" / "kt_kernel_stats.csv"), ["Name", "Calls", "AverageNs", "MinNs", "MaxNs", "Percentage"],
+         [[sweep, 20, 2.5e6, 2.4e6, 2.6e6, 90.0], [probe, 10, 2.4e6, 2.3e6, 2.5e6, 9.0]])
+    cc = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    # the copy: FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them
+    _csv(str(d / "cal_FETCH_SIZE" / "cal_counter_collection.csv"), cc, [[copy, "FETCH_SIZE", 262144.0]])
+    _csv(str(d / "cal_WRITE_SIZE" / "cal_counter_collection.csv"), cc, [[copy, "WRITE_SIZE", 524288.0]])
+    _csv(str(d / "pmc_FETCH_SIZE" / "pmc_counter_collection.csv"), cc,
+         [[sweep, "FETCH_SIZE", 1000.0], [sweep, "FETCH_SIZE", 3000.0], [probe, "FETCH_SIZE", 1500.0]])
+    _csv(str(d / "pmc_WRITE_SIZE" / "pmc_counter_collection.csv"), cc,
+         [[sweep, "WRITE_SIZE", 10.0], [sweep, "WRITE_SIZE", 30.0], [probe, "WRITE_SIZE", 0.0]])
+    bench.summarize_profiles(str(d))
+    t = json.load(open(bench.TRAFFIC_FILE))
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    assert t["fetch_kib_per_dispatch"] == pytest.approx(2000.0) and t["dispatches"] == [2, 2]
+    assert t["hbm_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0 + 20.0 * 1024 * 1.0)
+    assert t["ceiling_hbm_bytes_per_launch"] == pytest.approx(1500.0 * 1024 * 2.0)
+    assert t["avg_duration_ns_kernel_trace"] == pytest.approx(2.5e6)
+    assert all(c.startswith("rocprofv3 --pmc ") and "gpurun_out/prof/" in c for c in t["commands"])
+    text = open(os.path.join(str(root), "profiles", "sweep_n256_kernel_stats.txt")).read()
+    assert "k_sweep<float, 256, 2, 0, false>" in text and "anonymous namespace" not in text
+    # the bench takes the committed traffic only while the kernel source is the one it was taken on
+    assert bench.traffic_for_current_kernel(1.0, bench.TRAFFIC_FILE) == pytest.approx(t["hbm_bytes_per_launch"])
+    t["kernel_source_sha"] = "0" * 16
+    json.dump(t, open(bench.TRAFFIC_FILE, "w"))
+    assert bench.traffic_for_current_kernel(1.0, bench.TRAFFIC_FILE) is None
