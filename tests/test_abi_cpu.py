@@ -216,3 +216,46 @@ def test_window_means_doubling():
     np.testing.assert_allclose(m, [0.0, 1.0, 2.5, 5.5, 11.5, 23.5, 47.5, 81.5])
     y = np.random.default_rng(2).standard_normal(777)
     np.testing.assert_allclose(rlpt.window_means(y)[0], analysis.window_means(y), rtol=1e-13)
+
+
+def _workspace(graphs, **kw):
+    import ctypes as C
+    cfg = rlpt.default_config(**kw)
+    arr = (C.c_void_p * len(graphs))(*[g._h.value for g in graphs])
+    n = C.c_size_t()
+    rlpt._check(rlpt.lib().rlpt_workspace_size(C.byref(cfg), arr, len(graphs), C.byref(n)))
+    return n.value
+
+
+def test_learned_move_workspace_and_configuration_checks_on_the_host():
+    """rlpt_workspace_size (host only) sizes the learned-proposal region and
+    rejects the configurations the learned kernels do not support."""
+    g = [rlpt.Graph(64, 11), rlpt.Graph(64, 12)]
+    base = dict(n_temps=4, n_reps=2)
+    plain = _workspace(g, **base)
+    learned = _workspace(g, mlp_nets=2, mlp_capacity=1000, mlp_batch=16, **base)
+    assert learned > plain
+    # the stored training pairs: nets x capacity x (before, after) x 2N floats, nothing else grows
+    more = _workspace(g, mlp_nets=2, mlp_capacity=2000, mlp_batch=16, **base)
+    assert more - learned == 2 * 1000 * 2 * 2 * 64 * 4
+    # the subset move's arrays are laid out for the largest subset whatever m is
+    assert _workspace(g, mlp_nets=2, mlp_capacity=1000, mlp_batch=16, mlp_subset=8, **base) == learned
+
+    def rejected(graphs, **kw):
+        with pytest.raises(rlpt.RlptError) as e:
+            _workspace(graphs, **{**base, "mlp_nets": 2, "mlp_capacity": 64, "mlp_batch": 16, **kw})
+        assert e.value.code == rlpt.RLPT_E_ARG
+        return str(e.value)
+
+    assert "n_temps" in rejected(g, mlp_nets=5)
+    assert "mlp_components" in rejected(g, mlp_components=9)
+    assert "mlp_hidden" in rejected(g, mlp_hidden=0)
+    assert "mlp_capacity" in rejected(g, mlp_capacity=8, mlp_batch=16)
+    assert "mlp_subset" in rejected(g, mlp_subset=1)
+    assert "mlp_subset" in rejected(g, mlp_subset=65)
+    assert "mlp_subset" in rejected([rlpt.Graph(16, 13)], mlp_subset=17)
+    assert "one N" in rejected([rlpt.Graph(64, 11), rlpt.Graph(48, 14)])
+    assert "N <= 512" in rejected([rlpt.Graph(520, 15, mean_degree=8)])
+    # the largest supported sizes pass
+    _workspace([rlpt.Graph(512, 16, mean_degree=8)], **dict(base, mlp_nets=2, mlp_capacity=64, mlp_batch=16,
+                                                             mlp_components=8, mlp_subset=64))
