@@ -259,3 +259,40 @@ def test_learned_move_workspace_and_configuration_checks_on_the_host():
     # the largest supported sizes pass
     _workspace([rlpt.Graph(512, 16, mean_degree=8)], **dict(base, mlp_nets=2, mlp_capacity=64, mlp_batch=16,
                                                              mlp_components=8, mlp_subset=64))
+
+
+def test_context_configuration_checks_and_list_layout_choice_on_the_host():
+    """rlpt_workspace_size validates a context's configuration and picks the
+    list layout: chunked (6.25 B per entry) for dense graphs with 32 <= N <= 256,
+    packed (8 B per entry) for small N and sparse graphs."""
+    g = [rlpt.Graph(64, 21)]
+    base = dict(n_temps=4, n_reps=2)
+
+    def code(graphs, **kw):
+        try:
+            _workspace(graphs, **{**base, **kw})
+        except rlpt.RlptError as e:
+            return e.code
+        return rlpt.RLPT_OK
+
+    for kw in (dict(n_temps=0), dict(n_reps=0), dict(precision=7), dict(swap_interval=0), dict(resync_interval=-1),
+               dict(measure_interval=-1), dict(n_bins=0), dict(series_len=-1), dict(block_threads=100),
+               dict(block_threads=2048), dict(copies_per_block=-1), dict(list_layout=9), dict(field_mode=9),
+               dict(rho=3), dict(mlp_nets=-1)):
+        assert code(g, **kw) == rlpt.RLPT_E_ARG, kw
+    assert code(g, rho=2, mlp_nets=1) == rlpt.RLPT_E_UNSUPPORTED
+    assert code([rlpt.Graph(260, 22, mean_degree=8)], list_layout=rlpt.LAYOUT_CHUNKED) == rlpt.RLPT_E_ARG
+    for kw in (dict(rho=2), dict(precision=rlpt.FP64), dict(block_threads=512, copies_per_block=2),
+               dict(field_mode=rlpt.FIELDS_CACHED)):
+        assert code(g, **kw) == rlpt.RLPT_OK, kw
+
+    def layouts(graphs):
+        return [_workspace(graphs, list_layout=lay, **base)
+                for lay in (rlpt.LAYOUT_AUTO, rlpt.LAYOUT_PACKED, rlpt.LAYOUT_CHUNKED)]
+
+    auto, packed, chunked = layouts(g)
+    assert auto == chunked and chunked < packed            # dense N = 64
+    auto, packed, chunked = layouts([rlpt.Graph(16, 23)])
+    assert auto == packed                                  # N < 32
+    auto, packed, chunked = layouts([rlpt.Graph(64, 24, mean_degree=8)])
+    assert auto == packed                                  # sparse: partner groups of about one entry
